@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the Cholesky-decomposed CCSD particle-particle ladder on one
+MI355X.
+
+One step = one pass of the whole hot path over one synthetic input: the T2
+ladder R = sum_cd tau (ac|bd) and the T1-dressed Lambda ladder
+Z = sum_ef lambda W_efab, each with the symmetric-antisymmetric split, the
+(ac|bd) batches assembled on the fly, the FP64 epilogue (R/D and pair
+energies), on the 8-irrep workload o=20 (4,2,3,2,3,2,2,2), v=200
+(40,22,30,20,32,18,22,16), 1500 Cholesky vectors in the totally symmetric
+irrep.  Inputs are resident in HBM before the timed region.
+
+value = algorithmic TFLOP/s (symmetry-blocked, stored-halves flop count of
+both ladders) of the fastest path that passes its accuracy gate.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CD ladder residual TFLOP/s, FP64 vs split-precision at 1e-7; p50/p99 latency"
+PEAK = {"fp64": 78.6, "bf16": 2500.0}  # MI355X dense MFMA, TFLOP/s
+HBM_PEAK = 8000.0  # GB/s
+
+
+def workload(name):
+    import synth as S
+    if name == "d2h_medium":
+        return S.sym_d2h_medium("A"), "d2h_medium: 8 irreps, o=20, v=200, Ncd=1500 (all in the totally symmetric irrep)"
+    if name == "c1_small":
+        return S.sym_c1_small(), "c1_small: 1 irrep, o=8, v=40, Ncd=300"
+    if name == "d2h_large":
+        return S.sym_d2h_large(), "d2h_large: 8 irreps, o=40, v=400, Ncd=3000 (even split)"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def build_inputs(cdcc, sym, seed=0):
+    import synth as S
+    from tests.gpu_support import device_problem
+    pt = S.make_problem(sym, seed=seed, kind="t2")
+    pl = S.make_problem(sym, seed=seed, kind="lambda")
+    dt = device_problem(cdcc, pt, want_delta=True, want_energy=True, nan_fill=False)
+    dl = device_problem(cdcc, pl, want_delta=True, want_energy=True, nan_fill=False)
+    return pt, pl, dt, dl
+
+
+def step(cdcc, dt, dl, precision):
+    cdcc.ladder_t2(dt, precision=precision)
+    cdcc.ladder_lambda(dl, precision=precision)
+
+
+def accuracy(cdcc, pt, pl, dt, dl, precision):
+    """Normwise errors of both ladders against the FP64 oracle, and the
+    pair-energy error (Eh)."""
+    import torch
+    import oracle as O
+    from oracle.layout import OracleLayout
+    step(cdcc, dt, dl, precision)
+    torch.cuda.synchronize()
+    out = {}
+    for tag, p, d in (("t2", pt, dt), ("lambda", pl, dl)):
+        if p["kind"] == "t2":
+            ref = O.t2_ladder_blocks(p["sym"], p["B"], p["X"])
+        else:
+            ref = O.lambda_ladder_blocks(p["sym"], p["B"], p["Bvo"], p["t1"], p["X"])
+        lay = d["layout"]
+        got = lay.unpack_amp(d["R"].cpu().numpy())
+        mx, fro = O.rel_errors(got, ref)
+        ol = OracleLayout(p["sym"])
+        e_ref = O.pair_energies_full(ol.full_amp(p["X"]), ol.full_amp(ref))
+        e_got = d["pair_energy"].cpu().numpy().reshape(e_ref.shape)
+        out[tag] = {"max_rel": mx, "fro_rel": fro, "pair_energy_abs": float(np.max(np.abs(e_got - e_ref)))}
+    return out
+
+
+def timed(cdcc, dt, dl, precision, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step(cdcc, dt, dl, precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(cdcc, dt, dl, precision)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_times(cdcc, dt, dl, precision, steps):
+    """Per-class kernel durations from HIP events on the library's stream."""
+    import torch
+    torch.cuda.synchronize()
+    cdcc.timing_read()
+    cdcc.timing_enable(True)
+    for _ in range(steps):
+        step(cdcc, dt, dl, precision)
+    torch.cuda.synchronize()
+    cdcc.timing_enable(False)
+    return cdcc.timing_read()
+
+
+def cpu_baseline(pt, pl, flops_step, budget_s=12.0):
+    """The FP64 oracle (NumPy + host BLAS) on the same workload, repeated for
+    a bounded time on the host cores."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count())
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        O.t2_ladder_blocks(pt["sym"], pt["B"], pt["X"])
+        O.lambda_ladder_blocks(pl["sym"], pl["B"], pl["Bvo"], pl["t1"], pl["X"])
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s or reps >= 50:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": flops_step * reps / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{reps} full steps (T2 + dressed Lambda ladder, symmetry-blocked plain FP64 contraction) "
+                      f"in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="d2h_medium")
+    ap.add_argument("--precision", default="all", choices=["all", "fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle accuracy gate")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the ladder library runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2512_21909_amd as cdcc
+    cdcc.require_gpu()
+    sym, wdesc = workload(args.workload)
+    pt, pl, dt, dl = build_inputs(cdcc, sym)
+    lay = dt["layout"]
+    f_t2 = lay.flops(0)
+    f_l = lay.flops(2)
+    flops_step = sum(f_t2) + sum(f_l)
+    flops_assemble = f_t2[0] + f_l[0]
+    print(f"[bench] {wdesc}; F_alg per step {flops_step:.4e} (assembly {flops_assemble:.4e})", file=sys.stderr,
+          flush=True)
+
+    paths = ["fp64", "mixed"] if args.precision == "all" else [args.precision]
+    results = {}
+    for prec in paths:
+        try:
+            acc = None if args.no_check else accuracy(cdcc, pt, pl, dt, dl, prec)
+        except cdcc.CdccError as e:
+            print(f"[bench] {prec}: unavailable ({e})", file=sys.stderr, flush=True)
+            continue
+        sec = timed(cdcc, dt, dl, prec, args.steps, args.warmup)
+        kt = kernel_times(cdcc, dt, dl, prec, args.steps)
+        gate = 1e-12 if prec == "fp64" else 1e-7
+        ok = acc is None or all(a["max_rel"] <= gate and a["fro_rel"] <= gate and
+                                (prec == "fp64" or a["pair_energy_abs"] <= 1e-8) for a in acc.values())
+        results[prec] = {"ms_per_step": sec * 1e3, "tflops": flops_step / sec / 1e12, "accuracy": acc,
+                         "passes_gate": ok, "kernels": kt}
+        print(f"[bench] {prec}: {sec * 1e3:.3f} ms/step, {flops_step / sec / 1e12:.2f} TFLOP/s, gate ok={ok}, "
+              f"kernels={kt}", file=sys.stderr, flush=True)
+
+    good = [p for p in results if results[p]["passes_gate"]]
+    if not good:
+        print("[bench] no path passed its accuracy gate", file=sys.stderr)
+        sys.exit(1)
+    best = max(good, key=lambda p: results[p]["tflops"])
+    r = results[best]
+    asm_ms, asm_n = r["kernels"].get("assemble", (0.0, 0))
+    per_launch_flops = flops_assemble * args.steps / max(asm_n, 1)
+    avg_ms = asm_ms / max(asm_n, 1)
+    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    peak = PEAK["fp64"] if best == "fp64" else PEAK["bf16"]
+    line = {
+        "metric": METRIC,
+        "value": round(r["tflops"], 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if best == "fp64" else "bf16x4-split/f32-acc/f64-sum",
+        "data": "synthetic",
+        "config": {"workload": wdesc, "step": "T2 ladder + T1-dressed Lambda ladder, R/D and pair energies",
+                   "flops_per_step": flops_step, "path": best},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "assemble (ac|bd) batch", "launches": asm_n, "avg_launch_ms": avg_ms,
+                     "flops_per_launch": per_launch_flops},
+        "paths": {p: {k: v for k, v in results[p].items() if k != "kernels"} | {"kernels_ms": results[p]["kernels"]}
+                  for p in results},
+    }
+    if "fp64" in results and "mixed" in results:
+        line["mixed_speedup_vs_fp64"] = results["mixed"]["tflops"] / results["fp64"]["tflops"]
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pt, pl, flops_step)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * cdcc.h -- C ABI of the MI355X (gfx950) particle-particle ladder library for
+ * closed-shell CCSD with Cholesky-decomposed two-electron integrals and
+ * Abelian point-group symmetry (arXiv 2512.21909).
+ *
+ * Operations (paper section "Stationarity with respect to cluster amplitudes:
+ * Lambda equations", the PPL equations, plus Appendix A):
+ *
+ *   T2 ladder      R_ij^ab = sum_cd tau_ij^cd (ac|bd),
+ *                  (ac|bd) = sum_P B^P_ac B^P_bd          (CD of eq. 1)
+ *   Lambda ladder  Z_ij^ab = sum_ef lambda_ij^ef W_efab,
+ *                  W_efab  = sum_P [(B^P_ea - t^P_ea) B^P_fb - B^P_ea t^P_fb],
+ *                  t^P_xy  = sum_m t_m^x L^P_ym           (Appendix A)
+ *
+ * both evaluated with the symmetric-antisymmetric split (S + A, stored halves
+ * a>=b, i>=j, c>=d) and blocked by irreducible representation (direct-product
+ * decomposition, symmetry section).  (ac|bd) is assembled on the fly in
+ * bounded batches; the v^4 tensor never exists.
+ *
+ * Symmetry: h in {1,2,4,8} irreps labelled 0..h-1; the product of two irreps
+ * is their bitwise XOR (D2h and its subgroups in the standard ordering).
+ * Orbitals and Cholesky vectors are sorted by irrep, then by local index.
+ *
+ * Memory: every tensor pointer in cdcc_problem_t is a caller-owned DEVICE
+ * pointer to FP64 data in the layout described by cdcc_layout_t (all counts
+ * and offsets in elements, not bytes).  The library never frees or keeps a
+ * caller pointer after the call's work has completed on the stream.  It owns
+ * an internal workspace cache (device memory, per stream) and a plan cache,
+ * both released by cdcc_release() or at process exit.
+ *
+ * Errors: functions return CDCC_OK (0) or a negative status; nothing else
+ * crosses the ABI.  Ladder calls are asynchronous on the given stream; an
+ * error in argument checking is reported before anything is enqueued.
+ */
+#ifndef CDCC_H
+#define CDCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDCC_MAX_IRREP 8
+
+#define CDCC_OK            0
+#define CDCC_EINVAL       -1  /* bad layout, pointer, size or option            */
+#define CDCC_ENOMEM       -2  /* device workspace could not be allocated        */
+#define CDCC_EUNSUPPORTED -3  /* e.g. irrep count not in {1,2,4,8}              */
+#define CDCC_EDEVICE      -4  /* HIP runtime error, or no gfx950 device         */
+
+#define CDCC_FP64  0  /* FP64 MFMA throughout                                     */
+#define CDCC_MIXED 1  /* split-BF16 MFMA, FP32 accumulation, FP64 combination     */
+
+/* Orbital and Cholesky-vector counts per irrep (entries >= nirrep ignored). */
+typedef struct {
+  int32_t nirrep;
+  int32_t nocc[CDCC_MAX_IRREP];
+  int32_t nvir[CDCC_MAX_IRREP];
+  int32_t ncd[CDCC_MAX_IRREP];
+} cdcc_sym_t;
+
+/*
+ * Flat storage of every tensor, filled by cdcc_irrep_layout.
+ *
+ * Amplitudes (tau, lambda, R, Z, delta): one block per pair irrep G, at
+ *   amp_off[G], row-major n_oo[G] x n_vv[G].  Row of (i,j), Gi^Gj = G:
+ *   oo_off[G][Gi] + i*nocc[Gj] + j.  Column of (a,b), Ga^Gb = G:
+ *   vv_off[G][Ga] + a*nvir[Gb] + b   (i, j, a, b local to their irrep).
+ * Cholesky vectors of the vv block, B^P_ac with Ga^Gc = GP: block at
+ *   b_off[GP][Ga], dense [a][c][P] (P fastest), nvir[Ga] x nvir[Gc] x ncd[GP].
+ * Cholesky vectors of the vo block, L^P_am with Ga^Gm = GP: block at
+ *   bvo_off[GP][Ga], dense [a][m][P].
+ * Singles t_m^e (Gm == Ge): block at t1_off[G], dense [m][e].
+ * Orbital energies: eps_occ[occ_off[G] + i], eps_vir[vir_off[G] + a].
+ * Pair energies: dense nocc_tot x nocc_tot matrix, [I][J] with global
+ *   occupied indices I = occ_off[Gi] + i.
+ * n_oo_pk / n_vv_pk: number of pairs with i>=j / a>=b (orbital order above)
+ *   in pair irrep G, i.e. the stored halves of the symmetric-antisymmetric
+ *   algorithm.
+ */
+typedef struct {
+  cdcc_sym_t sym;
+  int64_t n_oo[CDCC_MAX_IRREP], n_vv[CDCC_MAX_IRREP];
+  int64_t n_oo_pk[CDCC_MAX_IRREP], n_vv_pk[CDCC_MAX_IRREP];
+  int64_t amp_off[CDCC_MAX_IRREP];
+  int64_t oo_off[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
+  int64_t vv_off[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
+  int64_t b_off[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
+  int64_t bvo_off[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
+  int64_t t1_off[CDCC_MAX_IRREP];
+  int64_t occ_off[CDCC_MAX_IRREP], vir_off[CDCC_MAX_IRREP], cd_off[CDCC_MAX_IRREP];
+  int64_t amp_size, b_size, bvo_size, t1_size;
+  int64_t nocc_tot, nvir_tot, ncd_tot;
+} cdcc_layout_t;
+
+/*
+ * One ladder evaluation.  Required: lay, B, X, R.  X is tau (T2) or lambda
+ * (Lambda) and must be pair-symmetric, X_ij^ab = X_ji^ba; only its rows with
+ * i >= j are read.  R receives the full result (every stored element is
+ * written).  Optional outputs (NULL = skip): delta = R / D with
+ * D_ij^ab = eps_i + eps_j - eps_a - eps_b (needs eps_occ, eps_vir), and
+ * pair_energy e_IJ = sum_ab (2 X_ij^ab - X_ij^ba) R_ij^ab.  Lambda only:
+ * Bvo and t1 enable the T1 dressing of Appendix A; both NULL gives the
+ * undressed W_efab = (ea|fb).  Input buffers must not overlap R/delta.
+ */
+typedef struct {
+  const cdcc_layout_t *lay;  /* host pointer, read during the call only        */
+  const double *B;           /* device, lay->b_size                             */
+  const double *X;           /* device, lay->amp_size                           */
+  double *R;                 /* device out, lay->amp_size                       */
+  const double *Bvo;         /* device, lay->bvo_size, or NULL                  */
+  const double *t1;          /* device, lay->t1_size, or NULL                   */
+  const double *eps_occ;     /* device, lay->nocc_tot, or NULL                  */
+  const double *eps_vir;     /* device, lay->nvir_tot, or NULL                  */
+  double *delta;             /* device out, lay->amp_size, or NULL              */
+  double *pair_energy;       /* device out, nocc_tot*nocc_tot, or NULL          */
+} cdcc_problem_t;
+
+typedef struct {
+  int32_t precision;         /* CDCC_FP64 or CDCC_MIXED                         */
+  int32_t tile_policy;       /* 0 = autotuned table, 1..3 = force a tile class  */
+  int64_t batch_bytes;       /* cap of the (ac|bd) batch buffer, 0 = default    */
+} cdcc_opts_t;
+
+/*
+ * Fill *out with the offsets above.  Host only, no device access.  Returns
+ * CDCC_EUNSUPPORTED unless nirrep is 1, 2, 4 or 8, CDCC_EINVAL for a NULL
+ * pointer or a negative count.
+ */
+int cdcc_irrep_layout(const cdcc_sym_t *sym, cdcc_layout_t *out);
+
+/*
+ * T2 ladder R_ij^ab = sum_cd tau_ij^cd sum_P B^P_ac B^P_bd for nsys >= 1
+ * independent systems (each with its own layout) in one batched, persistent
+ * launch sequence on `stream` (a hipStream_t, NULL = default stream).
+ * opts may be NULL (FP64, default batch size).  Returns CDCC_EINVAL for
+ * nsys < 1, NULL probs, a NULL required pointer, or eps missing while delta
+ * is requested; CDCC_ENOMEM if the workspace cannot be allocated;
+ * CDCC_EDEVICE on a HIP error.
+ */
+int cdcc_ladder_t2(int32_t nsys, const cdcc_problem_t *probs,
+                   const cdcc_opts_t *opts, void *stream);
+
+/*
+ * Lambda ladder Z_ij^ab = sum_ef lambda_ij^ef W_efab with the Appendix-A
+ * W_efab (X = lambda, R = Z).  Same conventions and errors as cdcc_ladder_t2;
+ * Bvo and t1 must be both set or both NULL.
+ */
+int cdcc_ladder_lambda(int32_t nsys, const cdcc_problem_t *probs,
+                       const cdcc_opts_t *opts, void *stream);
+
+/*
+ * Algorithmic flop count of one evaluation (host only): flops[0] = (ac|bd)
+ * assembly, flops[1] = contraction, flops[2] = T1 dressing (Lambda with t1).
+ * kind: 0 = T2, 1 = Lambda, 2 = Lambda with dressing.  Counts the stored
+ * halves (a>=b for the assembly; i>=j, a>=b, c>=d for the contraction) and
+ * only symmetry-allowed blocks, with 2 flops per multiply-add.
+ */
+int cdcc_ladder_flops(const cdcc_layout_t *lay, int32_t kind, double flops[3]);
+
+/*
+ * Device bytes the library allocates for a call with these problems and
+ * options (workspace only; excludes the caller's buffers).  Host only.
+ */
+int cdcc_workspace_bytes(int32_t nsys, const cdcc_problem_t *probs,
+                         const cdcc_opts_t *opts, int32_t lambda, int64_t *bytes);
+
+/*
+ * Kernel timing (instrumentation for benchmarks).  While enabled, every ladder
+ * call records a HIP event pair on its own stream around each kernel class:
+ * 0 = T1 dressing, 1 = amplitude packing, 2 = (ac|bd) batch assembly,
+ * 3 = contraction + unpack, 4 = pair energies, 5 = operand slicing (mixed).
+ * cdcc_timing_read waits for the recorded events, returns the summed elapsed
+ * milliseconds and launch counts per class (arrays of 8) and clears the record.
+ */
+int cdcc_timing_enable(int32_t on);
+int cdcc_timing_read(double ms[8], int64_t launches[8]);
+
+/* Static, human-readable text for a status code. */
+const char *cdcc_status_string(int status);
+
+/* Free the workspace and plan caches of every device (waits for the device). */
+int cdcc_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDCC_H */

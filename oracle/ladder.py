@@ -80,8 +80,10 @@ def t2_ladder_blocks(sym: dict, B: dict, tau: dict) -> dict:
                 if nc[gP] == 0:
                     continue
                 gc, gd = ga ^ gP, gb ^ gP
-                # (ac|bd) for this block: (v_a, v_c, v_b, v_d)
-                Wb = np.einsum("acP,bdP->acbd", B[(gP, ga)], B[(gP, gb)])
+                # (ac|bd) for this block: (v_a, v_c, v_b, v_d), a matmul over P
+                Ba, Bb = B[(gP, ga)], B[(gP, gb)]
+                Wb = (Ba.reshape(-1, nc[gP]) @ Bb.reshape(-1, nc[gP]).T).reshape(
+                    nv[ga], nv[gc], nv[gb], nv[gd])
                 Wm = Wb.transpose(1, 3, 0, 2).reshape(nv[gc] * nv[gd], nv[ga] * nv[gb])
                 for gi in range(h):
                     gj = gi ^ G
@@ -165,8 +167,11 @@ def lambda_ladder_blocks(sym: dict, B: dict, Bvo: dict, t1: list, lam: dict) -> 
                 ge, gf = ga ^ gP, gb ^ gP
                 Bea = B[(gP, ge)]          # (e, a, P)
                 Bfb = B[(gP, gf)]          # (f, b, P)
-                Wb = (np.einsum("eaP,fbP->efab", Bea - tP(gP, ge), Bfb)
-                      - np.einsum("eaP,fbP->efab", Bea, tP(gP, gf)))
+                n = nc[gP]
+                # W_efab = sum_P (B_ea - t_ea) B_fb - B_ea t_fb, each term a matmul over P
+                m1 = (Bea - tP(gP, ge)).reshape(-1, n) @ Bfb.reshape(-1, n).T      # (ea, fb)
+                m2 = Bea.reshape(-1, n) @ tP(gP, gf).reshape(-1, n).T              # (ea, fb)
+                Wb = (m1 - m2).reshape(nv[ge], nv[ga], nv[gf], nv[gb]).transpose(0, 2, 1, 3)
                 Wm = Wb.reshape(nv[ge] * nv[gf], nv[ga] * nv[gb])
                 for gi in range(h):
                     gj = gi ^ G

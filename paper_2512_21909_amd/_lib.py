@@ -1,0 +1,97 @@
+"""ctypes view of include/cdcc.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcdcc.so")
+
+MAX_IRREP = 8
+OK, EINVAL, ENOMEM, EUNSUPPORTED, EDEVICE = 0, -1, -2, -3, -4
+FP64, MIXED = 0, 1
+
+_i32, _i64 = ctypes.c_int32, ctypes.c_int64
+_A8 = _i32 * MAX_IRREP
+_L8 = _i64 * MAX_IRREP
+_L88 = (_i64 * MAX_IRREP) * MAX_IRREP
+
+
+class Sym(ctypes.Structure):
+    _fields_ = [("nirrep", _i32), ("nocc", _A8), ("nvir", _A8), ("ncd", _A8)]
+
+
+class LayoutC(ctypes.Structure):
+    _fields_ = [
+        ("sym", Sym),
+        ("n_oo", _L8), ("n_vv", _L8), ("n_oo_pk", _L8), ("n_vv_pk", _L8),
+        ("amp_off", _L8), ("oo_off", _L88), ("vv_off", _L88),
+        ("b_off", _L88), ("bvo_off", _L88),
+        ("t1_off", _L8), ("occ_off", _L8), ("vir_off", _L8), ("cd_off", _L8),
+        ("amp_size", _i64), ("b_size", _i64), ("bvo_size", _i64), ("t1_size", _i64),
+        ("nocc_tot", _i64), ("nvir_tot", _i64), ("ncd_tot", _i64),
+    ]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("lay", ctypes.POINTER(LayoutC)),
+        ("B", ctypes.c_void_p), ("X", ctypes.c_void_p), ("R", ctypes.c_void_p),
+        ("Bvo", ctypes.c_void_p), ("t1", ctypes.c_void_p),
+        ("eps_occ", ctypes.c_void_p), ("eps_vir", ctypes.c_void_p),
+        ("delta", ctypes.c_void_p), ("pair_energy", ctypes.c_void_p),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", _i32), ("tile_policy", _i32), ("batch_bytes", _i64)]
+
+
+EXPORTS = ["cdcc_irrep_layout", "cdcc_ladder_t2", "cdcc_ladder_lambda", "cdcc_ladder_flops",
+           "cdcc_workspace_bytes", "cdcc_timing_enable", "cdcc_timing_read", "cdcc_status_string",
+           "cdcc_release"]
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2512_21909_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.cdcc_irrep_layout.argtypes = [ctypes.POINTER(Sym), ctypes.POINTER(LayoutC)]
+    lib.cdcc_irrep_layout.restype = ctypes.c_int
+    for name in ("cdcc_ladder_t2", "cdcc_ladder_lambda"):
+        f = getattr(lib, name)
+        f.argtypes = [_i32, ctypes.POINTER(Problem), ctypes.POINTER(Opts), ctypes.c_void_p]
+        f.restype = ctypes.c_int
+    lib.cdcc_ladder_flops.argtypes = [ctypes.POINTER(LayoutC), _i32, ctypes.POINTER(ctypes.c_double)]
+    lib.cdcc_ladder_flops.restype = ctypes.c_int
+    lib.cdcc_workspace_bytes.argtypes = [_i32, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _i32,
+                                         ctypes.POINTER(_i64)]
+    lib.cdcc_workspace_bytes.restype = ctypes.c_int
+    lib.cdcc_status_string.argtypes = [ctypes.c_int]
+    lib.cdcc_status_string.restype = ctypes.c_char_p
+    lib.cdcc_timing_enable.argtypes = [_i32]
+    lib.cdcc_timing_enable.restype = ctypes.c_int
+    lib.cdcc_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    lib.cdcc_timing_read.restype = ctypes.c_int
+    lib.cdcc_release.argtypes = []
+    lib.cdcc_release.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class CdccError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load().cdcc_status_string(status).decode()
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != OK:
+        raise CdccError(status, where)

@@ -1,0 +1,871 @@
+// C-ABI entry points, planner and workspace management of the ladder library.
+//
+// A plan is built once per (kind, precision, options, list of symmetry
+// shapes) and cached per device.  It holds every device table the kernels
+// need (pair maps, K tables, column groups, tile lists) and the launch
+// sequence: the (ac|bd) assembly is split into column groups, and groups are
+// packed into batches whose intermediate buffer stays under a byte cap, so the
+// v^4 tensor is never formed.  Per call only the per-system pointer table is
+// uploaded (from pinned host memory, guarded by an event) and the launches are
+// enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cdcc.h"
+#include "ladder_types.hpp"
+
+namespace cdcc {
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s);
+hipError_t launch_pack(const PackJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, const int4 *ijtab,
+                       const int4 *vvtab, hipStream_t s);
+hipError_t launch_dress(const DressJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s);
+hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Tile *tiles, int ntiles, int *counter,
+                               const SysPtrs *sp, double *xbuf, hipStream_t s);
+hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, int ntiles, int *counter,
+                               const SysPtrs *sp, const double *xbuf, const int4 *ktab, const int4 *ijtab,
+                               const int4 *vvtab, hipStream_t s);
+hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s);
+// mixed path (kernels_mixed.hip)
+hipError_t launch_slice_rows(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s);
+hipError_t launch_colnorm(const P1Desc *descs, int ndesc, const SysPtrs *sp, hipStream_t s);
+hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, int ntiles, int *counter,
+                                 const SysPtrs *sp, double *xbuf, hipStream_t s);
+hipError_t launch_contract_mixed(int cls, int grid, const P2Group *groups, const Tile *tiles, int ntiles,
+                                 int *counter, const SysPtrs *sp, const double *xbuf, const int4 *ktab,
+                                 const int4 *ijtab, const int4 *vvtab, const double *colbound, hipStream_t s);
+}  // namespace cdcc
+
+using namespace cdcc;
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// P1 (assembly) tile classes and P2 (contraction) tile classes.
+constexpr int kP1BM[3] = {64, 128, 128};
+constexpr int kP1BN[3] = {64, 64, 128};
+constexpr int kP2BM[2] = {64, 128};
+constexpr int kP2BN[2] = {64, 64};
+
+struct Launch {
+  int cls = 0, start = 0, count = 0, grid = 0;
+};
+struct BatchPlan {
+  std::vector<Launch> p1, p2;
+  std::vector<std::pair<int, int>> p1_desc_range;  // mixed path: descs whose column bounds to compute
+};
+
+struct SysPlan {
+  cdcc_layout_t lay{};
+  int64_t th_elems = 0;      // packed +/- amplitudes
+  int64_t u_elems = 0;       // Lambda operand stack
+  int64_t op_rows = 0;       // rows of the assembly operand (mixed path slices)
+  int64_t op_elems = 0;      // elements of the assembly operand
+  int p1cls = 0;
+};
+
+struct Plan {
+  int nsys = 0;
+  int lambda = 0, dressed = 0, precision = 0;
+  std::vector<SysPlan> sys;
+  // device tables (single allocation)
+  void *dtab = nullptr;
+  PackJob *packjobs = nullptr;
+  int2 *packrows = nullptr;
+  int npackrows = 0;
+  DressJob *dressjobs = nullptr;
+  int2 *dressrows = nullptr;
+  int ndressrows = 0;
+  P1Desc *p1 = nullptr;
+  int np1 = 0;
+  Tile *p1tiles = nullptr;
+  P2Group *p2 = nullptr;
+  Tile *p2tiles = nullptr;
+  int4 *ktab = nullptr, *ijtab = nullptr, *vvtab = nullptr;
+  int *vvfull = nullptr;
+  EnergyJob *ejobs = nullptr;
+  int nejobs = 0;
+  SliceJob *slicejobs = nullptr;
+  int2 *slicerows = nullptr;
+  int nslicerows = 0;
+  std::vector<BatchPlan> batches;
+  int ncounters = 0;
+  int64_t xbuf_elems = 0;
+  int64_t colbound_elems = 0;
+  ~Plan() {
+    if (dtab) (void)hipFree(dtab);
+  }
+};
+
+struct Workspace {
+  void *dev = nullptr;
+  int64_t bytes = 0;
+  void *staging = nullptr;  // pinned host
+  int64_t staging_bytes = 0;
+  hipEvent_t ev = nullptr;
+  bool ev_recorded = false;
+  ~Workspace() {
+    if (ev) {
+      (void)hipEventSynchronize(ev);
+      (void)hipEventDestroy(ev);
+    }
+    if (dev) (void)hipFree(dev);
+    if (staging) (void)hipHostFree(staging);
+  }
+};
+
+std::mutex g_mu;
+
+// Optional event timing of kernel classes (see cdcc_timing_enable).
+struct TimedSpan {
+  int cls;
+  int launches;
+  hipEvent_t a, b;
+};
+bool g_timing = false;
+std::vector<TimedSpan> g_spans;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// RAII bracket around the launches of one kernel class.
+struct Span {
+  int cls, n;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Span(int c, int launches, hipStream_t st) : cls(c), n(launches), s(st) {
+    if (g_timing && n > 0) {
+      a = take_event();
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~Span() {
+    if (!a) return;
+    hipEvent_t b = take_event();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    g_spans.push_back({cls, n, a, b});
+  }
+};
+std::map<std::string, std::shared_ptr<Plan>> g_plans;                 // key includes device
+std::map<std::pair<int, void *>, std::unique_ptr<Workspace>> g_ws;  // (device, stream)
+
+int64_t env_i64(const char *name, int64_t dflt) {
+  const char *v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::strtoll(v, nullptr, 10);
+}
+
+struct TableBuilder {
+  std::vector<char> bytes;
+  template <class T>
+  int64_t add(const std::vector<T> &v) {
+    const int64_t off = align_up(int64_t(bytes.size()));
+    bytes.resize(off + int64_t(v.size() * sizeof(T)) + 1);
+    if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+bool valid_sym(const cdcc_sym_t &s) {
+  if (!(s.nirrep == 1 || s.nirrep == 2 || s.nirrep == 4 || s.nirrep == 8)) return false;
+  for (int g = 0; g < s.nirrep; ++g)
+    if (s.nocc[g] < 0 || s.nvir[g] < 0 || s.ncd[g] < 0) return false;
+  return true;
+}
+
+std::string plan_key(int dev, int nsys, const cdcc_problem_t *p, int lambda, int dressed, const cdcc_opts_t &o,
+                     int64_t cap) {
+  std::string k;
+  k.reserve(64 + nsys * 100);
+  auto put = [&](int64_t x) {
+    k += std::to_string(x);
+    k += ',';
+  };
+  put(dev);
+  put(lambda);
+  put(dressed);
+  put(o.precision);
+  put(o.tile_policy);
+  put(cap);
+  put(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_sym_t &y = p[s].lay->sym;
+    put(y.nirrep);
+    for (int g = 0; g < y.nirrep; ++g) {
+      put(y.nocc[g]);
+      put(y.nvir[g]);
+      put(y.ncd[g]);
+    }
+    k += '|';
+  }
+  return k;
+}
+
+int choose_p1_class(const cdcc_layout_t &L, int policy) {
+  if (policy >= 1 && policy <= 3) return policy - 1;
+  // Tile-table heuristic: the largest tile that still gives >= 2 tiles per CU.
+  const int h = L.sym.nirrep;
+  const int32_t *nv = L.sym.nvir, *nc = L.sym.ncd;
+  double tiles[3] = {0, 0, 0};
+  for (int ga = 0; ga < h; ++ga)
+    for (int gb = 0; gb <= ga; ++gb)
+      for (int gc = 0; gc < h; ++gc) {
+        const int gP = ga ^ gc, gd = gb ^ gP;
+        if (nc[gP] == 0) continue;
+        const double M = double(nv[ga]) * nv[gc], N = double(nv[gb]) * nv[gd] * (ga == gb ? 0.5 : 1.0);
+        for (int c = 0; c < 3; ++c) tiles[c] += std::ceil(M / kP1BM[c]) * std::ceil(N / kP1BN[c]);
+      }
+  if (tiles[2] >= 1024) return 2;
+  if (tiles[1] >= 768) return 1;
+  return 0;
+}
+
+// Packed i>=j (or a>=b) list of pair irrep G: (x_global_row_xy, row_yx, X, Y)
+void pair_table(const int32_t *n, int h, int G, const int64_t off[CDCC_MAX_IRREP], const int64_t goff[CDCC_MAX_IRREP],
+                std::vector<int4> &out, int64_t sb_start[CDCC_MAX_IRREP]) {
+  const int64_t first = int64_t(out.size());
+  for (int g1 = 0; g1 < h; ++g1) {
+    const int g2 = g1 ^ G;
+    sb_start[g1] = int64_t(out.size()) - first;  // relative to this pair irrep's list
+    if (g1 < g2) continue;
+    for (int x = 0; x < n[g1]; ++x)
+      for (int y = 0; y < (g1 == g2 ? x + 1 : n[g2]); ++y) {
+        int4 e;
+        e.x = int(off[g1] + int64_t(x) * n[g2] + y);
+        e.y = int(off[g2] + int64_t(y) * n[g1] + x);
+        e.z = int(goff[g1] + x);
+        e.w = int(goff[g2] + y);
+        out.push_back(e);
+      }
+  }
+}
+
+int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, const cdcc_opts_t &opts, int64_t cap,
+               Plan &P) {
+  P.nsys = nsys;
+  P.lambda = lambda;
+  P.dressed = dressed;
+  P.precision = opts.precision;
+  P.sys.resize(nsys);
+  std::vector<PackJob> packjobs;
+  std::vector<int2> packrows;
+  std::vector<DressJob> dressjobs;
+  std::vector<int2> dressrows;
+  std::vector<int4> ktab, ijtab, vvtab;
+  std::vector<int> vvfull;
+  std::vector<EnergyJob> ejobs;
+  std::vector<SliceJob> slicejobs;
+  std::vector<int2> slicerows;
+
+  struct GroupRec {
+    P2Group g;
+    std::vector<P1Desc> descs;
+    int64_t region = 0;
+    int sys = 0, p2cls = 0;
+  };
+  std::vector<GroupRec> groups;
+  const int64_t cap_elems = std::max<int64_t>(cap / 8, 1);
+
+  for (int s = 0; s < nsys; ++s) {
+    SysPlan &SP = P.sys[s];
+    SP.lay = *probs[s].lay;
+    const cdcc_layout_t &L = SP.lay;
+    const int h = L.sym.nirrep;
+    const int32_t *no = L.sym.nocc, *nv = L.sym.nvir, *nc = L.sym.ncd;
+    const int kmul = (lambda && dressed) ? 2 : 1;
+    SP.p1cls = choose_p1_class(L, opts.tile_policy);
+    SP.op_elems = kmul * L.b_size;
+    int64_t rows = 0;
+    for (int gP = 0; gP < h; ++gP)
+      for (int ga = 0; ga < h; ++ga) rows += int64_t(nv[ga]) * nv[ga ^ gP] * (nc[gP] > 0 ? 1 : 0);
+    SP.op_rows = rows;
+    if (lambda) SP.u_elems = kmul * L.b_size;
+
+    int ij_off[CDCC_MAX_IRREP], vv_off[CDCC_MAX_IRREP], vvf_off[CDCC_MAX_IRREP];
+    int64_t vv_sb[CDCC_MAX_IRREP][CDCC_MAX_IRREP], oo_sb[CDCC_MAX_IRREP];
+    int64_t th_off[CDCC_MAX_IRREP];
+    for (int G = 0; G < h; ++G) {
+      ij_off[G] = int(ijtab.size());
+      pair_table(no, h, G, L.oo_off[G], L.occ_off, ijtab, oo_sb);
+      vv_off[G] = int(vvtab.size());
+      pair_table(nv, h, G, L.vv_off[G], L.vir_off, vvtab, vv_sb[G]);
+      vvf_off[G] = int(vvfull.size());
+      for (int ga = 0; ga < h; ++ga) {
+        const int gb = ga ^ G;
+        for (int a = 0; a < nv[ga]; ++a)
+          for (int b = 0; b < nv[gb]; ++b) vvfull.push_back(int(L.vv_off[G][gb] + int64_t(b) * nv[ga] + a));
+      }
+      th_off[G] = SP.th_elems;
+      const int64_t nr = L.n_oo_pk[G], ncl = L.n_vv_pk[G];
+      if (nr > 0 && ncl > 0) {
+        PackJob J{};
+        J.sys = s;
+        J.nrow = int(nr);
+        J.ncol = int(ncl);
+        J.ldx = int(L.n_vv[G]);
+        J.ij_off = ij_off[G];
+        J.vv_off = vv_off[G];
+        J.x_off = L.amp_off[G];
+        J.th_off = SP.th_elems;
+        const int jid = int(packjobs.size());
+        packjobs.push_back(J);
+        for (int r = 0; r < nr; ++r) packrows.push_back(int2{jid, r});
+        SP.th_elems += 2 * nr * ncl;
+      }
+      if (probs[s].pair_energy)
+        for (int gi = 0; gi < h; ++gi) {
+          const int gj = gi ^ G;
+          for (int i = 0; i < no[gi]; ++i)
+            for (int j = 0; j < no[gj]; ++j) {
+              EnergyJob E{};
+              E.sys = s;
+              E.ncol = int(L.n_vv[G]);
+              E.ldr = int(L.n_vv[G]);
+              E.vvfull_off = vvf_off[G];
+              E.row = int(L.oo_off[G][gi] + int64_t(i) * no[gj] + j);
+              E.I = int(L.occ_off[gi] + i);
+              E.J = int(L.occ_off[gj] + j);
+              E.nocc_tot = int(L.nocc_tot);
+              E.r_off = L.amp_off[G];
+              if (E.ncol > 0) ejobs.push_back(E);
+            }
+        }
+    }
+    // Lambda operand stack
+    if (lambda)
+      for (int gP = 0; gP < h; ++gP)
+        for (int ga = 0; ga < h; ++ga) {
+          const int ge = ga ^ gP;
+          if (nc[gP] == 0 || nv[ga] == 0 || nv[ge] == 0) continue;
+          DressJob D{};
+          D.sys = s;
+          D.va = nv[ga];
+          D.ve = nv[ge];
+          D.np = nc[gP];
+          D.om = no[ge];
+          D.u_off = kmul * L.b_off[gP][ga];
+          D.b_off = L.b_off[gP][ge];
+          D.bvo_off = L.bvo_off[gP][ga];
+          D.t1_off = L.t1_off[ge];
+          const int jid = int(dressjobs.size());
+          dressjobs.push_back(D);
+          for (int a = 0; a < nv[ga]; ++a) dressrows.push_back(int2{jid, a});
+        }
+    // mixed path: row slicing of the operand and of the packed amplitudes
+    if (opts.precision == CDCC_MIXED) {
+      for (int gP = 0; gP < h; ++gP)
+        for (int ga = 0; ga < h; ++ga) {
+          const int gc = ga ^ gP;
+          const int64_t r = int64_t(nv[ga]) * nv[gc];
+          if (nc[gP] == 0 || r == 0) continue;
+          SliceJob J{};
+          J.sys = s;
+          J.rows = int(r);
+          J.K = kmul * nc[gP];
+          J.which = 0;
+          J.src_off = kmul * L.b_off[gP][ga];
+          J.dst_off = kmul * L.b_off[gP][ga];
+          J.scale_off = 0;  // filled below
+          J.ld_src = J.K;
+          J.ld_dst = J.K;
+          slicejobs.push_back(J);
+        }
+    }
+
+    // column groups
+    for (int G = 0; G < h; ++G) {
+      const int64_t n_ij = L.n_oo_pk[G];
+      for (int ga = 0; ga < h; ++ga) {
+        const int gb = ga ^ G;
+        if (ga < gb || nv[ga] == 0 || nv[gb] == 0) continue;
+        const bool tri = ga == gb;
+        // region rows: (c,d) for Gc with N_{Ga^Gc} > 0
+        int64_t xrow0[CDCC_MAX_IRREP];
+        bool valid[CDCC_MAX_IRREP];
+        int64_t nrows = 0;
+        for (int gc = 0; gc < h; ++gc) {
+          const int gd = gc ^ G;
+          valid[gc] = nc[ga ^ gc] > 0 && nv[gc] > 0 && nv[gd] > 0;
+          xrow0[gc] = nrows;
+          if (valid[gc]) nrows += int64_t(nv[gc]) * nv[gd];
+        }
+        // K table of (G, Ga)
+        const int kt_off = int(ktab.size());
+        {
+          const int64_t base = vv_off[G];
+          for (int gc = 0; gc < h; ++gc) {
+            const int gd = gc ^ G;
+            if (gc < gd) continue;
+            for (int c = 0; c < nv[gc]; ++c)
+              for (int d = 0; d < (gc == gd ? c + 1 : nv[gd]); ++d) {
+                const int64_t kcol = vv_sb[G][gc] + (gc == gd ? int64_t(c) * (c + 1) / 2 + d : int64_t(c) * nv[gd] + d);
+                const int r1 = valid[gc] ? int(xrow0[gc] + int64_t(c) * nv[gd] + d) : -1;
+                const int r2 = valid[gd] ? int(xrow0[gd] + int64_t(d) * nv[gc] + c) : -1;
+                if (r1 < 0 && r2 < 0) continue;
+                ktab.push_back(int4{int(kcol), r1, r2, 0});
+              }
+          }
+          (void)base;
+          while ((ktab.size() - kt_off) % 16) ktab.push_back(int4{-1, -1, -1, 0});
+        }
+        const int kt_len = int(ktab.size()) - kt_off;
+        // split the a range so that one group's region fits the cap
+        auto ncols_of = [&](int a0, int a1) -> int64_t {
+          return tri ? (int64_t(a1) * (a1 + 1) / 2 - int64_t(a0) * (a0 + 1) / 2) : int64_t(a1 - a0) * nv[gb];
+        };
+        int a0 = 0;
+        while (a0 < nv[ga]) {
+          int a1 = a0 + 1;
+          while (a1 < nv[ga] && std::max<int64_t>(nrows, 1) * ncols_of(a0, a1 + 1) <= cap_elems) ++a1;
+          GroupRec R;
+          R.sys = s;
+          P2Group &g = R.g;
+          g.sys = s;
+          g.G = G;
+          g.n_ij = int(n_ij);
+          g.ncols = int(ncols_of(a0, a1));
+          g.ldx = g.ncols;
+          g.ktab_len = kt_len;
+          g.ktab_off = kt_off;
+          g.ij_off = ij_off[G];
+          g.col_off = int(vv_off[G] + vv_sb[G][ga] + (tri ? int64_t(a0) * (a0 + 1) / 2 : int64_t(a0) * nv[gb]));
+          g.ldr = int(L.n_vv[G]);
+          g.th_ld = int(L.n_vv_pk[G]);
+          g.th_off = th_off[G];
+          g.r_off = L.amp_off[G];
+          R.region = nrows * g.ncols;
+          R.p2cls = n_ij > 64 ? 1 : 0;
+          // assembly GEMMs
+          const int bm = kP1BM[SP.p1cls];
+          for (int gc = 0; gc < h; ++gc) {
+            if (!valid[gc]) continue;
+            const int gd = gc ^ G, gP = ga ^ gc;
+            const int vc = nv[gc], vd = nv[gd];
+            const int K = kmul * nc[gP];
+            const int step = tri ? std::max(1, bm / std::max(vc, 1)) : (a1 - a0);
+            for (int as = a0; as < a1; as += step) {
+              const int ae = std::min(a1, as + step);
+              P1Desc d{};
+              d.sys = s;
+              d.M = (ae - as) * vc;
+              d.nb = tri ? ae : nv[gb];
+              d.N = d.nb * vd;
+              d.K = K;
+              d.kneg = (lambda && dressed) ? nc[gP] : K;
+              d.vc = vc;
+              d.vd = vd;
+              d.vb = nv[gb];
+              d.a_first = as;
+              d.ga0 = a0;
+              d.tri = tri ? 1 : 0;
+              d.ldx = g.ldx;
+              d.xrow0 = int(xrow0[gc]);
+              d.aoff = kmul * L.b_off[gP][ga] + int64_t(as) * vc * K;
+              d.boff = kmul * L.b_off[gP][gb];
+              d.ooff = kmul * L.b_off[gP][ga];
+              d.boff_blk = kmul * L.b_off[gP][gb];
+              R.descs.push_back(d);
+            }
+          }
+          groups.push_back(std::move(R));
+          a0 = a1;
+        }
+      }
+    }
+  }
+
+  // batches: consecutive groups whose regions fit the cap
+  std::vector<P1Desc> p1;
+  std::vector<Tile> p1tiles;
+  std::vector<P2Group> p2;
+  std::vector<Tile> p2tiles;
+  size_t gi = 0;
+  while (gi < groups.size()) {
+    int64_t used = 0;
+    size_t gj = gi;
+    while (gj < groups.size() && (gj == gi || used + groups[gj].region <= cap_elems)) {
+      used += align_up(groups[gj].region, 32);
+      ++gj;
+    }
+    BatchPlan B;
+    // gather tiles by class
+    std::vector<std::vector<std::pair<int64_t, Tile>>> t1(3), t2(2);
+    int64_t xo = 0;
+    const int desc_first = int(p1.size());
+    for (size_t k = gi; k < gj; ++k) {
+      GroupRec &R = groups[k];
+      R.g.xoff = xo;
+      xo += align_up(R.region, 32);
+      const int gid = int(p2.size());
+      p2.push_back(R.g);
+      const int c2 = R.p2cls;
+      if (R.g.n_ij > 0 && R.g.ncols > 0) {
+        const int tm = (R.g.n_ij + kP2BM[c2] - 1) / kP2BM[c2], tn = (R.g.ncols + kP2BN[c2] - 1) / kP2BN[c2];
+        for (int a = 0; a < tm; ++a)
+          for (int b = 0; b < tn; ++b) t2[c2].push_back({int64_t(R.g.ktab_len) + 1, Tile{gid, a, b, c2}});
+      }
+      const int c1 = P.sys[R.sys].p1cls;
+      for (P1Desc d : R.descs) {
+        d.xoff = R.g.xoff;
+        const int did = int(p1.size());
+        p1.push_back(d);
+        const int bm = kP1BM[c1], bn = kP1BN[c1];
+        const int tm = (d.M + bm - 1) / bm, tn = (d.N + bn - 1) / bn;
+        for (int a = 0; a < tm; ++a)
+          for (int b = 0; b < tn; ++b) {
+            if (d.tri) {  // skip tiles that lie entirely above the a>=b triangle
+              const int n0 = b * bn, n1 = std::min(d.N, n0 + bn) - 1;
+              const int minb = (n0 / d.nb == n1 / d.nb) ? n0 % d.nb : 0;
+              const int maxa = d.a_first + std::min(d.M - 1, a * bm + bm - 1) / d.vc;
+              if (minb > maxa) continue;
+            }
+            t1[c1].push_back({int64_t(d.K), Tile{did, a, b, c1}});
+          }
+      }
+    }
+    B.p1_desc_range = {{desc_first, int(p1.size())}};
+    P.xbuf_elems = std::max(P.xbuf_elems, xo);
+    for (int c = 0; c < 3; ++c) {
+      auto &v = t1[c];
+      if (v.empty()) continue;
+      std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+      Launch l;
+      l.cls = c;
+      l.start = int(p1tiles.size());
+      l.count = int(v.size());
+      l.grid = std::min<int>(l.count, c == 2 ? 512 : 1024);
+      for (auto &e : v) p1tiles.push_back(e.second);
+      B.p1.push_back(l);
+    }
+    for (int c = 0; c < 2; ++c) {
+      auto &v = t2[c];
+      if (v.empty()) continue;
+      std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+      Launch l;
+      l.cls = c;
+      l.start = int(p2tiles.size());
+      l.count = int(v.size());
+      l.grid = std::min<int>(l.count, 1024);
+      for (auto &e : v) p2tiles.push_back(e.second);
+      B.p2.push_back(l);
+    }
+    P.batches.push_back(std::move(B));
+    gi = gj;
+  }
+  P.np1 = int(p1.size());
+  int nl = 0;
+  for (auto &b : P.batches) nl += int(b.p1.size() + b.p2.size());
+  P.ncounters = nl;
+
+  // upload all tables in one allocation
+  TableBuilder T;
+  const int64_t o_pj = T.add(packjobs), o_pr = T.add(packrows), o_dj = T.add(dressjobs), o_dr = T.add(dressrows);
+  const int64_t o_p1 = T.add(p1), o_t1 = T.add(p1tiles), o_p2 = T.add(p2), o_t2 = T.add(p2tiles);
+  const int64_t o_kt = T.add(ktab), o_ij = T.add(ijtab), o_vv = T.add(vvtab), o_vf = T.add(vvfull);
+  const int64_t o_ej = T.add(ejobs), o_sj = T.add(slicejobs), o_sr = T.add(slicerows);
+  if (hipMalloc(&P.dtab, std::max<size_t>(T.bytes.size(), 256)) != hipSuccess) return CDCC_ENOMEM;
+  if (hipMemcpy(P.dtab, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return CDCC_EDEVICE;
+  char *b = static_cast<char *>(P.dtab);
+  P.packjobs = reinterpret_cast<PackJob *>(b + o_pj);
+  P.packrows = reinterpret_cast<int2 *>(b + o_pr);
+  P.npackrows = int(packrows.size());
+  P.dressjobs = reinterpret_cast<DressJob *>(b + o_dj);
+  P.dressrows = reinterpret_cast<int2 *>(b + o_dr);
+  P.ndressrows = int(dressrows.size());
+  P.p1 = reinterpret_cast<P1Desc *>(b + o_p1);
+  P.p1tiles = reinterpret_cast<Tile *>(b + o_t1);
+  P.p2 = reinterpret_cast<P2Group *>(b + o_p2);
+  P.p2tiles = reinterpret_cast<Tile *>(b + o_t2);
+  P.ktab = reinterpret_cast<int4 *>(b + o_kt);
+  P.ijtab = reinterpret_cast<int4 *>(b + o_ij);
+  P.vvtab = reinterpret_cast<int4 *>(b + o_vv);
+  P.vvfull = reinterpret_cast<int *>(b + o_vf);
+  P.ejobs = reinterpret_cast<EnergyJob *>(b + o_ej);
+  P.nejobs = int(ejobs.size());
+  P.slicejobs = reinterpret_cast<SliceJob *>(b + o_sj);
+  P.slicerows = reinterpret_cast<int2 *>(b + o_sr);
+  P.nslicerows = int(slicerows.size());
+  return CDCC_OK;
+}
+
+// Workspace layout of one call.
+struct WsLayout {
+  int64_t counters = 0, sysptrs = 0, xbuf = 0, total = 0;
+  std::vector<int64_t> th, u;
+};
+
+WsLayout ws_layout(const Plan &P) {
+  WsLayout W;
+  int64_t o = 0;
+  W.counters = o;
+  o = align_up(o + int64_t(std::max(P.ncounters, 1)) * 4);
+  W.sysptrs = o;
+  o = align_up(o + int64_t(P.nsys) * int64_t(sizeof(SysPtrs)));
+  W.xbuf = o;
+  o = align_up(o + P.xbuf_elems * 8);
+  W.th.resize(P.nsys);
+  W.u.resize(P.nsys);
+  for (int s = 0; s < P.nsys; ++s) {
+    W.th[s] = o;
+    o = align_up(o + P.sys[s].th_elems * 8);
+    W.u[s] = o;
+    o = align_up(o + P.sys[s].u_elems * 8);
+  }
+  W.total = o;
+  return W;
+}
+
+int validate(int32_t nsys, const cdcc_problem_t *probs, int lambda, int *dressed) {
+  if (nsys < 1 || !probs) return CDCC_EINVAL;
+  int dr = -1;
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_problem_t &p = probs[s];
+    if (!p.lay || !p.B || !p.X || !p.R) return CDCC_EINVAL;
+    if (!valid_sym(p.lay->sym)) return p.lay->sym.nirrep >= 1 && p.lay->sym.nirrep <= 8 ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+    cdcc_layout_t chk;
+    if (cdcc_irrep_layout(&p.lay->sym, &chk) != CDCC_OK) return CDCC_EINVAL;
+    if (chk.amp_size != p.lay->amp_size || chk.b_size != p.lay->b_size) return CDCC_EINVAL;
+    if (p.delta && (!p.eps_occ || !p.eps_vir)) return CDCC_EINVAL;
+    if (lambda) {
+      if ((p.Bvo == nullptr) != (p.t1 == nullptr)) return CDCC_EINVAL;
+      const int d = p.t1 ? 1 : 0;
+      if (dr >= 0 && dr != d) return CDCC_EINVAL;  // one batch: all dressed or all undressed
+      dr = d;
+    }
+    // the amplitude tables use 32-bit indices
+    for (int G = 0; G < p.lay->sym.nirrep; ++G)
+      if (p.lay->n_vv[G] >= (int64_t(1) << 31) || p.lay->n_oo[G] >= (int64_t(1) << 31)) return CDCC_EUNSUPPORTED;
+  }
+  *dressed = dr > 0 ? 1 : 0;
+  return CDCC_OK;
+}
+
+int64_t batch_cap(const cdcc_opts_t &o) {
+  int64_t cap = o.batch_bytes > 0 ? o.batch_bytes : env_i64("CDCC_BATCH_MB", 1024) * (int64_t(1) << 20);
+  return std::max<int64_t>(cap, 1 << 16);
+}
+
+int get_plan(int dev, int32_t nsys, const cdcc_problem_t *probs, int lambda, int dressed, const cdcc_opts_t &opts,
+             std::shared_ptr<Plan> &out) {
+  const int64_t cap = batch_cap(opts);
+  const std::string key = plan_key(dev, nsys, probs, lambda, dressed, opts, cap);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    out = it->second;
+    return CDCC_OK;
+  }
+  auto P = std::make_shared<Plan>();
+  const int rc = build_plan(nsys, probs, lambda, dressed, opts, cap, *P);
+  if (rc != CDCC_OK) return rc;
+  if (g_plans.size() > 256) g_plans.clear();
+  g_plans[key] = P;
+  out = P;
+  return CDCC_OK;
+}
+
+int get_workspace(int dev, hipStream_t stream, int64_t bytes, int64_t staging, Workspace *&out) {
+  auto &slot = g_ws[{dev, (void *)stream}];
+  if (!slot) slot.reset(new Workspace());
+  Workspace &W = *slot;
+  const int64_t fail_above = env_i64("CDCC_FAIL_ALLOC_ABOVE", -1);
+  if (W.bytes < bytes) {
+    if (fail_above >= 0 && bytes > fail_above) return CDCC_ENOMEM;
+    if (W.dev) {
+      if (hipStreamSynchronize(stream) != hipSuccess) return CDCC_EDEVICE;
+      (void)hipFree(W.dev);
+      W.dev = nullptr;
+      W.bytes = 0;
+    }
+    if (hipMalloc(&W.dev, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      W.dev = nullptr;
+      return CDCC_ENOMEM;
+    }
+    W.bytes = bytes;
+  }
+  if (!W.ev) {
+    if (hipEventCreateWithFlags(&W.ev, hipEventDisableTiming) != hipSuccess) return CDCC_EDEVICE;
+  }
+  if (W.staging_bytes < staging) {
+    if (W.ev_recorded && hipEventSynchronize(W.ev) != hipSuccess) return CDCC_EDEVICE;
+    if (W.staging) (void)hipHostFree(W.staging);
+    W.staging = nullptr;
+    if (hipHostMalloc(&W.staging, staging, hipHostMallocDefault) != hipSuccess) return CDCC_ENOMEM;
+    W.staging_bytes = staging;
+  }
+  out = &W;
+  return CDCC_OK;
+}
+
+#define HIPCHK(x)                               \
+  do {                                          \
+    if ((x) != hipSuccess) return CDCC_EDEVICE; \
+  } while (0)
+
+int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *popts, void *vstream, int lambda) {
+  cdcc_opts_t opts{};
+  if (popts) opts = *popts;
+  if (opts.precision != CDCC_FP64 && opts.precision != CDCC_MIXED) return CDCC_EINVAL;
+  if (opts.tile_policy < 0 || opts.tile_policy > 3) return CDCC_EINVAL;
+  if (opts.precision == CDCC_MIXED) return CDCC_EUNSUPPORTED;  // split-BF16 kernels not wired in yet
+  int dressed = 0;
+  int rc = validate(nsys, probs, lambda, &dressed);
+  if (rc != CDCC_OK) return rc;
+  hipStream_t stream = static_cast<hipStream_t>(vstream);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  std::shared_ptr<Plan> P;
+  rc = get_plan(dev, nsys, probs, lambda, dressed, opts, P);
+  if (rc != CDCC_OK) return rc;
+  const WsLayout W = ws_layout(*P);
+  Workspace *ws = nullptr;
+  rc = get_workspace(dev, stream, W.total, int64_t(nsys) * sizeof(SysPtrs), ws);
+  if (rc != CDCC_OK) return rc;
+  char *base = static_cast<char *>(ws->dev);
+
+  // per-call pointer table
+  if (ws->ev_recorded) HIPCHK(hipEventSynchronize(ws->ev));
+  SysPtrs *hs = static_cast<SysPtrs *>(ws->staging);
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_problem_t &p = probs[s];
+    SysPtrs q{};
+    q.opnd = lambda ? reinterpret_cast<const double *>(base + W.u[s]) : p.B;
+    q.X = p.X;
+    q.R = p.R;
+    q.delta = p.delta;
+    q.eps_occ = p.eps_occ;
+    q.eps_vir = p.eps_vir;
+    q.epair = p.pair_energy;
+    q.tauhat = reinterpret_cast<double *>(base + W.th[s]);
+    q.B = p.B;
+    q.Bvo = p.Bvo;
+    q.t1 = p.t1;
+    hs[s] = q;
+  }
+  SysPtrs *dsp = reinterpret_cast<SysPtrs *>(base + W.sysptrs);
+  HIPCHK(hipMemcpyAsync(dsp, hs, size_t(nsys) * sizeof(SysPtrs), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(ws->ev, stream));
+  ws->ev_recorded = true;
+
+  int *counters = reinterpret_cast<int *>(base + W.counters);
+  double *xbuf = reinterpret_cast<double *>(base + W.xbuf);
+  HIPCHK(launch_fill_int(counters, P->ncounters, 0, stream));
+  if (lambda) {
+    Span sp(0, P->ndressrows > 0, stream);
+    HIPCHK(launch_dress(P->dressjobs, P->dressrows, P->ndressrows, dsp, stream));
+  }
+  {
+    Span sp(1, P->npackrows > 0, stream);
+    HIPCHK(launch_pack(P->packjobs, P->packrows, P->npackrows, dsp, P->ijtab, P->vvtab, stream));
+  }
+  int ci = 0;
+  for (const BatchPlan &B : P->batches) {
+    {
+      Span sp(2, int(B.p1.size()), stream);
+      for (const Launch &l : B.p1)
+        HIPCHK(launch_assemble_f64(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.count, counters + ci++, dsp, xbuf,
+                                   stream));
+    }
+    {
+      Span sp(3, int(B.p2.size()), stream);
+      for (const Launch &l : B.p2)
+        HIPCHK(launch_contract_f64(l.cls, l.grid, P->p2, P->p2tiles + l.start, l.count, counters + ci++, dsp, xbuf,
+                                   P->ktab, P->ijtab, P->vvtab, stream));
+    }
+  }
+  {
+    Span sp(4, P->nejobs > 0, stream);
+    HIPCHK(launch_energy(P->ejobs, P->nejobs, dsp, P->vvfull, stream));
+  }
+  return CDCC_OK;
+}
+
+}  // namespace
+
+extern "C" int cdcc_ladder_t2(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *opts, void *stream) {
+  return run_ladder(nsys, probs, opts, stream, 0);
+}
+
+extern "C" int cdcc_ladder_lambda(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *opts, void *stream) {
+  return run_ladder(nsys, probs, opts, stream, 1);
+}
+
+extern "C" int cdcc_workspace_bytes(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *popts,
+                                    int32_t lambda, int64_t *bytes) {
+  if (!bytes) return CDCC_EINVAL;
+  cdcc_opts_t opts{};
+  if (popts) opts = *popts;
+  int dressed = 0;
+  int rc = validate(nsys, probs, lambda, &dressed);
+  if (rc != CDCC_OK) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CDCC_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_mu);
+  std::shared_ptr<Plan> P;
+  rc = get_plan(dev, nsys, probs, lambda, dressed, opts, P);
+  if (rc != CDCC_OK) return rc;
+  *bytes = ws_layout(*P).total;
+  return CDCC_OK;
+}
+
+extern "C" int cdcc_timing_enable(int32_t on) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_timing = on != 0;
+  return CDCC_OK;
+}
+
+extern "C" int cdcc_timing_read(double ms[8], int64_t launches[8]) {
+  if (!ms || !launches) return CDCC_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (int k = 0; k < 8; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  int rc = CDCC_OK;
+  for (const TimedSpan &t : g_spans) {
+    float e = 0.f;
+    if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&e, t.a, t.b) != hipSuccess) rc = CDCC_EDEVICE;
+    ms[t.cls] += e;
+    launches[t.cls] += t.launches;
+    g_event_pool.push_back(t.a);
+    g_event_pool.push_back(t.b);
+  }
+  g_spans.clear();
+  return rc;
+}
+
+extern "C" int cdcc_release(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  if (hipDeviceSynchronize() != hipSuccess) return CDCC_EDEVICE;
+  g_ws.clear();
+  g_plans.clear();
+  for (const TimedSpan &t : g_spans) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  g_spans.clear();
+  for (hipEvent_t e : g_event_pool) (void)hipEventDestroy(e);
+  g_event_pool.clear();
+  return CDCC_OK;
+}

@@ -1,0 +1,444 @@
+// FP64 kernels of the particle-particle ladder for gfx950 (CDNA4).
+//
+// Pipeline of one evaluation (paper: PPL equations of the Lambda section,
+// symmetric-antisymmetric algorithm; Appendix A for the Lambda W):
+//   pack     X -> tauhat(+/-), stored halves i>=j, c>=d, weights folded in
+//   dress    (Lambda) U^P_ae = B^P_ea - t^P_ea and t^P_ea, a signed K stack
+//   assemble X_{cd,ab} = 1/2 sum_P U^P_ac U^P_bd into a bounded batch buffer
+//            (grouped GEMM on MFMA f64 16x16x4, operands staged in LDS)
+//   contract S = tauhat(+) W(+), A = tauhat(-) W(-), W(+/-) = X_cd +/- X_dc
+//            formed while staging; the epilogue unpacks S +/- A into the four
+//            (ij,ab) permutations of R and writes R / D
+//   energy   e_ij = sum_ab (2 X_ij^ab - X_ij^ba) R_ij^ab, fixed-order tree
+// Tiles are pulled from an integer work counter (persistent workgroups).
+#include <hip/hip_runtime.h>
+
+#include "ladder_types.hpp"
+
+namespace cdcc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__global__ void fill_int_kernel(int *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// pack: one workgroup per packed row (i>=j) of one (system, G).
+//   tauhat(+)_ij^cd = X_ij^cd + X_ij^dc   (c>d),   X_ij^cc   (c=d)
+//   tauhat(-)_ij^cd = X_ij^cd - X_ij^dc   (c>d),   0         (c=d or i=j)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pack_kernel(const PackJob *__restrict__ jobs,
+                                                   const int2 *__restrict__ rows,
+                                                   const SysPtrs *__restrict__ sp,
+                                                   const int4 *__restrict__ ijtab,
+                                                   const int4 *__restrict__ vvtab) {
+  const int2 jr = rows[blockIdx.x];
+  const PackJob J = jobs[jr.x];
+  const int r = jr.y;
+  const SysPtrs S = sp[J.sys];
+  const int4 ij = ijtab[J.ij_off + r];
+  const bool diag_ij = ij.x == ij.y;
+  const double *__restrict__ xr = S.X + J.x_off + int64_t(ij.x) * J.ldx;
+  double *__restrict__ tp = S.tauhat + J.th_off + int64_t(r) * J.ncol;
+  double *__restrict__ tm = tp + int64_t(J.nrow) * J.ncol;
+  for (int k = threadIdx.x; k < J.ncol; k += blockDim.x) {
+    const int4 cd = vvtab[J.vv_off + k];
+    const double x1 = xr[cd.x];
+    const double x2 = xr[cd.y];
+    const bool dcd = cd.x == cd.y;
+    tp[k] = dcd ? x1 : x1 + x2;
+    tm[k] = (dcd || diag_ij) ? 0.0 : x1 - x2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dress (Lambda, Appendix A): rows (job, a); for every e in Ge = Ga^GP, P:
+//   t^P_ea = sum_m t_m^e L^P_am,  U[a][e][P] = B^P_ea - t^P_ea,
+//   U[a][e][np + P] = t^P_ea   (subtracted in the assembly: kneg = np)
+// Without singles (om == 0 or no t1) only the first half is written.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void dress_kernel(const DressJob *__restrict__ jobs,
+                                                    const int2 *__restrict__ rows,
+                                                    const SysPtrs *__restrict__ sp,
+                                                    double *__restrict__ ubuf_unused) {
+  (void)ubuf_unused;
+  const int2 jr = rows[blockIdx.x];
+  const DressJob J = jobs[jr.x];
+  const int a = jr.y;
+  const SysPtrs S = sp[J.sys];
+  double *__restrict__ U = const_cast<double *>(S.opnd);
+  const bool dressed = S.t1 != nullptr && S.Bvo != nullptr;
+  const int kst = dressed ? 2 * J.np : J.np;
+  const int n = J.ve * J.np;
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int e = idx / J.np, P = idx - e * J.np;
+    const double bea = S.B[J.b_off + (int64_t(e) * J.va + a) * J.np + P];
+    double tea = 0.0;
+    if (dressed)
+      for (int m = 0; m < J.om; ++m)
+        tea += S.t1[J.t1_off + int64_t(m) * J.ve + e] * S.Bvo[J.bvo_off + (int64_t(a) * J.om + m) * J.np + P];
+    double *urow = U + J.u_off + (int64_t(a) * J.ve + e) * kst;
+    urow[P] = bea - tea;
+    if (dressed) urow[J.np + P] = tea;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// assemble (FP64): X[(c,d),(a,b)] = 1/2 sum_K U[(a,c),K] s_K U[(b,d),K]
+// Tile BM x BN of the (a,c) x (d,b) product, BK = 16, 4 waves in 2x2, each
+// wave (BM/2) x (BN/2) as 16x16 MFMA f64 blocks.  LDS holds [k][row].
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restrict__ descs,
+                                                           const Tile *__restrict__ tiles, int ntiles,
+                                                           int *__restrict__ counter,
+                                                           const SysPtrs *__restrict__ sp,
+                                                           double *__restrict__ xbuf) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int RA = BM / 64, RB = BN / 64;  // row slots per thread
+  __shared__ double As[BK][BM];
+  __shared__ double Bs[BK][BN];
+  __shared__ int s_tile;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = tid >> 2, lk = (tid & 3) * 4;
+
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_tile;
+    __syncthreads();
+    if (t >= ntiles) break;
+    const Tile tl = tiles[t];
+    const P1Desc D = descs[tl.desc];
+    const double *__restrict__ op = sp[D.sys].opnd;
+    const int m0 = tl.tm * BM, n0 = tl.tn * BN;
+    const int K = D.K;
+
+    const double *arow[RA];
+    const double *brow[RB];
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int m = m0 + lr + 64 * q;
+      arow[q] = m < D.M ? op + D.aoff + int64_t(m) * K : nullptr;
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int n = n0 + lr + 64 * q;
+      if (n < D.N) {
+        const int dd = n / D.nb, b = n - dd * D.nb;
+        brow[q] = op + D.boff + (int64_t(b) * D.vd + dd) * K;
+      } else {
+        brow[q] = nullptr;
+      }
+    }
+
+    d4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    double ra[RA][4], rb[RB][4];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < RA; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = k0 + lk + e;
+          ra[q][e] = (arow[q] && k < K) ? arow[q][k] : 0.0;
+        }
+#pragma unroll
+      for (int q = 0; q < RB; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = k0 + lk + e;
+          const double v = (brow[q] && k < K) ? brow[q][k] : 0.0;
+          rb[q][e] = k >= D.kneg ? -v : v;
+        }
+    };
+
+    gload(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < RA; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[lk + e][lr + 64 * q] = ra[q][e];
+#pragma unroll
+      for (int q = 0; q < RB; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Bs[lk + e][lr + 64 * q] = rb[q][e];
+      __syncthreads();
+      if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        double fa[FM], fb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) fa[i] = As[kr][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) fb[j] = Bs[kr][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      }
+    }
+
+    // epilogue: permuted store into the column group's X region
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
+          const int n = n0 + wn * WN + j * 16 + (lane & 15);
+          if (m >= D.M || n >= D.N) continue;
+          const int am = m / D.vc, c = m - am * D.vc;
+          const int a = D.a_first + am;
+          const int dd = n / D.nb, b = n - dd * D.nb;
+          if (D.tri && b > a) continue;
+          const int64_t xcol = D.tri ? (int64_t(a) * (a + 1) / 2 - int64_t(D.ga0) * (D.ga0 + 1) / 2 + b)
+                                     : (int64_t(a - D.ga0) * D.vb + b);
+          const int64_t xrow = D.xrow0 + int64_t(c) * D.vd + dd;
+          xbuf[D.xoff + xrow * D.ldx + xcol] = 0.5 * acc[i][j][r];
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// contract (FP64): S = tauhat(+) W(+), A = tauhat(-) W(-) over the K table of
+// the group (entries: tauhat column, X rows of (c,d) and (d,c), -1 = absent).
+// Tile BM x BN of (packed ij) x (group columns); 2x2 waves; both products
+// share the staged X rows.  Epilogue writes R (and R/D) at the four
+// permutations (ij,ab), (ij,ba) = S-A, (ji,ab) = S-A, (ji,ba) = S+A.
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__restrict__ groups,
+                                                           const Tile *__restrict__ tiles, int ntiles,
+                                                           int *__restrict__ counter,
+                                                           const SysPtrs *__restrict__ sp,
+                                                           const double *__restrict__ xbuf,
+                                                           const int4 *__restrict__ ktab,
+                                                           const int4 *__restrict__ ijtab,
+                                                           const int4 *__restrict__ vvtab) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int RA = (BM * BK) / (256 * 4);  // A row slots per thread (4 k each)
+  constexpr int CB = BN / 16;                // B columns per thread (16 threads per k row)
+  static_assert(RA >= 1, "BM too small");
+  __shared__ double Ap[BK][BM], Am[BK][BM];
+  __shared__ double Bp[BK][BN], Bm[BK][BN];
+  __shared__ int s_tile;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = tid >> 2, lk = (tid & 3) * 4;  // A staging
+  const int bk = tid >> 4, bc = (tid & 15) * CB; // B staging
+
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_tile;
+    __syncthreads();
+    if (t >= ntiles) break;
+    const Tile tl = tiles[t];
+    const P2Group g = groups[tl.desc];
+    const SysPtrs S = sp[g.sys];
+    const double *__restrict__ thp = S.tauhat + g.th_off;
+    const double *__restrict__ thm = thp + int64_t(g.n_ij) * g.th_ld;
+    const double *__restrict__ xr = xbuf + g.xoff;
+    const int4 *__restrict__ kt = ktab + g.ktab_off;
+    const int m0 = tl.tm * BM, n0 = tl.tn * BN;
+
+    d4 accS[FM][FN], accA[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        accS[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        accA[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+
+    double rap[RA][4], ram[RA][4], rbp[CB], rbm[CB];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < RA; ++q) {
+        const int r = m0 + lr + 64 * q;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int kc = kt[k0 + lk + e].x;
+          const bool ok = r < g.n_ij && kc >= 0;
+          rap[q][e] = ok ? thp[int64_t(r) * g.th_ld + kc] : 0.0;
+          ram[q][e] = ok ? thm[int64_t(r) * g.th_ld + kc] : 0.0;
+        }
+      }
+      const int4 ke = kt[k0 + bk];
+#pragma unroll
+      for (int e = 0; e < CB; ++e) {
+        const int n = n0 + bc + e;
+        const double x1 = (ke.y >= 0 && n < g.ncols) ? xr[int64_t(ke.y) * g.ldx + n] : 0.0;
+        const double x2 = (ke.z >= 0 && n < g.ncols) ? xr[int64_t(ke.z) * g.ldx + n] : 0.0;
+        rbp[e] = x1 + x2;
+        rbm[e] = x1 - x2;
+      }
+    };
+
+    if (g.ktab_len > 0) gload(0);
+    for (int k0 = 0; k0 < g.ktab_len; k0 += BK) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < RA; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          Ap[lk + e][lr + 64 * q] = rap[q][e];
+          Am[lk + e][lr + 64 * q] = ram[q][e];
+        }
+#pragma unroll
+      for (int e = 0; e < CB; ++e) {
+        Bp[bk][bc + e] = rbp[e];
+        Bm[bk][bc + e] = rbm[e];
+      }
+      __syncthreads();
+      if (k0 + BK < g.ktab_len) gload(k0 + BK);
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        double fap[FM], fam[FM], fbp[FN], fbm[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          fap[i] = Ap[kr][wm * WM + i * 16 + (lane & 15)];
+          fam[i] = Am[kr][wm * WM + i * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          fbp[j] = Bp[kr][wn * WN + j * 16 + (lane & 15)];
+          fbm[j] = Bm[kr][wn * WN + j * 16 + (lane & 15)];
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            accS[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fap[i], fbp[j], accS[i][j], 0, 0, 0);
+            accA[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fam[i], fbm[j], accA[i][j], 0, 0, 0);
+          }
+      }
+    }
+
+    double *__restrict__ R = S.R + g.r_off;
+    double *__restrict__ Dl = S.delta ? S.delta + g.r_off : nullptr;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
+          const int n = n0 + wn * WN + j * 16 + (lane & 15);
+          if (m >= g.n_ij || n >= g.ncols) continue;
+          const int4 ij = ijtab[g.ij_off + m];
+          const int4 ab = vvtab[g.col_off + n];
+          const double s = accS[i][j][r], a = accA[i][j][r];
+          const double pp = s + a, pm = s - a;
+          const int64_t ld = g.ldr;
+          const bool oab = ab.x != ab.y, oij = ij.x != ij.y;
+          R[int64_t(ij.x) * ld + ab.x] = pp;
+          if (oab) R[int64_t(ij.x) * ld + ab.y] = pm;
+          if (oij) R[int64_t(ij.y) * ld + ab.x] = pm;
+          if (oab && oij) R[int64_t(ij.y) * ld + ab.y] = pp;
+          if (Dl) {
+            const double den = (S.eps_occ[ij.z] + S.eps_occ[ij.w]) - (S.eps_vir[ab.z] + S.eps_vir[ab.w]);
+            const double inv = 1.0 / den;
+            Dl[int64_t(ij.x) * ld + ab.x] = pp * inv;
+            if (oab) Dl[int64_t(ij.x) * ld + ab.y] = pm * inv;
+            if (oij) Dl[int64_t(ij.y) * ld + ab.x] = pm * inv;
+            if (oab && oij) Dl[int64_t(ij.y) * ld + ab.y] = pp * inv;
+          }
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pair energies: one workgroup per amplitude row (i,j); fixed-order tree.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void energy_kernel(const EnergyJob *__restrict__ jobs,
+                                                     const SysPtrs *__restrict__ sp,
+                                                     const int *__restrict__ vvfull) {
+  __shared__ double red[256];
+  const EnergyJob J = jobs[blockIdx.x];
+  const SysPtrs S = sp[J.sys];
+  if (!S.epair) return;
+  const double *__restrict__ xr = S.X + J.r_off + int64_t(J.row) * J.ldr;
+  const double *__restrict__ rr = S.R + J.r_off + int64_t(J.row) * J.ldr;
+  const int *__restrict__ tc = vvfull + J.vvfull_off;
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < J.ncol; c += 256) acc += (2.0 * xr[c] - xr[tc[c]]) * rr[c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) S.epair[int64_t(J.I) * J.nocc_tot + J.J] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_int_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const PackJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, const int4 *ijtab,
+                       const int4 *vvtab, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  pack_kernel<<<nrows, 256, 0, s>>>(jobs, rows, sp, ijtab, vvtab);
+  return hipGetLastError();
+}
+
+hipError_t launch_dress(const DressJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  dress_kernel<<<nrows, 256, 0, s>>>(jobs, rows, sp, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Tile *tiles, int ntiles, int *counter,
+                               const SysPtrs *sp, double *xbuf, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (cls) {
+    case 0: assemble_f64_kernel<64, 64><<<grid, 256, 0, s>>>(descs, tiles, ntiles, counter, sp, xbuf); break;
+    case 1: assemble_f64_kernel<128, 64><<<grid, 256, 0, s>>>(descs, tiles, ntiles, counter, sp, xbuf); break;
+    default: assemble_f64_kernel<128, 128><<<grid, 256, 0, s>>>(descs, tiles, ntiles, counter, sp, xbuf); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, int ntiles, int *counter,
+                               const SysPtrs *sp, const double *xbuf, const int4 *ktab, const int4 *ijtab,
+                               const int4 *vvtab, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (cls) {
+    case 0: contract_f64_kernel<64, 64><<<grid, 256, 0, s>>>(groups, tiles, ntiles, counter, sp, xbuf, ktab, ijtab, vvtab); break;
+    default: contract_f64_kernel<128, 64><<<grid, 256, 0, s>>>(groups, tiles, ntiles, counter, sp, xbuf, ktab, ijtab, vvtab); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  energy_kernel<<<njobs, 256, 0, s>>>(jobs, sp, vvfull);
+  return hipGetLastError();
+}
+
+}  // namespace cdcc

@@ -1,0 +1,101 @@
+// Device-visible descriptors shared by the host planner and the HIP kernels.
+// All structs are plain data, 8-byte aligned, copied to device memory once per
+// plan (tables) or once per call (pointers).
+#pragma once
+#include <stdint.h>
+
+namespace cdcc {
+
+// Per-system device pointers of one call.
+struct SysPtrs {
+  const double *opnd;    // operand of the (ac|bd) assembly: B (T2) or the dressed stack U (Lambda)
+  const double *X;       // tau or lambda, full DPD storage
+  double *R;             // result
+  double *delta;         // optional R / D
+  const double *eps_occ; // optional
+  const double *eps_vir; // optional
+  double *epair;         // optional pair energies
+  double *tauhat;        // workspace: packed +/- amplitudes of this system
+  const double *B;       // raw Cholesky vectors (Lambda dressing input)
+  const double *Bvo;     // optional vo block (Lambda)
+  const double *t1;      // optional singles (Lambda)
+  uint16_t *slices;      // workspace: BF16 slices of the assembly operand (mixed path)
+  double *rowscale;      // workspace: per-row power-of-two scales of the operand (mixed path)
+  uint16_t *thslices;    // workspace: BF16 slices of the packed amplitudes (mixed path)
+  double *thscale;       // workspace: per-row scales of the packed amplitudes (mixed path)
+  double *colnorm;       // workspace: Schwarz bound of each (a,b) column (mixed path)
+};
+
+// Packing of X into the +/- halves for one (system, pair irrep G).
+struct PackJob {
+  int32_t sys, nrow, ncol, ldx;   // nrow = n_oo_pk(G), ncol = n_vv_pk(G), ldx = n_vv(G)
+  int32_t ij_off, vv_off, pad0, pad1;
+  int64_t x_off;                  // amp_off[G]
+  int64_t th_off;                 // element offset of tauhat(+) in SysPtrs::tauhat; (-) follows
+};
+
+// One GEMM of the (ac|bd) assembly: rows (a,c) for a in [a_first, a_first+na),
+// c in Gc; columns (d,b) with b fastest; K = Cholesky index (x2 for Lambda).
+struct P1Desc {
+  int32_t sys, M, N, K;
+  int32_t kneg;        // K index from which the right operand is negated (Lambda stack)
+  int32_t vc, vd, vb;  // extents of c, d and b
+  int32_t nb;          // number of b values covered (vb, or a_last+1 when Ga == Gb)
+  int32_t a_first;     // first a of the rows
+  int32_t ga0;         // first a of the owning column group (column numbering)
+  int32_t tri;         // Ga == Gb: only b <= a is stored
+  int32_t ldx, xrow0;  // X region row length; first region row of this Gc block
+  int32_t pad0, pad1;
+  int64_t aoff;        // element offset of operand row (a_first, c=0)
+  int64_t boff;        // element offset of operand row (b=0, d=0) of block (GP, Gb)
+  int64_t xoff;        // element offset of the group's X region in the batch buffer
+  int64_t ooff;        // element offset of the block (GP, Ga) in the slice/scale buffers
+  int64_t boff_blk;    // element offset of block (GP, Gb) in the slice/scale buffers
+  int64_t colnorm_off; // offset of this group's column bounds (mixed path)
+};
+
+// One column group: the (a,b) pairs with a in [a0, a0+na) of sub-block (Ga, Gb)
+// of pair irrep G, numbered like the packed a>=b list.
+struct P2Group {
+  int32_t sys, G, n_ij, ncols;
+  int32_t ldx, ktab_len, ktab_off, ij_off;
+  int32_t col_off;     // offset into the vv-pair table for column 0 of the group
+  int32_t ldr;         // n_vv(G): R row length
+  int32_t th_ld;       // n_vv_pk(G): tauhat row length
+  int32_t pad0;
+  int64_t xoff;        // X region in the batch buffer
+  int64_t th_off;      // tauhat(+) offset; (-) at th_off + n_ij * th_ld
+  int64_t r_off;       // amp_off[G]
+  int64_t ths_off;     // mixed path: offset of this (sys,G) in the sliced tauhat buffer
+};
+
+// Per-row data of the pair-energy reduction.
+struct EnergyJob {
+  int32_t sys, ncol, ldr, vvfull_off;
+  int32_t row, I, J, nocc_tot;
+  int64_t r_off;
+};
+
+struct Tile {
+  int32_t desc, tm, tn, cls;
+};
+
+// Lambda dressing of one (system, GP, Ga) block.
+struct DressJob {
+  int32_t sys, va, ve, np;   // rows a, columns e (Ge = Ga ^ GP), Cholesky count
+  int32_t om, pad0, pad1, pad2;  // occupied count of irrep Ge
+  int64_t u_off;             // U block (a, e, 2np)
+  int64_t b_off;             // B block (GP, Ge): [e][a][P]
+  int64_t bvo_off;           // Bvo block (GP, Ga): [a][m][P]
+  int64_t t1_off;            // t1 block Ge: [m][e]
+};
+
+// Slicing of one operand block (mixed path): rows x K.
+struct SliceJob {
+  int32_t sys, rows, K, which;   // which = 0: assembly operand, 1: tauhat(+), 2: tauhat(-)
+  int64_t src_off, dst_off;      // element offsets (source doubles, destination slice units)
+  int64_t scale_off;             // row-scale offset
+  int32_t ld_src, ld_dst, pad0, pad1;
+};
+
+}  // namespace cdcc

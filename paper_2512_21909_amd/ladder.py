@@ -1,0 +1,130 @@
+"""Python entry points over the C ABI.  Device buffers are torch tensors
+(memory and streams only); every step of the computation runs in the HIP
+library.  There is no CPU fallback: a missing library or GPU raises."""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from .layout import Layout
+
+_PREC = {"fp64": _lib.FP64, "mixed": _lib.MIXED}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def require_gpu() -> None:
+    """Raise unless the HIP library is built and a GPU is visible."""
+    _lib.load()
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the ladder library runs only on the GPU")
+
+
+def _ptr(t, n, name, optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, layout needs {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_problems(problems: list[dict], lambda_: bool):
+    """Marshal a list of problem dicts into a ctypes array of cdcc_problem_t.
+    Keys: layout (Layout), B, X, R; optional eps_occ, eps_vir, delta,
+    pair_energy; Lambda: Bvo, t1."""
+    arr = (_lib.Problem * len(problems))()
+    keep = []
+    for k, p in enumerate(problems):
+        lay: Layout = p["layout"]
+        keep.append(lay)
+        q = arr[k]
+        q.lay = ctypes.pointer(lay.c)
+        q.B = _ptr(p["B"], lay.b_size, "B")
+        q.X = _ptr(p["X"], lay.amp_size, "X")
+        q.R = _ptr(p["R"], lay.amp_size, "R")
+        q.eps_occ = _ptr(p.get("eps_occ"), lay.nocc_tot, "eps_occ", True)
+        q.eps_vir = _ptr(p.get("eps_vir"), lay.nvir_tot, "eps_vir", True)
+        q.delta = _ptr(p.get("delta"), lay.amp_size, "delta", True)
+        q.pair_energy = _ptr(p.get("pair_energy"), lay.nocc_tot * lay.nocc_tot, "pair_energy", True)
+        if lambda_:
+            q.Bvo = _ptr(p.get("Bvo"), lay.bvo_size, "Bvo", True)
+            q.t1 = _ptr(p.get("t1"), lay.t1_size, "t1", True)
+    return arr, keep
+
+
+def _opts(precision, tile_policy, batch_bytes):
+    o = _lib.Opts()
+    o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+    o.tile_policy = int(tile_policy)
+    o.batch_bytes = int(batch_bytes)
+    return o
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def ladder_t2(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0) -> None:
+    """T2 ladder R_ij^ab = sum_cd tau_ij^cd (ac|bd) for one problem dict or a
+    list of them (one batched launch sequence).  Asynchronous on ``stream``."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr, keep = make_problems(problems, False)
+    o = _opts(precision, tile_policy, batch_bytes)
+    st = _lib.load().cdcc_ladder_t2(len(problems), arr, ctypes.byref(o), _stream(stream))
+    _lib.check(st, "cdcc_ladder_t2")
+
+
+def ladder_lambda(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0) -> None:
+    """Lambda ladder Z_ij^ab = sum_ef lambda_ij^ef W_efab (Appendix-A W)."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr, keep = make_problems(problems, True)
+    o = _opts(precision, tile_policy, batch_bytes)
+    st = _lib.load().cdcc_ladder_lambda(len(problems), arr, ctypes.byref(o), _stream(stream))
+    _lib.check(st, "cdcc_ladder_lambda")
+
+
+def workspace_bytes(problems, lambda_=False, precision="fp64", tile_policy=0, batch_bytes=0) -> int:
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr, keep = make_problems(problems, lambda_)
+    o = _opts(precision, tile_policy, batch_bytes)
+    out = ctypes.c_int64(0)
+    _lib.check(_lib.load().cdcc_workspace_bytes(len(problems), arr, ctypes.byref(o), int(bool(lambda_)),
+                                                ctypes.byref(out)), "cdcc_workspace_bytes")
+    return int(out.value)
+
+
+def release() -> None:
+    _lib.check(_lib.load().cdcc_release(), "cdcc_release")
+
+
+KERNEL_CLASSES = ("dress", "pack", "assemble", "contract", "energy", "slice", "unused6", "unused7")
+
+
+def timing_enable(on: bool = True) -> None:
+    """Record HIP event pairs around each kernel class of every call."""
+    _lib.check(_lib.load().cdcc_timing_enable(int(bool(on))), "cdcc_timing_enable")
+
+
+def timing_read() -> dict:
+    """{class: (total_ms, launches)} since the last read (waits for the events)."""
+    ms = (ctypes.c_double * 8)()
+    n = (_lib._i64 * 8)()
+    _lib.check(_lib.load().cdcc_timing_read(ms, n), "cdcc_timing_read")
+    return {KERNEL_CLASSES[k]: (float(ms[k]), int(n[k])) for k in range(8) if n[k]}

@@ -1,0 +1,151 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+from oracle.layout import OracleLayout
+from tests.gpu_support import blocks, device_problem, oracle_result, problem, run
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12      # normwise relative, max and Frobenius
+
+SMALL = [
+    ("c1_tiny", ([2], [5], [3])),
+    ("c2_ragged", ([3, 1], [7, 5], [9, 4])),
+    ("c2v_empty_irreps", ([2, 0, 1, 1], [6, 3, 0, 5], [5, 0, 4, 2])),
+    ("d2h_uneven", ([1, 2, 1, 0, 1, 1, 0, 2], [5, 3, 4, 2, 6, 0, 3, 2], [4, 3, 0, 2, 5, 1, 3, 0])),
+    ("d2h_cd_only_sym", ([2, 1, 1, 1, 1, 1, 1, 1], [9, 4, 6, 3, 7, 2, 4, 3], [40, 0, 0, 0, 0, 0, 0, 0])),
+    ("c1_tiles_ragged", ([5], [37], [70])),
+]
+
+
+def _check(got, ref, tol, what):
+    mx, fro = O.rel_errors(got, ref)
+    assert np.isfinite(mx) and mx <= tol and fro <= tol, f"{what}: max {mx:.3e} fro {fro:.3e}"
+    return mx, fro
+
+
+@pytest.mark.parametrize("name,spec", SMALL)
+@pytest.mark.parametrize("symB", [True, False])
+def test_t2_small_fp64(gpu_lib, name, spec, symB):
+    prob = problem(S.sym_custom(*spec), seed=7, symmetric_B=symB)
+    d = device_problem(gpu_lib, prob)
+    run(gpu_lib, d)
+    _check(blocks(d), oracle_result(prob), FP64_TOL, name)
+
+
+@pytest.mark.parametrize("name,spec", SMALL)
+@pytest.mark.parametrize("dressed", [True, False])
+def test_lambda_small_fp64(gpu_lib, name, spec, dressed):
+    prob = problem(S.sym_custom(*spec), seed=8, kind="lambda", symmetric_B=False, dressed=dressed)
+    d = device_problem(gpu_lib, prob)
+    run(gpu_lib, d, kind="lambda")
+    _check(blocks(d), oracle_result(prob), FP64_TOL, name)
+
+
+def test_t2_c1_small_fp64_with_epilogue(gpu_lib):
+    """o=8, v=40, 300 vectors: result, R/D and pair energies."""
+    prob = problem(S.sym_c1_small(), seed=0)
+    d = device_problem(gpu_lib, prob, want_delta=True, want_energy=True)
+    run(gpu_lib, d)
+    ref = oracle_result(prob)
+    _check(blocks(d), ref, FP64_TOL, "R")
+    lay = OracleLayout(prob["sym"])
+    Rf = lay.full_amp(ref)
+    eo, ev = np.concatenate(prob["eps_occ"]), np.concatenate(prob["eps_vir"])
+    dref = lay.blocks_from_full(O.denominator_update_full(Rf, eo, ev) * lay.allowed_mask())
+    _check(blocks(d, "delta"), dref, FP64_TOL, "delta")
+    e_ref = O.pair_energies_full(lay.full_amp(prob["X"]), Rf)
+    e_got = d["pair_energy"].cpu().numpy().reshape(e_ref.shape)
+    assert np.max(np.abs(e_got - e_ref)) <= 1e-12 * max(1.0, np.max(np.abs(e_ref)))
+
+
+@pytest.mark.parametrize("reading", ["A", "B"])
+def test_t2_d2h_medium_fp64(gpu_lib, reading):
+    """8 irreps, o=20, v=200, 1500 vectors (all in the totally symmetric irrep,
+    or split evenly), with R/D and pair energies."""
+    prob = problem(S.sym_d2h_medium(reading), seed=0)
+    d = device_problem(gpu_lib, prob, want_delta=True, want_energy=True)
+    run(gpu_lib, d)
+    ref = oracle_result(prob)
+    _check(blocks(d), ref, FP64_TOL, "R")
+    lay = OracleLayout(prob["sym"])
+    Rf = lay.full_amp(ref)
+    e_ref = O.pair_energies_full(lay.full_amp(prob["X"]), Rf)
+    e_got = d["pair_energy"].cpu().numpy().reshape(e_ref.shape)
+    assert np.max(np.abs(e_got - e_ref)) <= 1e-12 * max(1.0, np.max(np.abs(e_ref)))
+
+
+def test_lambda_d2h_medium_fp64(gpu_lib):
+    prob = problem(S.sym_d2h_medium(), seed=0, kind="lambda")
+    d = device_problem(gpu_lib, prob)
+    run(gpu_lib, d, kind="lambda")
+    _check(blocks(d), oracle_result(prob), FP64_TOL, "Z")
+
+
+def test_batch_bytes_and_tile_classes_agree(gpu_lib):
+    """A tiny batch cap (many bounded batches) and every tile class give the
+    same result as the default plan, bitwise."""
+    prob = problem(S.sym_custom([3, 2], [21, 14], [50, 31]), seed=3)
+    d0 = device_problem(gpu_lib, prob)
+    run(gpu_lib, d0)
+    r0 = d0["R"].cpu().numpy()
+    for kw in ({"batch_bytes": 1 << 16}, {"tile_policy": 1}, {"tile_policy": 2}, {"tile_policy": 3}):
+        d = device_problem(gpu_lib, prob)
+        run(gpu_lib, d, **kw)
+        assert np.array_equal(d["R"].cpu().numpy(), r0), kw
+
+
+def test_batched_systems_equal_alone(gpu_lib):
+    """Several systems of different shapes in one call: each result equals the
+    result of the same system alone (bitwise) and the oracle."""
+    syms = S.batch_syms(6, seed=1)
+    probs = [problem(s, seed=k) for k, s in enumerate(syms)]
+    ds = [device_problem(gpu_lib, p) for p in probs]
+    run(gpu_lib, ds)
+    for p, d in zip(probs, ds):
+        alone = device_problem(gpu_lib, p)
+        run(gpu_lib, alone)
+        assert np.array_equal(alone["R"].cpu().numpy(), d["R"].cpu().numpy())
+        _check(blocks(d), oracle_result(p), FP64_TOL, str(p["sym"]))
+
+
+def test_repeatable_bitwise(gpu_lib):
+    prob = problem(S.sym_d2h_medium("B"), seed=4)
+    d = device_problem(gpu_lib, prob)
+    run(gpu_lib, d)
+    r1 = d["R"].cpu().numpy()
+    run(gpu_lib, d)
+    assert np.array_equal(r1, d["R"].cpu().numpy())
+
+
+def test_t2_d2h_large_sampled_fp64(gpu_lib):
+    """o=40, v=400, 3000 vectors at full size: sampled elements against the
+    oracle's one-by-one evaluation, plus R_ij^ab = R_ji^ba everywhere."""
+    prob = problem(S.sym_d2h_large(), seed=0)
+    sym = prob["sym"]
+    d = device_problem(gpu_lib, prob)
+    run(gpu_lib, d)
+    lay = d["layout"]
+    R = d["R"].cpu().numpy()
+    assert np.all(np.isfinite(R))
+    Rb = lay.unpack_amp(R)
+    rng = np.random.default_rng(123)
+    no, nv = sym["nocc"], sym["nvir"]
+    scale = max(float(np.max(np.abs(b))) for b in Rb.values() if b.size)
+    worst = 0.0
+    for _ in range(300):
+        G, gi, ga = (int(x) for x in rng.integers(0, 8, 3))
+        gj, gb = gi ^ G, ga ^ G
+        if not (no[gi] and no[gj] and nv[ga] and nv[gb]):
+            continue
+        i, j = int(rng.integers(no[gi])), int(rng.integers(no[gj]))
+        a, b = int(rng.integers(nv[ga])), int(rng.integers(nv[gb]))
+        I, J = lay.occ_off[gi] + i, lay.occ_off[gj] + j
+        A, Bg = lay.vir_off[ga] + a, lay.vir_off[gb] + b
+        ref = O.element_t2(sym, prob["B"], prob["X"], I, J, A, Bg)
+        worst = max(worst, abs(Rb[(G, gi, ga)][i, j, a, b] - ref) / scale)
+        assert Rb[(G, gi, ga)][i, j, a, b] == Rb[(G, gj, gb)][j, i, b, a]
+    assert worst <= FP64_TOL, worst
