@@ -34,13 +34,9 @@ hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const T
                                const int4 *vvtab, hipStream_t s);
 hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s);
 // mixed path (kernels_mixed.hip)
-hipError_t launch_slice_rows(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s);
-hipError_t launch_colnorm(const P1Desc *descs, int ndesc, const SysPtrs *sp, hipStream_t s);
+hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s);
 hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, int ntiles, int *counter,
                                  const SysPtrs *sp, double *xbuf, hipStream_t s);
-hipError_t launch_contract_mixed(int cls, int grid, const P2Group *groups, const Tile *tiles, int ntiles,
-                                 int *counter, const SysPtrs *sp, const double *xbuf, const int4 *ktab,
-                                 const int4 *ijtab, const int4 *vvtab, const double *colbound, hipStream_t s);
 }  // namespace cdcc
 
 using namespace cdcc;
@@ -53,6 +49,8 @@ inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a 
 // P1 (assembly) tile classes and P2 (contraction) tile classes.
 constexpr int kP1BM[3] = {64, 128, 128};
 constexpr int kP1BN[3] = {64, 64, 128};
+constexpr int kMixBM[2] = {64, 128};   // mixed path assembly tiles
+constexpr int kMixBN[2] = {128, 64};
 constexpr int kP2BM[2] = {64, 128};
 constexpr int kP2BN[2] = {64, 64};
 
@@ -61,15 +59,14 @@ struct Launch {
 };
 struct BatchPlan {
   std::vector<Launch> p1, p2;
-  std::vector<std::pair<int, int>> p1_desc_range;  // mixed path: descs whose column bounds to compute
 };
 
 struct SysPlan {
   cdcc_layout_t lay{};
   int64_t th_elems = 0;      // packed +/- amplitudes
   int64_t u_elems = 0;       // Lambda operand stack
-  int64_t op_rows = 0;       // rows of the assembly operand (mixed path slices)
-  int64_t op_elems = 0;      // elements of the assembly operand
+  int64_t slice_u16 = 0;     // mixed path: sliced operand (uint16 units)
+  int64_t scale_rows = 0;    // mixed path: row scales
   int p1cls = 0;
 };
 
@@ -100,7 +97,6 @@ struct Plan {
   std::vector<BatchPlan> batches;
   int ncounters = 0;
   int64_t xbuf_elems = 0;
-  int64_t colbound_elems = 0;
   ~Plan() {
     if (dtab) (void)hipFree(dtab);
   }
@@ -292,13 +288,34 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     const int h = L.sym.nirrep;
     const int32_t *no = L.sym.nocc, *nv = L.sym.nvir, *nc = L.sym.ncd;
     const int kmul = (lambda && dressed) ? 2 : 1;
-    SP.p1cls = choose_p1_class(L, opts.tile_policy);
-    SP.op_elems = kmul * L.b_size;
-    int64_t rows = 0;
-    for (int gP = 0; gP < h; ++gP)
-      for (int ga = 0; ga < h; ++ga) rows += int64_t(nv[ga]) * nv[ga ^ gP] * (nc[gP] > 0 ? 1 : 0);
-    SP.op_rows = rows;
+    const bool mixed = opts.precision == CDCC_MIXED;
+    SP.p1cls = mixed ? 0 : choose_p1_class(L, opts.tile_policy);
     if (lambda) SP.u_elems = kmul * L.b_size;
+    // mixed path: slice every operand block once per call
+    int64_t blk_s[CDCC_MAX_IRREP][CDCC_MAX_IRREP], blk_sc[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
+    int blk_kp[CDCC_MAX_IRREP];
+    for (int gP = 0; gP < h; ++gP) blk_kp[gP] = kmul * ((nc[gP] + 15) / 16 * 16);
+    for (int gP = 0; gP < h; ++gP)
+      for (int ga = 0; ga < h; ++ga) {
+        blk_s[gP][ga] = SP.slice_u16;
+        blk_sc[gP][ga] = SP.scale_rows;
+        const int64_t r = int64_t(nv[ga]) * nv[ga ^ gP];
+        if (!mixed || nc[gP] == 0 || r == 0) continue;
+        SliceJob J{};
+        J.sys = s;
+        J.rows = int(r);
+        J.np = nc[gP];
+        J.halves = kmul;
+        J.Kp = blk_kp[gP];
+        J.src_off = kmul * L.b_off[gP][ga];
+        J.dst_off = SP.slice_u16;
+        J.scale_off = SP.scale_rows;
+        const int jid = int(slicejobs.size());
+        slicejobs.push_back(J);
+        for (int q = 0; q < r; ++q) slicerows.push_back(int2{jid, q});
+        SP.slice_u16 += r * J.Kp * 4;
+        SP.scale_rows += r;
+      }
 
     int ij_off[CDCC_MAX_IRREP], vv_off[CDCC_MAX_IRREP], vvf_off[CDCC_MAX_IRREP];
     int64_t vv_sb[CDCC_MAX_IRREP][CDCC_MAX_IRREP], oo_sb[CDCC_MAX_IRREP];
@@ -370,26 +387,6 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           dressjobs.push_back(D);
           for (int a = 0; a < nv[ga]; ++a) dressrows.push_back(int2{jid, a});
         }
-    // mixed path: row slicing of the operand and of the packed amplitudes
-    if (opts.precision == CDCC_MIXED) {
-      for (int gP = 0; gP < h; ++gP)
-        for (int ga = 0; ga < h; ++ga) {
-          const int gc = ga ^ gP;
-          const int64_t r = int64_t(nv[ga]) * nv[gc];
-          if (nc[gP] == 0 || r == 0) continue;
-          SliceJob J{};
-          J.sys = s;
-          J.rows = int(r);
-          J.K = kmul * nc[gP];
-          J.which = 0;
-          J.src_off = kmul * L.b_off[gP][ga];
-          J.dst_off = kmul * L.b_off[gP][ga];
-          J.scale_off = 0;  // filled below
-          J.ld_src = J.K;
-          J.ld_dst = J.K;
-          slicejobs.push_back(J);
-        }
-    }
 
     // column groups
     for (int G = 0; G < h; ++G) {
@@ -455,7 +452,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           R.region = nrows * g.ncols;
           R.p2cls = n_ij > 64 ? 1 : 0;
           // assembly GEMMs
-          const int bm = kP1BM[SP.p1cls];
+          const int bm = mixed ? kMixBM[SP.p1cls] : kP1BM[SP.p1cls];
           for (int gc = 0; gc < h; ++gc) {
             if (!valid[gc]) continue;
             const int gd = gc ^ G, gP = ga ^ gc;
@@ -481,8 +478,12 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
               d.xrow0 = int(xrow0[gc]);
               d.aoff = kmul * L.b_off[gP][ga] + int64_t(as) * vc * K;
               d.boff = kmul * L.b_off[gP][gb];
-              d.ooff = kmul * L.b_off[gP][ga];
-              d.boff_blk = kmul * L.b_off[gP][gb];
+              d.Kp = blk_kp[gP];
+              d.kneg_blk = (lambda && dressed) ? blk_kp[gP] / 32 : blk_kp[gP] / 16;
+              d.a_soff = blk_s[gP][ga] + int64_t(as) * vc * d.Kp * 4;
+              d.b_soff = blk_s[gP][gb];
+              d.a_scoff = blk_sc[gP][ga] + int64_t(as) * vc;
+              d.b_scoff = blk_sc[gP][gb];
               R.descs.push_back(d);
             }
           }
@@ -510,7 +511,6 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     // gather tiles by class
     std::vector<std::vector<std::pair<int64_t, Tile>>> t1(3), t2(2);
     int64_t xo = 0;
-    const int desc_first = int(p1.size());
     for (size_t k = gi; k < gj; ++k) {
       GroupRec &R = groups[k];
       R.g.xoff = xo;
@@ -524,11 +524,12 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           for (int b = 0; b < tn; ++b) t2[c2].push_back({int64_t(R.g.ktab_len) + 1, Tile{gid, a, b, c2}});
       }
       const int c1 = P.sys[R.sys].p1cls;
+      const bool mixed = P.precision == CDCC_MIXED;
       for (P1Desc d : R.descs) {
         d.xoff = R.g.xoff;
         const int did = int(p1.size());
         p1.push_back(d);
-        const int bm = kP1BM[c1], bn = kP1BN[c1];
+        const int bm = mixed ? kMixBM[c1] : kP1BM[c1], bn = mixed ? kMixBN[c1] : kP1BN[c1];
         const int tm = (d.M + bm - 1) / bm, tn = (d.N + bn - 1) / bn;
         for (int a = 0; a < tm; ++a)
           for (int b = 0; b < tn; ++b) {
@@ -542,7 +543,6 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           }
       }
     }
-    B.p1_desc_range = {{desc_first, int(p1.size())}};
     P.xbuf_elems = std::max(P.xbuf_elems, xo);
     for (int c = 0; c < 3; ++c) {
       auto &v = t1[c];
@@ -552,7 +552,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
       l.cls = c;
       l.start = int(p1tiles.size());
       l.count = int(v.size());
-      l.grid = std::min<int>(l.count, c == 2 ? 512 : 1024);
+      l.grid = std::min<int>(l.count, (c == 2 || P.precision == CDCC_MIXED) ? 512 : 1024);
       for (auto &e : v) p1tiles.push_back(e.second);
       B.p1.push_back(l);
     }
@@ -610,7 +610,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
 // Workspace layout of one call.
 struct WsLayout {
   int64_t counters = 0, sysptrs = 0, xbuf = 0, total = 0;
-  std::vector<int64_t> th, u;
+  std::vector<int64_t> th, u, sl, sc;
 };
 
 WsLayout ws_layout(const Plan &P) {
@@ -624,11 +624,17 @@ WsLayout ws_layout(const Plan &P) {
   o = align_up(o + P.xbuf_elems * 8);
   W.th.resize(P.nsys);
   W.u.resize(P.nsys);
+  W.sl.resize(P.nsys);
+  W.sc.resize(P.nsys);
   for (int s = 0; s < P.nsys; ++s) {
     W.th[s] = o;
     o = align_up(o + P.sys[s].th_elems * 8);
     W.u[s] = o;
     o = align_up(o + P.sys[s].u_elems * 8);
+    W.sl[s] = o;
+    o = align_up(o + P.sys[s].slice_u16 * 2);
+    W.sc[s] = o;
+    o = align_up(o + P.sys[s].scale_rows * 8);
   }
   W.total = o;
   return W;
@@ -726,7 +732,6 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
   if (popts) opts = *popts;
   if (opts.precision != CDCC_FP64 && opts.precision != CDCC_MIXED) return CDCC_EINVAL;
   if (opts.tile_policy < 0 || opts.tile_policy > 3) return CDCC_EINVAL;
-  if (opts.precision == CDCC_MIXED) return CDCC_EUNSUPPORTED;  // split-BF16 kernels not wired in yet
   int dressed = 0;
   int rc = validate(nsys, probs, lambda, &dressed);
   if (rc != CDCC_OK) return rc;
@@ -761,6 +766,8 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
     q.B = p.B;
     q.Bvo = p.Bvo;
     q.t1 = p.t1;
+    q.slices = reinterpret_cast<uint16_t *>(base + W.sl[s]);
+    q.rowscale = reinterpret_cast<double *>(base + W.sc[s]);
     hs[s] = q;
   }
   SysPtrs *dsp = reinterpret_cast<SysPtrs *>(base + W.sysptrs);
@@ -775,6 +782,10 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
     Span sp(0, P->ndressrows > 0, stream);
     HIPCHK(launch_dress(P->dressjobs, P->dressrows, P->ndressrows, dsp, stream));
   }
+  if (P->precision == CDCC_MIXED) {
+    Span sp(5, P->nslicerows > 0, stream);
+    HIPCHK(launch_slice(P->slicejobs, P->slicerows, P->nslicerows, dsp, stream));
+  }
   {
     Span sp(1, P->npackrows > 0, stream);
     HIPCHK(launch_pack(P->packjobs, P->packrows, P->npackrows, dsp, P->ijtab, P->vvtab, stream));
@@ -783,9 +794,14 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
   for (const BatchPlan &B : P->batches) {
     {
       Span sp(2, int(B.p1.size()), stream);
-      for (const Launch &l : B.p1)
-        HIPCHK(launch_assemble_f64(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.count, counters + ci++, dsp, xbuf,
-                                   stream));
+      for (const Launch &l : B.p1) {
+        if (P->precision == CDCC_MIXED)
+          HIPCHK(launch_assemble_mixed(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.count, counters + ci++, dsp,
+                                       xbuf, stream));
+        else
+          HIPCHK(launch_assemble_f64(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.count, counters + ci++, dsp, xbuf,
+                                     stream));
+      }
     }
     {
       Span sp(3, int(B.p2.size()), stream);

@@ -19,6 +19,9 @@ namespace cdcc {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// MFMA f64 16x16x4 lane mapping (gfx950): A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k, result register r of lane l is D[l/16 + 4r][l%16].
+
 __global__ void fill_int_kernel(int *p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
+          const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * r;
           const int n = n0 + wn * WN + j * 16 + (lane & 15);
           if (m >= D.M || n >= D.N) continue;
           const int am = m / D.vc, c = m - am * D.vc;
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
+          const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * r;
           const int n = n0 + wn * WN + j * 16 + (lane & 15);
           if (m >= g.n_ij || n >= g.ncols) continue;
           const int4 ij = ijtab[g.ij_off + m];

@@ -21,9 +21,6 @@ struct SysPtrs {
   const double *t1;      // optional singles (Lambda)
   uint16_t *slices;      // workspace: BF16 slices of the assembly operand (mixed path)
   double *rowscale;      // workspace: per-row power-of-two scales of the operand (mixed path)
-  uint16_t *thslices;    // workspace: BF16 slices of the packed amplitudes (mixed path)
-  double *thscale;       // workspace: per-row scales of the packed amplitudes (mixed path)
-  double *colnorm;       // workspace: Schwarz bound of each (a,b) column (mixed path)
 };
 
 // Packing of X into the +/- halves for one (system, pair irrep G).
@@ -45,13 +42,15 @@ struct P1Desc {
   int32_t ga0;         // first a of the owning column group (column numbering)
   int32_t tri;         // Ga == Gb: only b <= a is stored
   int32_t ldx, xrow0;  // X region row length; first region row of this Gc block
-  int32_t pad0, pad1;
+  int32_t Kp;          // mixed path: padded K of a sliced row (multiple of 16)
+  int32_t kneg_blk;    // mixed path: first 16-wide K block negated on the right
   int64_t aoff;        // element offset of operand row (a_first, c=0)
   int64_t boff;        // element offset of operand row (b=0, d=0) of block (GP, Gb)
   int64_t xoff;        // element offset of the group's X region in the batch buffer
-  int64_t ooff;        // element offset of the block (GP, Ga) in the slice/scale buffers
-  int64_t boff_blk;    // element offset of block (GP, Gb) in the slice/scale buffers
-  int64_t colnorm_off; // offset of this group's column bounds (mixed path)
+  int64_t a_soff;      // mixed path: uint16 offset of sliced row (a_first, c=0)
+  int64_t b_soff;      // mixed path: uint16 offset of sliced row (0, 0) of block (GP, Gb)
+  int64_t a_scoff;     // mixed path: row-scale index of row (a_first, c=0)
+  int64_t b_scoff;     // mixed path: row-scale index of row (0, 0) of block (GP, Gb)
 };
 
 // One column group: the (a,b) pairs with a in [a0, a0+na) of sub-block (Ga, Gb)
@@ -66,7 +65,6 @@ struct P2Group {
   int64_t xoff;        // X region in the batch buffer
   int64_t th_off;      // tauhat(+) offset; (-) at th_off + n_ij * th_ld
   int64_t r_off;       // amp_off[G]
-  int64_t ths_off;     // mixed path: offset of this (sys,G) in the sliced tauhat buffer
 };
 
 // Per-row data of the pair-energy reduction.
@@ -90,12 +88,15 @@ struct DressJob {
   int64_t t1_off;            // t1 block Ge: [m][e]
 };
 
-// Slicing of one operand block (mixed path): rows x K.
+// Slicing of one operand block (mixed path): rows of length K = halves * np
+// (the Lambda stack has two halves), written as Kp = halves * roundup(np, 16)
+// padded K, 4 BF16 slices per element.
 struct SliceJob {
-  int32_t sys, rows, K, which;   // which = 0: assembly operand, 1: tauhat(+), 2: tauhat(-)
-  int64_t src_off, dst_off;      // element offsets (source doubles, destination slice units)
-  int64_t scale_off;             // row-scale offset
-  int32_t ld_src, ld_dst, pad0, pad1;
+  int32_t sys, rows, np, halves;
+  int32_t Kp, pad0, pad1, pad2;
+  int64_t src_off;     // element offset of row 0 in the operand
+  int64_t dst_off;     // uint16 offset of row 0 in the slice buffer
+  int64_t scale_off;   // row-scale index of row 0
 };
 
 }  // namespace cdcc

@@ -149,3 +149,53 @@ def test_t2_d2h_large_sampled_fp64(gpu_lib):
         worst = max(worst, abs(Rb[(G, gi, ga)][i, j, a, b] - ref) / scale)
         assert Rb[(G, gi, ga)][i, j, a, b] == Rb[(G, gj, gb)][j, i, b, a]
     assert worst <= FP64_TOL, worst
+
+
+# ---------------------------------------------------------------- mixed path
+MIXED_TOL = 1e-7      # normwise relative
+PAIR_TOL = 1e-8       # Eh, absolute
+
+
+def _pair_energy_err(d, prob, ref):
+    lay = OracleLayout(prob["sym"])
+    e_ref = O.pair_energies_full(lay.full_amp(prob["X"]), lay.full_amp(ref))
+    e_got = d["pair_energy"].cpu().numpy().reshape(e_ref.shape)
+    return float(np.max(np.abs(e_got - e_ref)))
+
+
+@pytest.mark.parametrize("name,spec", SMALL)
+@pytest.mark.parametrize("kind", ["t2", "lambda"])
+def test_mixed_small(gpu_lib, name, spec, kind):
+    prob = problem(S.sym_custom(*spec), seed=9, kind=kind, symmetric_B=False)
+    d = device_problem(gpu_lib, prob, want_energy=True)
+    run(gpu_lib, d, kind=kind, precision="mixed")
+    ref = oracle_result(prob)
+    _check(blocks(d), ref, MIXED_TOL, name)
+    assert _pair_energy_err(d, prob, ref) <= PAIR_TOL
+
+
+@pytest.mark.parametrize("wl", ["c1_small", "d2h_medium_A", "d2h_medium_B"])
+@pytest.mark.parametrize("kind", ["t2", "lambda"])
+def test_mixed_named_workloads(gpu_lib, wl, kind):
+    sym = {"c1_small": S.sym_c1_small(), "d2h_medium_A": S.sym_d2h_medium("A"),
+           "d2h_medium_B": S.sym_d2h_medium("B")}[wl]
+    prob = problem(sym, seed=0, kind=kind)
+    d = device_problem(gpu_lib, prob, want_energy=True)
+    run(gpu_lib, d, kind=kind, precision="mixed")
+    ref = oracle_result(prob)
+    mx, fro = _check(blocks(d), ref, MIXED_TOL, wl)
+    err_e = _pair_energy_err(d, prob, ref)
+    print(f"{wl} {kind} mixed: max {mx:.2e} fro {fro:.2e} pair-energy {err_e:.2e} Eh")
+    assert err_e <= PAIR_TOL
+
+
+def test_mixed_batched_equal_alone(gpu_lib):
+    syms = S.batch_syms(5, seed=2)
+    probs = [problem(s, seed=k) for k, s in enumerate(syms)]
+    ds = [device_problem(gpu_lib, p) for p in probs]
+    run(gpu_lib, ds, precision="mixed")
+    for p, d in zip(probs, ds):
+        alone = device_problem(gpu_lib, p)
+        run(gpu_lib, alone, precision="mixed")
+        assert np.array_equal(alone["R"].cpu().numpy(), d["R"].cpu().numpy())
+        _check(blocks(d), oracle_result(p), MIXED_TOL, str(p["sym"]))
