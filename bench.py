@@ -52,9 +52,12 @@ def build_inputs(cdcc, sym, seed=0):
     return pt, pl, dt, dl
 
 
+TILE_POLICY = 0
+
+
 def step(cdcc, dt, dl, precision):
-    cdcc.ladder_t2(dt, precision=precision)
-    cdcc.ladder_lambda(dl, precision=precision)
+    cdcc.ladder_t2(dt, precision=precision, tile_policy=TILE_POLICY)
+    cdcc.ladder_lambda(dl, precision=precision, tile_policy=TILE_POLICY)
 
 
 def accuracy(cdcc, pt, pl, dt, dl, precision):
@@ -138,6 +141,9 @@ def main():
     ap.add_argument("--precision", default="all", choices=["all", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle accuracy gate")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--tile-policy", type=int, default=0, help="0 = tile table, 1..3 force a tile class")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ladder library runs on a single MI355X "
@@ -147,6 +153,15 @@ def main():
     import torch
     import paper_2512_21909_amd as cdcc
     cdcc.require_gpu()
+    global TILE_POLICY
+    TILE_POLICY = args.tile_policy
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sym, wdesc = workload(args.workload)
     pt, pl, dt, dl = build_inputs(cdcc, sym)
     lay = dt["layout"]

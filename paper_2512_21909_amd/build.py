@@ -23,7 +23,10 @@ ARCH = "gfx950"
 # Packed-FP32 instructions are switched off for all device code.
 DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                "-munsafe-fp-atomics", "-ffp-contract=fast"]
+                "-munsafe-fp-atomics", "-ffp-contract=fast",
+                # keep MFMA accumulators in VGPRs: avoids an AGPR<->VGPR copy of
+                # every accumulator on each K step of the main loops
+                "-mllvm", "-amdgpu-mfma-vgpr-form"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 
 

@@ -27,16 +27,18 @@ hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s);
 hipError_t launch_pack(const PackJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, const int4 *ijtab,
                        const int4 *vvtab, hipStream_t s);
 hipError_t launch_dress(const DressJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s);
-hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Tile *tiles, int ntiles, int *counter,
-                               const SysPtrs *sp, double *xbuf, hipStream_t s);
-hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, int ntiles, int *counter,
+hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q,
+                               int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
+hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,
                                const SysPtrs *sp, const double *xbuf, const int4 *ktab, const int4 *ijtab,
                                const int4 *vvtab, hipStream_t s);
+int occupancy_f64(int which, int cls);
 hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s);
 // mixed path (kernels_mixed.hip)
 hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s);
-hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, int ntiles, int *counter,
-                                 const SysPtrs *sp, double *xbuf, hipStream_t s);
+hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q,
+                                 int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
+int occupancy_mixed(int cls);
 }  // namespace cdcc
 
 using namespace cdcc;
@@ -49,13 +51,14 @@ inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a 
 // P1 (assembly) tile classes and P2 (contraction) tile classes.
 constexpr int kP1BM[3] = {64, 128, 128};
 constexpr int kP1BN[3] = {64, 64, 128};
-constexpr int kMixBM[2] = {64, 128};   // mixed path assembly tiles
-constexpr int kMixBN[2] = {128, 64};
+constexpr int kMixBM[3] = {64, 128, 128};   // mixed path assembly tiles
+constexpr int kMixBN[3] = {128, 64, 128};
 constexpr int kP2BM[2] = {64, 128};
 constexpr int kP2BN[2] = {64, 64};
 
 struct Launch {
   int cls = 0, start = 0, count = 0, grid = 0;
+  Queues q{};
 };
 struct BatchPlan {
   std::vector<Launch> p1, p2;
@@ -120,6 +123,7 @@ struct Workspace {
 };
 
 std::mutex g_mu;
+int g_num_cu = 256;
 
 // Optional event timing of kernel classes (see cdcc_timing_enable).
 struct TimedSpan {
@@ -289,7 +293,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     const int32_t *no = L.sym.nocc, *nv = L.sym.nvir, *nc = L.sym.ncd;
     const int kmul = (lambda && dressed) ? 2 : 1;
     const bool mixed = opts.precision == CDCC_MIXED;
-    SP.p1cls = mixed ? 0 : choose_p1_class(L, opts.tile_policy);
+    SP.p1cls = mixed ? (opts.tile_policy >= 1 ? opts.tile_policy - 1 : 0) : choose_p1_class(L, opts.tile_policy);
     if (lambda) SP.u_elems = kmul * L.b_size;
     // mixed path: slice every operand block once per call
     int64_t blk_s[CDCC_MAX_IRREP][CDCC_MAX_IRREP], blk_sc[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
@@ -510,6 +514,28 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     BatchPlan B;
     // gather tiles by class
     std::vector<std::vector<std::pair<int64_t, Tile>>> t1(3), t2(2);
+    // deal chunks of consecutive tiles round-robin to the 8 XCD queues
+    auto emit = [&](std::vector<std::pair<int64_t, Tile>> &v, int chunk, int cls, int occ,
+                    std::vector<Tile> &out, std::vector<Launch> &launches) {
+      if (v.empty()) return;
+      std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+      std::vector<std::vector<Tile>> qs(8);
+      for (size_t i = 0; i < v.size(); ++i) qs[(i / chunk) % 8].push_back(v[i].second);
+      Launch l;
+      l.cls = cls;
+      l.start = int(out.size());
+      l.count = int(v.size());
+      int acc = 0;
+      for (int x = 0; x < 8; ++x) {
+        l.q.qb[x] = acc;
+        for (const Tile &t : qs[x]) out.push_back(t);
+        acc += int(qs[x].size());
+      }
+      l.q.qb[8] = acc;
+      const int cap = std::max(8, g_num_cu * std::max(occ, 1));
+      l.grid = std::min(cap, (l.count + 7) / 8 * 8);
+      launches.push_back(l);
+    };
     int64_t xo = 0;
     for (size_t k = gi; k < gj; ++k) {
       GroupRec &R = groups[k];
@@ -531,50 +557,33 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
         p1.push_back(d);
         const int bm = mixed ? kMixBM[c1] : kP1BM[c1], bn = mixed ? kMixBN[c1] : kP1BN[c1];
         const int tm = (d.M + bm - 1) / bm, tn = (d.N + bn - 1) / bn;
-        for (int a = 0; a < tm; ++a)
-          for (int b = 0; b < tn; ++b) {
-            if (d.tri) {  // skip tiles that lie entirely above the a>=b triangle
-              const int n0 = b * bn, n1 = std::min(d.N, n0 + bn) - 1;
-              const int minb = (n0 / d.nb == n1 / d.nb) ? n0 % d.nb : 0;
-              const int maxa = d.a_first + std::min(d.M - 1, a * bm + bm - 1) / d.vc;
-              if (minb > maxa) continue;
-            }
-            t1[c1].push_back({int64_t(d.K), Tile{did, a, b, c1}});
-          }
+        // 4 x 8 supertiles: neighbours share operand rows in one XCD's L2
+        for (int sa = 0; sa < tm; sa += 4)
+          for (int sb = 0; sb < tn; sb += 8)
+            for (int a = sa; a < std::min(tm, sa + 4); ++a)
+              for (int b = sb; b < std::min(tn, sb + 8); ++b) {
+                if (d.tri) {  // skip tiles that lie entirely above the a>=b triangle
+                  const int n0 = b * bn, n1 = std::min(d.N, n0 + bn) - 1;
+                  const int minb = (n0 / d.nb == n1 / d.nb) ? n0 % d.nb : 0;
+                  const int maxa = d.a_first + std::min(d.M - 1, a * bm + bm - 1) / d.vc;
+                  if (minb > maxa) continue;
+                }
+                t1[c1].push_back({int64_t(d.K), Tile{did, a, b, c1}});
+              }
       }
     }
     P.xbuf_elems = std::max(P.xbuf_elems, xo);
-    for (int c = 0; c < 3; ++c) {
-      auto &v = t1[c];
-      if (v.empty()) continue;
-      std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
-      Launch l;
-      l.cls = c;
-      l.start = int(p1tiles.size());
-      l.count = int(v.size());
-      l.grid = std::min<int>(l.count, (c == 2 || P.precision == CDCC_MIXED) ? 512 : 1024);
-      for (auto &e : v) p1tiles.push_back(e.second);
-      B.p1.push_back(l);
-    }
-    for (int c = 0; c < 2; ++c) {
-      auto &v = t2[c];
-      if (v.empty()) continue;
-      std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
-      Launch l;
-      l.cls = c;
-      l.start = int(p2tiles.size());
-      l.count = int(v.size());
-      l.grid = std::min<int>(l.count, 1024);
-      for (auto &e : v) p2tiles.push_back(e.second);
-      B.p2.push_back(l);
-    }
+    const bool mixedp = P.precision == CDCC_MIXED;
+    for (int c = 0; c < 3; ++c)
+      emit(t1[c], 32, c, mixedp ? occupancy_mixed(c) : occupancy_f64(0, c), p1tiles, B.p1);
+    for (int c = 0; c < 2; ++c) emit(t2[c], 8, c, occupancy_f64(1, c), p2tiles, B.p2);
     P.batches.push_back(std::move(B));
     gi = gj;
   }
   P.np1 = int(p1.size());
   int nl = 0;
   for (auto &b : P.batches) nl += int(b.p1.size() + b.p2.size());
-  P.ncounters = nl;
+  P.ncounters = 8 * nl;
 
   // upload all tables in one allocation
   TableBuilder T;
@@ -680,6 +689,8 @@ int get_plan(int dev, int32_t nsys, const cdcc_problem_t *probs, int lambda, int
     return CDCC_OK;
   }
   auto P = std::make_shared<Plan>();
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) g_num_cu = ncu;
   const int rc = build_plan(nsys, probs, lambda, dressed, opts, cap, *P);
   if (rc != CDCC_OK) return rc;
   if (g_plans.size() > 256) g_plans.clear();
@@ -795,18 +806,17 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
     {
       Span sp(2, int(B.p1.size()), stream);
       for (const Launch &l : B.p1) {
+        int *cnt = counters + 8 * ci++;
         if (P->precision == CDCC_MIXED)
-          HIPCHK(launch_assemble_mixed(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.count, counters + ci++, dsp,
-                                       xbuf, stream));
+          HIPCHK(launch_assemble_mixed(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
         else
-          HIPCHK(launch_assemble_f64(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.count, counters + ci++, dsp, xbuf,
-                                     stream));
+          HIPCHK(launch_assemble_f64(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
       }
     }
     {
       Span sp(3, int(B.p2.size()), stream);
       for (const Launch &l : B.p2)
-        HIPCHK(launch_contract_f64(l.cls, l.grid, P->p2, P->p2tiles + l.start, l.count, counters + ci++, dsp, xbuf,
+        HIPCHK(launch_contract_f64(l.cls, l.grid, P->p2, P->p2tiles + l.start, l.q, counters + 8 * ci++, dsp, xbuf,
                                    P->ktab, P->ijtab, P->vvtab, stream));
     }
   }

@@ -10,10 +10,10 @@
 //            formed while staging; the epilogue unpacks S +/- A into the four
 //            (ij,ab) permutations of R and writes R / D
 //   energy   e_ij = sum_ab (2 X_ij^ab - X_ij^ba) R_ij^ab, fixed-order tree
-// Tiles are pulled from an integer work counter (persistent workgroups).
+// Tiles are pulled from per-XCD integer work queues by persistent workgroups.
 #include <hip/hip_runtime.h>
 
-#include "ladder_types.hpp"
+#include "kernel_common.hpp"
 
 namespace cdcc {
 
@@ -91,54 +91,56 @@ __global__ __launch_bounds__(256) void dress_kernel(const DressJob *__restrict__
 // ---------------------------------------------------------------------------
 // assemble (FP64): X[(c,d),(a,b)] = 1/2 sum_K U[(a,c),K] s_K U[(b,d),K]
 // Tile BM x BN of the (a,c) x (d,b) product, BK = 16, 4 waves in 2x2, each
-// wave (BM/2) x (BN/2) as 16x16 MFMA f64 blocks.  LDS holds [k][row].
+// wave (BM/2) x (BN/2) as 16x16 MFMA f64 blocks.  LDS holds [k][row] (padded
+// by 2 doubles, double-buffered, one barrier per K step).  Out-of-range rows
+// and K are read from a clamped address and zeroed by a select, so the loads
+// are straight-line code.
 // ---------------------------------------------------------------------------
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restrict__ descs,
-                                                           const Tile *__restrict__ tiles, int ntiles,
-                                                           int *__restrict__ counter,
+                                                           const Tile *__restrict__ tiles, Queues Q,
+                                                           int *__restrict__ cnt,
                                                            const SysPtrs *__restrict__ sp,
                                                            double *__restrict__ xbuf) {
   constexpr int BK = 16;
+  constexpr int LA = BM + 2, LB = BN + 2;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int RA = BM / 64, RB = BN / 64;  // row slots per thread
-  __shared__ double As[BK][BM];
-  __shared__ double Bs[BK][BN];
+  __shared__ double As[2][BK][LA];
+  __shared__ double Bs[2][BK][LB];
   __shared__ int s_tile;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = tid >> 2, lk = (tid & 3) * 4;
+  int tries = 0;
 
   for (;;) {
-    if (tid == 0) s_tile = atomicAdd(counter, 1);
-    __syncthreads();
-    const int t = s_tile;
-    __syncthreads();
-    if (t >= ntiles) break;
+    const int t = next_tile(cnt, Q, tries, &s_tile);
+    if (t < 0) break;
     const Tile tl = tiles[t];
     const P1Desc D = descs[tl.desc];
     const double *__restrict__ op = sp[D.sys].opnd;
     const int m0 = tl.tm * BM, n0 = tl.tn * BN;
     const int K = D.K;
 
-    const double *arow[RA];
-    const double *brow[RB];
+    const CDCC_GLOBAL double *arow[RA];
+    const CDCC_GLOBAL double *brow[RB];
+    double am[RA], bmk[RB];  // 1 for a real row, 0 for a padding row
 #pragma unroll
     for (int q = 0; q < RA; ++q) {
       const int m = m0 + lr + 64 * q;
-      arow[q] = m < D.M ? op + D.aoff + int64_t(m) * K : nullptr;
+      am[q] = m < D.M ? 1.0 : 0.0;
+      arow[q] = as_global(op) + D.aoff + int64_t(m < D.M ? m : D.M - 1) * K;
     }
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
       const int n = n0 + lr + 64 * q;
-      if (n < D.N) {
-        const int dd = n / D.nb, b = n - dd * D.nb;
-        brow[q] = op + D.boff + (int64_t(b) * D.vd + dd) * K;
-      } else {
-        brow[q] = nullptr;
-      }
+      bmk[q] = n < D.N ? 1.0 : 0.0;
+      const int nn = n < D.N ? n : D.N - 1;
+      const int dd = nn / D.nb, b = nn - dd * D.nb;
+      brow[q] = as_global(op) + D.boff + (int64_t(b) * D.vd + dd) * K;
     }
 
     d4 acc[FM][FN];
@@ -147,52 +149,59 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
+    // loads are unconditional (clamped index) and masked by a multiply, so
+    // the K loop is one basic block
     double ra[RA][4], rb[RB][4];
     auto gload = [&](int k0) {
 #pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = k0 + lk + e;
+        const bool kin = k < K;
+        const int kc = kin ? k : K - 1;
+        const double ka = kin ? 1.0 : 0.0;
+        const double kb = kin ? (k >= D.kneg ? -1.0 : 1.0) : 0.0;
+#pragma unroll
+        for (int q = 0; q < RA; ++q) ra[q][e] = arow[q][kc] * (am[q] * ka);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) rb[q][e] = brow[q][kc] * (bmk[q] * kb);
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
       for (int q = 0; q < RA; ++q)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = k0 + lk + e;
-          ra[q][e] = (arow[q] && k < K) ? arow[q][k] : 0.0;
-        }
+        for (int e = 0; e < 4; ++e) As[buf][lk + e][lr + 64 * q] = ra[q][e];
 #pragma unroll
       for (int q = 0; q < RB; ++q)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = k0 + lk + e;
-          const double v = (brow[q] && k < K) ? brow[q][k] : 0.0;
-          rb[q][e] = k >= D.kneg ? -v : v;
-        }
+        for (int e = 0; e < 4; ++e) Bs[buf][lk + e][lr + 64 * q] = rb[q][e];
     };
 
+    const int nk = (K + BK - 1) / BK;
     gload(0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < RA; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) As[lk + e][lr + 64 * q] = ra[q][e];
-#pragma unroll
-      for (int q = 0; q < RB; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) Bs[lk + e][lr + 64 * q] = rb[q][e];
-      __syncthreads();
-      if (k0 + BK < K) gload(k0 + BK);
+    lstore(0);
+    __syncthreads();
+    for (int kb = 0; kb < nk; ++kb) {
+      const int cur = kb & 1;
+      // unconditional prefetch (clamped, zeroed past K): no branch, so the
+      // wait for these loads lands after the MFMAs below
+      gload((kb + 1) * BK);
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
         double fa[FM], fb[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) fa[i] = As[kr][wm * WM + i * 16 + (lane & 15)];
+        for (int i = 0; i < FM; ++i) fa[i] = As[cur][kr][wm * WM + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) fb[j] = Bs[kr][wn * WN + j * 16 + (lane & 15)];
+        for (int j = 0; j < FN; ++j) fb[j] = Bs[cur][kr][wn * WN + j * 16 + (lane & 15)];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
       }
+      lstore(cur ^ 1);
+      __syncthreads();
     }
 
     // epilogue: permuted store into the column group's X region
@@ -226,8 +235,8 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
 // ---------------------------------------------------------------------------
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__restrict__ groups,
-                                                           const Tile *__restrict__ tiles, int ntiles,
-                                                           int *__restrict__ counter,
+                                                           const Tile *__restrict__ tiles, Queues Q,
+                                                           int *__restrict__ cnt,
                                                            const SysPtrs *__restrict__ sp,
                                                            const double *__restrict__ xbuf,
                                                            const int4 *__restrict__ ktab,
@@ -247,13 +256,11 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = tid >> 2, lk = (tid & 3) * 4;  // A staging
   const int bk = tid >> 4, bc = (tid & 15) * CB; // B staging
+  int tries = 0;
 
   for (;;) {
-    if (tid == 0) s_tile = atomicAdd(counter, 1);
-    __syncthreads();
-    const int t = s_tile;
-    __syncthreads();
-    if (t >= ntiles) break;
+    const int t = next_tile(cnt, Q, tries, &s_tile);
+    if (t < 0) break;
     const Tile tl = tiles[t];
     const P2Group g = groups[tl.desc];
     const SysPtrs S = sp[g.sys];
@@ -272,30 +279,43 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
         accA[i][j] = d4{0.0, 0.0, 0.0, 0.0};
       }
 
+    const CDCC_GLOBAL double *gthp = as_global(thp);
+    const CDCC_GLOBAL double *gthm = as_global(thm);
+    const CDCC_GLOBAL double *gxr = as_global(xr);
+    const CDCC_GLOBAL int *gkt = as_global(reinterpret_cast<const int *>(kt));  // int4 entries
     double rap[RA][4], ram[RA][4], rbp[CB], rbm[CB];
+    // branch-free staging: clamped indices, masked by a multiply
     auto gload = [&](int k0) {
 #pragma unroll
       for (int q = 0; q < RA; ++q) {
         const int r = m0 + lr + 64 * q;
+        const int rc = r < g.n_ij ? r : g.n_ij - 1;
+        const double rm = r < g.n_ij ? 1.0 : 0.0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int kc = kt[k0 + lk + e].x;
-          const bool ok = r < g.n_ij && kc >= 0;
-          rap[q][e] = ok ? thp[int64_t(r) * g.th_ld + kc] : 0.0;
-          ram[q][e] = ok ? thm[int64_t(r) * g.th_ld + kc] : 0.0;
+          const int kc = gkt[4 * (k0 + lk + e)];
+          const double mk = kc >= 0 ? rm : 0.0;
+          const int64_t off = int64_t(rc) * g.th_ld + (kc >= 0 ? kc : 0);
+          rap[q][e] = gthp[off] * mk;
+          ram[q][e] = gthm[off] * mk;
         }
       }
-      const int4 ke = kt[k0 + bk];
+      const int r1 = gkt[4 * (k0 + bk) + 1], r2 = gkt[4 * (k0 + bk) + 2];
+      const double m1 = r1 >= 0 ? 1.0 : 0.0, m2 = r2 >= 0 ? 1.0 : 0.0;
+      const int64_t o1 = int64_t(r1 >= 0 ? r1 : 0) * g.ldx, o2 = int64_t(r2 >= 0 ? r2 : 0) * g.ldx;
 #pragma unroll
       for (int e = 0; e < CB; ++e) {
         const int n = n0 + bc + e;
-        const double x1 = (ke.y >= 0 && n < g.ncols) ? xr[int64_t(ke.y) * g.ldx + n] : 0.0;
-        const double x2 = (ke.z >= 0 && n < g.ncols) ? xr[int64_t(ke.z) * g.ldx + n] : 0.0;
+        const int nc = n < g.ncols ? n : g.ncols - 1;
+        const double nm = n < g.ncols ? 1.0 : 0.0;
+        const double x1 = gxr[o1 + nc] * (m1 * nm);
+        const double x2 = gxr[o2 + nc] * (m2 * nm);
         rbp[e] = x1 + x2;
         rbm[e] = x1 - x2;
       }
     };
 
+    const int klast = g.ktab_len - BK;
     if (g.ktab_len > 0) gload(0);
     for (int k0 = 0; k0 < g.ktab_len; k0 += BK) {
       __syncthreads();
@@ -312,7 +332,7 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
         Bm[bk][bc + e] = rbm[e];
       }
       __syncthreads();
-      if (k0 + BK < g.ktab_len) gload(k0 + BK);
+      gload(k0 + BK < g.ktab_len ? k0 + BK : klast);  // unconditional (last one redundant)
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
@@ -416,26 +436,41 @@ hipError_t launch_dress(const DressJob *jobs, const int2 *rows, int nrows, const
   return hipGetLastError();
 }
 
-hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Tile *tiles, int ntiles, int *counter,
-                               const SysPtrs *sp, double *xbuf, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q,
+                               int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
   switch (cls) {
-    case 0: assemble_f64_kernel<64, 64><<<grid, 256, 0, s>>>(descs, tiles, ntiles, counter, sp, xbuf); break;
-    case 1: assemble_f64_kernel<128, 64><<<grid, 256, 0, s>>>(descs, tiles, ntiles, counter, sp, xbuf); break;
-    default: assemble_f64_kernel<128, 128><<<grid, 256, 0, s>>>(descs, tiles, ntiles, counter, sp, xbuf); break;
+    case 0: assemble_f64_kernel<64, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    case 1: assemble_f64_kernel<128, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    default: assemble_f64_kernel<128, 128><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, int ntiles, int *counter,
+hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,
                                const SysPtrs *sp, const double *xbuf, const int4 *ktab, const int4 *ijtab,
                                const int4 *vvtab, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
+  if (grid <= 0) return hipSuccess;
   switch (cls) {
-    case 0: contract_f64_kernel<64, 64><<<grid, 256, 0, s>>>(groups, tiles, ntiles, counter, sp, xbuf, ktab, ijtab, vvtab); break;
-    default: contract_f64_kernel<128, 64><<<grid, 256, 0, s>>>(groups, tiles, ntiles, counter, sp, xbuf, ktab, ijtab, vvtab); break;
+    case 0: contract_f64_kernel<64, 64><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab); break;
+    default: contract_f64_kernel<128, 64><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab); break;
   }
   return hipGetLastError();
+}
+
+// Resident workgroups per CU (which: 0 = assemble, 1 = contract).
+int occupancy_f64(int which, int cls) {
+  int n = 0;
+  hipError_t e;
+  if (which == 0) {
+    if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<64, 64>, 256, 0);
+    else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 64>, 256, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 128>, 256, 0);
+  } else {
+    if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<64, 64>, 256, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<128, 64>, 256, 0);
+  }
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s) {

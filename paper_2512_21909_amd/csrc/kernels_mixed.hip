@@ -12,12 +12,13 @@
 // The FP64 total is finally scaled by sigma_x sigma_y (exact).
 #include <hip/hip_runtime.h>
 
-#include "ladder_types.hpp"
+#include "kernel_common.hpp"
 
 namespace cdcc {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // MFMA f32 32x32x16 bf16 lane mapping (gfx950): A[i][k] in lane i + 32(k/8),
 // element k%8; B[k][j] in lane j + 32(k/8); result register r of lane l is
@@ -77,33 +78,30 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// assemble (mixed): tile BM x BN, 4 waves, each 32 x 64 = two 32x32 blocks.
-// LDS rows hold one 16-wide K block of all four slices (128 B + 16 B pad).
+// assemble (mixed): tile BM x BN, (BM/32) x (BN/64) waves of 32 x 64 (two
+// 32x32 blocks each).  An LDS row holds one 16-wide K block of all four
+// slices (128 B + 16 B pad); double-buffered, one barrier per K block.
 // ---------------------------------------------------------------------------
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void assemble_mixed_kernel(const P1Desc *__restrict__ descs,
-                                                             const Tile *__restrict__ tiles, int ntiles,
-                                                             int *__restrict__ counter,
-                                                             const SysPtrs *__restrict__ sp,
-                                                             double *__restrict__ xbuf) {
+__global__ __launch_bounds__(64 * (BM / 32) * (BN / 64)) void assemble_mixed_kernel(
+    const P1Desc *__restrict__ descs, const Tile *__restrict__ tiles, Queues Q, int *__restrict__ cnt,
+    const SysPtrs *__restrict__ sp, double *__restrict__ xbuf) {
   constexpr int WAVES_N = BN / 64, WAVES_M = BM / 32;
-  static_assert(WAVES_M * WAVES_N == 4, "4 waves of 32x64");
+  constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int ROWB = 144;                    // bytes per LDS row
-  constexpr int CHUNKS = (BM + BN) * 8;        // 16-byte chunks per K block
-  constexpr int CPT = CHUNKS / 256;            // chunks per thread
-  static_assert(CHUNKS % 256 == 0, "chunk split");
-  __shared__ __attribute__((aligned(16))) unsigned char lds[(BM + BN) * ROWB];
+  constexpr int CPT = (BM + BN) * 8 / NT;      // 16-byte chunks per thread per K block
+  constexpr int QA = BM * 8 / NT;              // the first QA chunks of a thread are A rows
+  static_assert((BM + BN) * 8 % NT == 0 && BM * 8 % NT == 0, "chunk split");
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][(BM + BN) * ROWB];
   __shared__ int s_tile;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+  int tries = 0;
 
   for (;;) {
-    if (tid == 0) s_tile = atomicAdd(counter, 1);
-    __syncthreads();
-    const int t = s_tile;
-    __syncthreads();
-    if (t >= ntiles) break;
+    const int t = next_tile(cnt, Q, tries, &s_tile);
+    if (t < 0) break;
     const Tile tl = tiles[t];
     const P1Desc D = descs[tl.desc];
     const SysPtrs S = sp[D.sys];
@@ -111,25 +109,22 @@ __global__ __launch_bounds__(256) void assemble_mixed_kernel(const P1Desc *__res
     const int nkb = D.Kp / 16;
     const int64_t rowstride = int64_t(D.Kp) * 4;  // uint16 per sliced row
 
-    // source pointer and sign of every staged chunk
-    const uint4 *src[CPT];
-    bool neg[CPT];
+    // source of every staged chunk (clamped row) and whether it is real
+    const CDCC_GLOBAL u32x4 *src[CPT];
+    bool ok[CPT];
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
-      const int c = tid + 256 * q;
-      const int r = c >> 3, part = c & 7;
-      src[q] = nullptr;
-      neg[q] = false;
-      if (r < BM) {
+      const int r = (tid >> 3) + (NT / 8) * q, part = tid & 7;
+      if (q < QA) {
         const int m = m0 + r;
-        if (m < D.M) src[q] = reinterpret_cast<const uint4 *>(S.slices + D.a_soff + int64_t(m) * rowstride) + part;
+        ok[q] = m < D.M;
+        src[q] = as_global(reinterpret_cast<const u32x4 *>(S.slices + D.a_soff + int64_t(ok[q] ? m : D.M - 1) * rowstride)) + part;
       } else {
         const int n = n0 + (r - BM);
-        if (n < D.N) {
-          const int dd = n / D.nb, b = n - dd * D.nb;
-          src[q] = reinterpret_cast<const uint4 *>(S.slices + D.b_soff + (int64_t(b) * D.vd + dd) * rowstride) + part;
-          neg[q] = true;
-        }
+        ok[q] = n < D.N;
+        const int nn = ok[q] ? n : D.N - 1;
+        const int dd = nn / D.nb, b = nn - dd * D.nb;
+        src[q] = as_global(reinterpret_cast<const u32x4 *>(S.slices + D.b_soff + (int64_t(b) * D.vd + dd) * rowstride)) + part;
       }
     }
 
@@ -143,21 +138,23 @@ __global__ __launch_bounds__(256) void assemble_mixed_kernel(const P1Desc *__res
       for (int r = 0; r < 16; ++r) tot[j][r] = 0.0;
     }
 
-    uint4 pre[CPT];
-    auto gload = [&](int kb) {
+    u32x4 pre[CPT];
+    auto gload = [&](int kbr) {
+      const int kb = kbr < nkb ? kbr : nkb - 1;  // clamped: the last prefetch is redundant
+      const unsigned flip = kb >= D.kneg_blk ? 0x80008000u : 0u;
 #pragma unroll
       for (int q = 0; q < CPT; ++q) {
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (src[q]) {
-          v = src[q][int64_t(kb) * 8];
-          if (neg[q] && kb >= D.kneg_blk) {
-            v.x ^= 0x80008000u;
-            v.y ^= 0x80008000u;
-            v.z ^= 0x80008000u;
-            v.w ^= 0x80008000u;
-          }
-        }
+        u32x4 v = src[q][int64_t(kb) * 8];
+        if (q >= QA) v ^= flip;
+        v &= ok[q] ? 0xffffffffu : 0u;
         pre[q] = v;
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int r = (tid >> 3) + (NT / 8) * q;
+        *reinterpret_cast<u32x4 *>(&lds[buf][r * ROWB + (tid & 7) * 16]) = pre[q];
       }
     };
     auto flush = [&]() {
@@ -170,45 +167,46 @@ __global__ __launch_bounds__(256) void assemble_mixed_kernel(const P1Desc *__res
       }
     };
 
-    if (nkb > 0) gload(0);
-    for (int kb = 0; kb < nkb; ++kb) {
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int c = tid + 256 * q;
-        *reinterpret_cast<uint4 *>(lds + (c >> 3) * ROWB + (c & 7) * 16) = pre[q];
-      }
-      __syncthreads();
-      if (kb + 1 < nkb) gload(kb + 1);
-      const int arow = wm * 32 + (lane & 31);
-      const int koff = (lane >> 5) * 16;
-      bf8 a[4], b[2][4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        a[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(lds + arow * ROWB + s * 32 + koff));
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int brow = BM + wn * 64 + j * 32 + (lane & 31);
+    if (nkb > 0) {
+      gload(0);
+      lstore(0);
+    }
+    __syncthreads();
+    const int arow = wm * 32 + (lane & 31);
+    const int koff = (lane >> 5) * 16;
+    // chunks of 16 K blocks (256 K); the inner loop is one basic block
+    for (int kc = 0; kc < nkb; kc += 16) {
+      const int kend = kc + 16 < nkb ? kc + 16 : nkb;
+      for (int kb = kc; kb < kend; ++kb) {
+        const unsigned char *L = lds[kb & 1];
+        gload(kb + 1);
+        bf8 a[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-          b[j][s] = __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(lds + brow * ROWB + s * 32 + koff));
-      }
+          a[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + arow * ROWB + s * 32 + koff));
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        acc0[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][0], acc0[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][1], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[j][0], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][2], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[j][1], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[j][0], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[j][3], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[j][2], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[j][1], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[j][0], acc1[j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) {
+          const int brow = BM + wn * 64 + j * 32 + (lane & 31);
+          bf8 b[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            b[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + brow * ROWB + s * 32 + koff));
+          acc0[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], acc0[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[3], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[2], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[1], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[0], acc1[j], 0, 0, 0);
+        }
+        lstore((kb + 1) & 1);
+        __syncthreads();
       }
-      if ((kb & 15) == 15) flush();  // 256 K: keep the leading accumulator exact
+      flush();  // 256 K: keep the leading accumulator exact
     }
-    flush();
 
     // epilogue: scale and permuted store (same numbering as the FP64 path)
 #pragma unroll
@@ -238,14 +236,24 @@ hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const
   return hipGetLastError();
 }
 
-hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, int ntiles, int *counter,
-                                 const SysPtrs *sp, double *xbuf, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  if (cls == 0)
-    assemble_mixed_kernel<64, 128><<<grid, 256, 0, s>>>(descs, tiles, ntiles, counter, sp, xbuf);
-  else
-    assemble_mixed_kernel<128, 64><<<grid, 256, 0, s>>>(descs, tiles, ntiles, counter, sp, xbuf);
+hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q,
+                                 int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  switch (cls) {
+    case 0: assemble_mixed_kernel<64, 128><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    case 1: assemble_mixed_kernel<128, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    default: assemble_mixed_kernel<128, 128><<<grid, 512, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+  }
   return hipGetLastError();
+}
+
+int occupancy_mixed(int cls) {
+  int n = 0;
+  hipError_t e;
+  if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 128>, 256, 0);
+  else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 64>, 256, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 128>, 512, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 }  // namespace cdcc

@@ -78,6 +78,14 @@ struct Tile {
   int32_t desc, tm, tn, cls;
 };
 
+// Per-XCD tile queues of one launch: queue x holds tiles [qb[x], qb[x+1]) of
+// the launch's tile list.  Workgroup w runs on XCD w % 8, drains queue w % 8
+// first and then steals from the others, so every workgroup ends.
+struct Queues {
+  int32_t qb[9];
+};
+
+
 // Lambda dressing of one (system, GP, Ga) block.
 struct DressJob {
   int32_t sys, va, ve, np;   // rows a, columns e (Ge = Ga ^ GP), Cholesky count
