@@ -29,107 +29,166 @@ sys.path.insert(0, ROOT)
 METRIC = "CD ladder residual TFLOP/s, FP64 vs split-precision at 1e-7; p50/p99 latency"
 PEAK = {"fp64": 78.6, "bf16": 2500.0}  # MI355X dense MFMA, TFLOP/s
 HBM_PEAK = 8000.0  # GB/s
+# HBM bytes of one assembly launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (x2.0 and
+# x1.0 copy-kernel calibration), per (workload, path); None until measured for
+# the current kernels.
+TRAFFIC = {}
 
 
 def workload(name):
+    """(description, [(kind, [problem, ...]), ...]): each entry is one library
+    call (a list of several problems is one batched call)."""
     import synth as S
     if name == "d2h_medium":
-        return S.sym_d2h_medium("A"), "d2h_medium: 8 irreps, o=20, v=200, Ncd=1500 (all in the totally symmetric irrep)"
+        sym = S.sym_d2h_medium("A")
+        return ("d2h_medium: 8 irreps, o=20, v=200, Ncd=1500 (all in the totally symmetric irrep); "
+                "T2 + T1-dressed Lambda ladder",
+                [("t2", [S.make_problem(sym, 0, "t2")]), ("lambda", [S.make_problem(sym, 0, "lambda")])])
     if name == "c1_small":
-        return S.sym_c1_small(), "c1_small: 1 irrep, o=8, v=40, Ncd=300"
+        sym = S.sym_c1_small()
+        return ("c1_small: 1 irrep, o=8, v=40, Ncd=300; T2 + T1-dressed Lambda ladder",
+                [("t2", [S.make_problem(sym, 0, "t2")]), ("lambda", [S.make_problem(sym, 0, "lambda")])])
     if name == "d2h_large":
-        return S.sym_d2h_large(), "d2h_large: 8 irreps, o=40, v=400, Ncd=3000 (even split)"
+        sym = S.sym_d2h_large()
+        return ("d2h_large: 8 irreps, o=40, v=400, Ncd=3000 (even split); T2 ladder",
+                [("t2", [S.make_problem(sym, 0, "t2")])])
+    if name == "batch64":
+        syms = S.batch_syms(64, seed=0)
+        return ("batch64: 64 uneven systems (o 5-20, v 40-160, Ncd 7.5(o+v), 1/2/4/8 irreps) in one batched "
+                "T2 call", [("t2", [S.make_problem(s, k, "t2") for k, s in enumerate(syms)])])
     raise SystemExit(f"unknown workload {name}")
 
 
-def build_inputs(cdcc, sym, seed=0):
-    import synth as S
+def build_inputs(cdcc, entries):
     from tests.gpu_support import device_problem
-    pt = S.make_problem(sym, seed=seed, kind="t2")
-    pl = S.make_problem(sym, seed=seed, kind="lambda")
-    dt = device_problem(cdcc, pt, want_delta=True, want_energy=True, nan_fill=False)
-    dl = device_problem(cdcc, pl, want_delta=True, want_energy=True, nan_fill=False)
-    return pt, pl, dt, dl
+    return [(kind, probs, [device_problem(cdcc, p, want_delta=True, want_energy=True, nan_fill=False)
+                           for p in probs]) for kind, probs in entries]
 
 
 TILE_POLICY = 0
 
 
-def step(cdcc, dt, dl, precision):
-    cdcc.ladder_t2(dt, precision=precision, tile_policy=TILE_POLICY)
-    cdcc.ladder_lambda(dl, precision=precision, tile_policy=TILE_POLICY)
+def step(cdcc, dev, precision):
+    for kind, _, ds in dev:
+        fn = cdcc.ladder_t2 if kind == "t2" else cdcc.ladder_lambda
+        fn(ds, precision=precision, tile_policy=TILE_POLICY)
 
 
-def accuracy(cdcc, pt, pl, dt, dl, precision):
-    """Normwise errors of both ladders against the FP64 oracle, and the
-    pair-energy error (Eh)."""
+def _oracle_flops(p):
+    from oracle.layout import OracleLayout
+    lay = OracleLayout(p["sym"])
+    return sum(2.0 * lay.n_oo[G] * lay.n_vv[G] ** 2 for G in range(lay.h))
+
+
+def accuracy(cdcc, dev, precision, samples=300):
+    """Errors against the FP64 oracle: full comparison (normwise, pair
+    energies) when the oracle is cheap, else sampled elements computed one by
+    one (max error relative to max|R|)."""
     import torch
     import oracle as O
     from oracle.layout import OracleLayout
-    step(cdcc, dt, dl, precision)
+    step(cdcc, dev, precision)
     torch.cuda.synchronize()
     out = {}
-    for tag, p, d in (("t2", pt, dt), ("lambda", pl, dl)):
-        if p["kind"] == "t2":
-            ref = O.t2_ladder_blocks(p["sym"], p["B"], p["X"])
-        else:
-            ref = O.lambda_ladder_blocks(p["sym"], p["B"], p["Bvo"], p["t1"], p["X"])
-        lay = d["layout"]
-        got = lay.unpack_amp(d["R"].cpu().numpy())
-        mx, fro = O.rel_errors(got, ref)
-        ol = OracleLayout(p["sym"])
-        e_ref = O.pair_energies_full(ol.full_amp(p["X"]), ol.full_amp(ref))
-        e_got = d["pair_energy"].cpu().numpy().reshape(e_ref.shape)
-        out[tag] = {"max_rel": mx, "fro_rel": fro, "pair_energy_abs": float(np.max(np.abs(e_got - e_ref)))}
+    rng = np.random.default_rng(2024)
+    for kind, probs, ds in dev:
+        worst = {"max_rel": 0.0, "fro_rel": 0.0, "pair_energy_abs": 0.0}
+        sampled = sum(_oracle_flops(p) for p in probs) > 2e11
+        for p, d in zip(probs, ds):
+            lay = d["layout"]
+            got = lay.unpack_amp(d["R"].cpu().numpy())
+            if not sampled:
+                ref = (O.t2_ladder_blocks(p["sym"], p["B"], p["X"]) if kind == "t2"
+                       else O.lambda_ladder_blocks(p["sym"], p["B"], p["Bvo"], p["t1"], p["X"]))
+                mx, fro = O.rel_errors(got, ref)
+                ol = OracleLayout(p["sym"])
+                e_ref = O.pair_energies_full(ol.full_amp(p["X"]), ol.full_amp(ref))
+                e_got = d["pair_energy"].cpu().numpy().reshape(e_ref.shape)
+                worst["max_rel"] = max(worst["max_rel"], mx)
+                worst["fro_rel"] = max(worst["fro_rel"], fro)
+                worst["pair_energy_abs"] = max(worst["pair_energy_abs"], float(np.max(np.abs(e_got - e_ref))))
+                continue
+            sym, h = p["sym"], p["sym"]["h"]
+            no, nv = sym["nocc"], sym["nvir"]
+            scale = max(float(np.max(np.abs(b))) for b in got.values() if b.size)
+            n = max(8, samples // len(probs))
+            for _ in range(n):
+                G, gi, ga = (int(x) for x in rng.integers(0, h, 3))
+                gj, gb = gi ^ G, ga ^ G
+                if not (no[gi] and no[gj] and nv[ga] and nv[gb]):
+                    continue
+                i, j = int(rng.integers(no[gi])), int(rng.integers(no[gj]))
+                a, b = int(rng.integers(nv[ga])), int(rng.integers(nv[gb]))
+                args = (lay.occ_off[gi] + i, lay.occ_off[gj] + j, lay.vir_off[ga] + a, lay.vir_off[gb] + b)
+                ref = (O.element_t2(sym, p["B"], p["X"], *args) if kind == "t2"
+                       else O.element_lambda(sym, p["B"], p["Bvo"], p["t1"], p["X"], *args))
+                worst["max_rel"] = max(worst["max_rel"], abs(got[(G, gi, ga)][i, j, a, b] - ref) / scale)
+            worst["sampled_elements"] = True
+        out[kind] = worst
     return out
 
 
-def timed(cdcc, dt, dl, precision, steps, warmup):
+def timed(cdcc, dev, precision, steps, warmup):
     import torch
     for _ in range(warmup):
-        step(cdcc, dt, dl, precision)
+        step(cdcc, dev, precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step(cdcc, dt, dl, precision)
+        step(cdcc, dev, precision)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
 
 
-def kernel_times(cdcc, dt, dl, precision, steps):
+def kernel_times(cdcc, dev, precision, steps):
     """Per-class kernel durations from HIP events on the library's stream."""
     import torch
     torch.cuda.synchronize()
     cdcc.timing_read()
     cdcc.timing_enable(True)
     for _ in range(steps):
-        step(cdcc, dt, dl, precision)
+        step(cdcc, dev, precision)
     torch.cuda.synchronize()
     cdcc.timing_enable(False)
     return cdcc.timing_read()
 
 
-def cpu_baseline(pt, pl, flops_step, budget_s=12.0):
+def cpu_baseline(entries, flops_step, budget_s=12.0):
     """The FP64 oracle (NumPy + host BLAS) on the same workload, repeated for
-    a bounded time on the host cores."""
+    a bounded time on the host cores (whole steps while they fit the budget,
+    else the first problems of the first call)."""
     import oracle as O
     try:
         from threadpoolctl import threadpool_info
         cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count())
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
+
+    def run_one(kind, p):
+        if kind == "t2":
+            O.t2_ladder_blocks(p["sym"], p["B"], p["X"])
+        else:
+            O.lambda_ladder_blocks(p["sym"], p["B"], p["Bvo"], p["t1"], p["X"])
+
+    from paper_2512_21909_amd import Layout
     t0 = time.perf_counter()
-    reps = 0
-    while True:
-        O.t2_ladder_blocks(pt["sym"], pt["B"], pt["X"])
-        O.lambda_ladder_blocks(pl["sym"], pl["B"], pl["Bvo"], pl["t1"], pl["X"])
+    done_flops, reps, items = 0.0, 0, 0
+    while time.perf_counter() - t0 < budget_s and reps < 50:
+        for kind, probs in entries:
+            for p in probs:
+                run_one(kind, p)
+                f = Layout(p["sym"]).flops(0 if kind == "t2" else 2)
+                done_flops += sum(f)
+                items += 1
+                if time.perf_counter() - t0 >= budget_s:
+                    break
+            if time.perf_counter() - t0 >= budget_s:
+                break
         reps += 1
-        if time.perf_counter() - t0 >= budget_s or reps >= 50:
-            break
     dt = time.perf_counter() - t0
-    return {"value": flops_step * reps / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{reps} full steps (T2 + dressed Lambda ladder, symmetry-blocked plain FP64 contraction) "
-                      f"in {dt:.1f} s"}
+    return {"value": done_flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{items} ladder evaluations of this workload (symmetry-blocked plain FP64 contraction, "
+                      f"NumPy + host BLAS) in {dt:.1f} s; rate = their algorithmic flops / time"}
 
 
 def main():
@@ -144,6 +203,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--tile-policy", type=int, default=0, help="0 = tile table, 1..3 force a tile class")
+    ap.add_argument("--serving", type=int, default=200,
+                    help="requests of the serving run reported beside the step (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ladder library runs on a single MI355X "
@@ -162,13 +223,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    sym, wdesc = workload(args.workload)
-    pt, pl, dt, dl = build_inputs(cdcc, sym)
-    lay = dt["layout"]
-    f_t2 = lay.flops(0)
-    f_l = lay.flops(2)
-    flops_step = sum(f_t2) + sum(f_l)
-    flops_assemble = f_t2[0] + f_l[0]
+    wdesc, entries = workload(args.workload)
+    dev = build_inputs(cdcc, entries)
+    flops_step = flops_assemble = 0.0
+    for kind, _, ds in dev:
+        for d in ds:
+            f = d["layout"].flops(0 if kind == "t2" else 2)
+            flops_step += sum(f)
+            flops_assemble += f[0]
     print(f"[bench] {wdesc}; F_alg per step {flops_step:.4e} (assembly {flops_assemble:.4e})", file=sys.stderr,
           flush=True)
 
@@ -176,12 +238,12 @@ def main():
     results = {}
     for prec in paths:
         try:
-            acc = None if args.no_check else accuracy(cdcc, pt, pl, dt, dl, prec)
+            acc = None if args.no_check else accuracy(cdcc, dev, prec)
         except cdcc.CdccError as e:
             print(f"[bench] {prec}: unavailable ({e})", file=sys.stderr, flush=True)
             continue
-        sec = timed(cdcc, dt, dl, prec, args.steps, args.warmup)
-        kt = kernel_times(cdcc, dt, dl, prec, args.steps)
+        sec = timed(cdcc, dev, prec, args.steps, args.warmup)
+        kt = kernel_times(cdcc, dev, prec, args.steps)
         gate = 1e-12 if prec == "fp64" else 1e-7
         ok = acc is None or all(a["max_rel"] <= gate and a["fro_rel"] <= gate and
                                 (prec == "fp64" or a["pair_energy_abs"] <= 1e-8) for a in acc.values())
@@ -214,19 +276,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if best == "fp64" else "bf16x4-split/f32-acc/f64-sum",
         "data": "synthetic",
-        "config": {"workload": wdesc, "step": "T2 ladder + T1-dressed Lambda ladder, R/D and pair energies",
-                   "flops_per_step": flops_step, "path": best},
+        "config": {"workload": wdesc, "flops_per_step": flops_step, "path": best},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get((args.workload, best)),
                      "kernel": "assemble (ac|bd) batch", "launches": asm_n, "avg_launch_ms": avg_ms,
                      "flops_per_launch": per_launch_flops},
         "paths": {p: {k: v for k, v in results[p].items() if k != "kernels"} | {"kernels_ms": results[p]["kernels"]}
                   for p in results},
     }
+    if best != "fp64":
+        line["roofline"]["issued_bf16_tflops"] = round(achieved * 10, 3)
+        line["roofline"]["issued_frac"] = round(achieved * 10 / peak, 4)
+    if "fp64" in results:
+        f = results["fp64"]
+        fa_ms, fa_n = f["kernels"].get("assemble", (0.0, 0))
+        fa = flops_assemble * args.steps / max(fa_n, 1) / (fa_ms / max(fa_n, 1) * 1e-3) / 1e12 if fa_ms else 0.0
+        line["roofline_fp64"] = {"bound": "mfma", "achieved": round(fa, 3), "peak": PEAK["fp64"],
+                                 "unit": "TFLOP/s", "frac": round(fa / PEAK["fp64"], 4)}
     if "fp64" in results and "mixed" in results:
         line["mixed_speedup_vs_fp64"] = results["mixed"]["tflops"] / results["fp64"]["tflops"]
+    if args.serving:
+        from paper_2512_21909_amd import serve
+        line["serving"] = serve.measure(best, n_requests=args.serving)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(pt, pl, flops_step)
+        line["cpu_baseline"] = cpu_baseline(entries, flops_step)
     print(json.dumps(line), flush=True)
 
 

@@ -53,8 +53,8 @@ constexpr int kP1BM[3] = {64, 128, 128};
 constexpr int kP1BN[3] = {64, 64, 128};
 constexpr int kMixBM[3] = {64, 128, 128};   // mixed path assembly tiles
 constexpr int kMixBN[3] = {128, 64, 128};
-constexpr int kP2BM[2] = {64, 128};
-constexpr int kP2BN[2] = {64, 64};
+constexpr int kP2BM[3] = {32, 64, 128};
+constexpr int kP2BN[3] = {64, 64, 64};
 
 struct Launch {
   int cls = 0, start = 0, count = 0, grid = 0;
@@ -100,7 +100,10 @@ struct Plan {
   std::vector<BatchPlan> batches;
   int ncounters = 0;
   int64_t xbuf_elems = 0;
+  // captured launch sequences, keyed by the workspace base they were built for
+  std::map<void *, hipGraphExec_t> graphs;
   ~Plan() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
     if (dtab) (void)hipFree(dtab);
   }
 };
@@ -234,8 +237,9 @@ int choose_p1_class(const cdcc_layout_t &L, int policy) {
         const double M = double(nv[ga]) * nv[gc], N = double(nv[gb]) * nv[gd] * (ga == gb ? 0.5 : 1.0);
         for (int c = 0; c < 3; ++c) tiles[c] += std::ceil(M / kP1BM[c]) * std::ceil(N / kP1BN[c]);
       }
-  if (tiles[2] >= 1024) return 2;
-  if (tiles[1] >= 768) return 1;
+  // measured on the 8-irrep o=20/v=200 workload: the 64x64 class (4 waves per
+  // SIMD) beats the larger ones unless there are many more tiles than slots
+  if (tiles[1] >= 8192) return 1;
   return 0;
 }
 
@@ -293,7 +297,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     const int32_t *no = L.sym.nocc, *nv = L.sym.nvir, *nc = L.sym.ncd;
     const int kmul = (lambda && dressed) ? 2 : 1;
     const bool mixed = opts.precision == CDCC_MIXED;
-    SP.p1cls = mixed ? (opts.tile_policy >= 1 ? opts.tile_policy - 1 : 0) : choose_p1_class(L, opts.tile_policy);
+    SP.p1cls = mixed ? (opts.tile_policy >= 1 ? opts.tile_policy - 1 : 1) : choose_p1_class(L, opts.tile_policy);
     if (lambda) SP.u_elems = kmul * L.b_size;
     // mixed path: slice every operand block once per call
     int64_t blk_s[CDCC_MAX_IRREP][CDCC_MAX_IRREP], blk_sc[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
@@ -389,7 +393,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           D.t1_off = L.t1_off[ge];
           const int jid = int(dressjobs.size());
           dressjobs.push_back(D);
-          for (int a = 0; a < nv[ga]; ++a) dressrows.push_back(int2{jid, a});
+          for (int ae = 0; ae < nv[ga] * nv[ge]; ++ae) dressrows.push_back(int2{jid, ae});
         }
 
     // column groups
@@ -454,7 +458,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           g.th_off = th_off[G];
           g.r_off = L.amp_off[G];
           R.region = nrows * g.ncols;
-          R.p2cls = n_ij > 64 ? 1 : 0;
+          R.p2cls = n_ij > 64 ? 2 : (n_ij > 32 ? 1 : 0);  // unified per batch below
           // assembly GEMMs
           const int bm = mixed ? kMixBM[SP.p1cls] : kP1BM[SP.p1cls];
           for (int gc = 0; gc < h; ++gc) {
@@ -513,7 +517,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     }
     BatchPlan B;
     // gather tiles by class
-    std::vector<std::vector<std::pair<int64_t, Tile>>> t1(3), t2(2);
+    std::vector<std::vector<std::pair<int64_t, Tile>>> t1(3), t2(3);
     // deal chunks of consecutive tiles round-robin to the 8 XCD queues
     auto emit = [&](std::vector<std::pair<int64_t, Tile>> &v, int chunk, int cls, int occ,
                     std::vector<Tile> &out, std::vector<Launch> &launches) {
@@ -537,8 +541,13 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
       launches.push_back(l);
     };
     int64_t xo = 0;
+    // one contraction tile class per batch (the largest any group needs): a
+    // second launch of a few tiles would serialise behind the first
+    int c2max = 0;
+    for (size_t k = gi; k < gj; ++k) c2max = std::max(c2max, groups[k].p2cls);
     for (size_t k = gi; k < gj; ++k) {
       GroupRec &R = groups[k];
+      R.p2cls = c2max;
       R.g.xoff = xo;
       xo += align_up(R.region, 32);
       const int gid = int(p2.size());
@@ -576,7 +585,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     const bool mixedp = P.precision == CDCC_MIXED;
     for (int c = 0; c < 3; ++c)
       emit(t1[c], 32, c, mixedp ? occupancy_mixed(c) : occupancy_f64(0, c), p1tiles, B.p1);
-    for (int c = 0; c < 2; ++c) emit(t2[c], 8, c, occupancy_f64(1, c), p2tiles, B.p2);
+    for (int c = 0; c < 3; ++c) emit(t2[c], 8, c, occupancy_f64(1, c), p2tiles, B.p2);
     P.batches.push_back(std::move(B));
     gi = gj;
   }
@@ -738,6 +747,59 @@ int get_workspace(int dev, hipStream_t stream, int64_t bytes, int64_t staging, W
     if ((x) != hipSuccess) return CDCC_EDEVICE; \
   } while (0)
 
+// Every kernel of one evaluation, in order, on stream s.
+int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, hipStream_t stream) {
+  const Plan *P = &Pl;
+  HIPCHK(launch_fill_int(counters, P->ncounters, 0, stream));
+  if (P->lambda) {
+    Span sp(0, P->ndressrows > 0, stream);
+    HIPCHK(launch_dress(P->dressjobs, P->dressrows, P->ndressrows, dsp, stream));
+  }
+  if (P->precision == CDCC_MIXED) {
+    Span sp(5, P->nslicerows > 0, stream);
+    HIPCHK(launch_slice(P->slicejobs, P->slicerows, P->nslicerows, dsp, stream));
+  }
+  {
+    Span sp(1, P->npackrows > 0, stream);
+    HIPCHK(launch_pack(P->packjobs, P->packrows, P->npackrows, dsp, P->ijtab, P->vvtab, stream));
+  }
+  int ci = 0;
+  for (const BatchPlan &B : P->batches) {
+    {
+      Span sp(2, int(B.p1.size()), stream);
+      for (const Launch &l : B.p1) {
+        int *cnt = counters + 8 * ci++;
+        if (P->precision == CDCC_MIXED)
+          HIPCHK(launch_assemble_mixed(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
+        else
+          HIPCHK(launch_assemble_f64(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
+      }
+    }
+    {
+      Span sp(3, int(B.p2.size()), stream);
+      for (const Launch &l : B.p2)
+        HIPCHK(launch_contract_f64(l.cls, l.grid, P->p2, P->p2tiles + l.start, l.q, counters + 8 * ci++, dsp, xbuf,
+                                   P->ktab, P->ijtab, P->vvtab, stream));
+    }
+  }
+  {
+    Span sp(4, P->nejobs > 0, stream);
+    HIPCHK(launch_energy(P->ejobs, P->nejobs, dsp, P->vvfull, stream));
+  }
+  return CDCC_OK;
+}
+
+std::map<int, hipStream_t> g_capture_streams;
+
+hipStream_t capture_stream(int dev) {
+  auto it = g_capture_streams.find(dev);
+  if (it != g_capture_streams.end()) return it->second;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  g_capture_streams[dev] = s;
+  return s;
+}
+
 int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *popts, void *vstream, int lambda) {
   cdcc_opts_t opts{};
   if (popts) opts = *popts;
@@ -788,42 +850,28 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
 
   int *counters = reinterpret_cast<int *>(base + W.counters);
   double *xbuf = reinterpret_cast<double *>(base + W.xbuf);
-  HIPCHK(launch_fill_int(counters, P->ncounters, 0, stream));
-  if (lambda) {
-    Span sp(0, P->ndressrows > 0, stream);
-    HIPCHK(launch_dress(P->dressjobs, P->dressrows, P->ndressrows, dsp, stream));
-  }
-  if (P->precision == CDCC_MIXED) {
-    Span sp(5, P->nslicerows > 0, stream);
-    HIPCHK(launch_slice(P->slicejobs, P->slicerows, P->nslicerows, dsp, stream));
-  }
-  {
-    Span sp(1, P->npackrows > 0, stream);
-    HIPCHK(launch_pack(P->packjobs, P->packrows, P->npackrows, dsp, P->ijtab, P->vvtab, stream));
-  }
-  int ci = 0;
-  for (const BatchPlan &B : P->batches) {
-    {
-      Span sp(2, int(B.p1.size()), stream);
-      for (const Launch &l : B.p1) {
-        int *cnt = counters + 8 * ci++;
-        if (P->precision == CDCC_MIXED)
-          HIPCHK(launch_assemble_mixed(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
-        else
-          HIPCHK(launch_assemble_f64(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
-      }
+  const bool use_graph = !g_timing && env_i64("CDCC_GRAPH", 1) != 0;
+  if (!use_graph) return enqueue_sequence(*P, dsp, counters, xbuf, stream);
+  auto it = P->graphs.find(ws->dev);
+  if (it == P->graphs.end()) {
+    // capture the kernel sequence once per (plan, workspace) on a private stream
+    hipStream_t cap = capture_stream(dev);
+    if (!cap) return CDCC_EDEVICE;
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    const int rc2 = enqueue_sequence(*P, dsp, counters, xbuf, cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &graph);
+    if (rc2 != CDCC_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc2 != CDCC_OK ? rc2 : CDCC_EDEVICE;
     }
-    {
-      Span sp(3, int(B.p2.size()), stream);
-      for (const Launch &l : B.p2)
-        HIPCHK(launch_contract_f64(l.cls, l.grid, P->p2, P->p2tiles + l.start, l.q, counters + 8 * ci++, dsp, xbuf,
-                                   P->ktab, P->ijtab, P->vvtab, stream));
-    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return CDCC_EDEVICE;
+    it = P->graphs.emplace(ws->dev, exec).first;
   }
-  {
-    Span sp(4, P->nejobs > 0, stream);
-    HIPCHK(launch_energy(P->ejobs, P->nejobs, dsp, P->vvfull, stream));
-  }
+  HIPCHK(hipGraphLaunch(it->second, stream));
   return CDCC_OK;
 }
 
@@ -886,6 +934,8 @@ extern "C" int cdcc_release(void) {
   if (hipDeviceSynchronize() != hipSuccess) return CDCC_EDEVICE;
   g_ws.clear();
   g_plans.clear();
+  for (auto &c : g_capture_streams) (void)hipStreamDestroy(c.second);
+  g_capture_streams.clear();
   for (const TimedSpan &t : g_spans) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);

@@ -57,34 +57,35 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackJob *__restrict__ j
 }
 
 // ---------------------------------------------------------------------------
-// dress (Lambda, Appendix A): rows (job, a); for every e in Ge = Ga^GP, P:
+// dress (Lambda, Appendix A): one workgroup per (job, a, e), Ge = Ga^GP,
+// threads along P:
 //   t^P_ea = sum_m t_m^e L^P_am,  U[a][e][P] = B^P_ea - t^P_ea,
 //   U[a][e][np + P] = t^P_ea   (subtracted in the assembly: kneg = np)
-// Without singles (om == 0 or no t1) only the first half is written.
+// Without singles only the first half is written (U = B transposed).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void dress_kernel(const DressJob *__restrict__ jobs,
                                                     const int2 *__restrict__ rows,
-                                                    const SysPtrs *__restrict__ sp,
-                                                    double *__restrict__ ubuf_unused) {
-  (void)ubuf_unused;
+                                                    const SysPtrs *__restrict__ sp) {
   const int2 jr = rows[blockIdx.x];
   const DressJob J = jobs[jr.x];
-  const int a = jr.y;
+  const int a = jr.y / J.ve, e = jr.y - a * J.ve;
   const SysPtrs S = sp[J.sys];
   double *__restrict__ U = const_cast<double *>(S.opnd);
   const bool dressed = S.t1 != nullptr && S.Bvo != nullptr;
   const int kst = dressed ? 2 * J.np : J.np;
-  const int n = J.ve * J.np;
-  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-    const int e = idx / J.np, P = idx - e * J.np;
-    const double bea = S.B[J.b_off + (int64_t(e) * J.va + a) * J.np + P];
+  const CDCC_GLOBAL double *bea = as_global(S.B) + J.b_off + (int64_t(e) * J.va + a) * J.np;
+  double *__restrict__ urow = U + J.u_off + (int64_t(a) * J.ve + e) * kst;
+  if (!dressed) {
+    for (int P = threadIdx.x; P < J.np; P += 256) urow[P] = bea[P];
+    return;
+  }
+  const CDCC_GLOBAL double *lam = as_global(S.Bvo) + J.bvo_off + int64_t(a) * J.om * J.np;
+  const CDCC_GLOBAL double *t1e = as_global(S.t1) + J.t1_off + e;
+  for (int P = threadIdx.x; P < J.np; P += 256) {
     double tea = 0.0;
-    if (dressed)
-      for (int m = 0; m < J.om; ++m)
-        tea += S.t1[J.t1_off + int64_t(m) * J.ve + e] * S.Bvo[J.bvo_off + (int64_t(a) * J.om + m) * J.np + P];
-    double *urow = U + J.u_off + (int64_t(a) * J.ve + e) * kst;
-    urow[P] = bea - tea;
-    if (dressed) urow[J.np + P] = tea;
+    for (int m = 0; m < J.om; ++m) tea += t1e[int64_t(m) * J.ve] * lam[int64_t(m) * J.np + P];
+    urow[P] = bea[P] - tea;
+    urow[J.np + P] = tea;
   }
 }
 
@@ -230,8 +231,9 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
 // contract (FP64): S = tauhat(+) W(+), A = tauhat(-) W(-) over the K table of
 // the group (entries: tauhat column, X rows of (c,d) and (d,c), -1 = absent).
 // Tile BM x BN of (packed ij) x (group columns); 2x2 waves; both products
-// share the staged X rows.  Epilogue writes R (and R/D) at the four
-// permutations (ij,ab), (ij,ba) = S-A, (ji,ab) = S-A, (ji,ba) = S+A.
+// share the staged X rows; double-buffered LDS, one barrier per K step.
+// Epilogue writes R (and R/D) at the four permutations (ij,ab),
+// (ij,ba) = S-A, (ji,ab) = S-A, (ji,ba) = S+A.
 // ---------------------------------------------------------------------------
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__restrict__ groups,
@@ -245,17 +247,19 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int RA = (BM * BK) / (256 * 4);  // A row slots per thread (4 k each)
+  constexpr int EPT = BM * BK / 256;         // A elements per thread (one row, EPT consecutive k)
+  constexpr int TPR = BK / EPT;              // threads per A row
   constexpr int CB = BN / 16;                // B columns per thread (16 threads per k row)
-  static_assert(RA >= 1, "BM too small");
-  __shared__ double Ap[BK][BM], Am[BK][BM];
-  __shared__ double Bp[BK][BN], Bm[BK][BN];
+  constexpr int LA = BM + 2, LB = BN + 2;
+  static_assert(EPT >= 1 && BK % EPT == 0, "A staging");
+  __shared__ double Ap[2][BK][LA], Am[2][BK][LA];
+  __shared__ double Bp[2][BK][LB], Bm[2][BK][LB];
   __shared__ int s_tile;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int lr = tid >> 2, lk = (tid & 3) * 4;  // A staging
-  const int bk = tid >> 4, bc = (tid & 15) * CB; // B staging
+  const int lr = tid / TPR, lk = (tid % TPR) * EPT;  // A staging
+  const int bk = tid >> 4, bc = (tid & 15) * CB;     // B staging
   int tries = 0;
 
   for (;;) {
@@ -264,11 +268,11 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
     const Tile tl = tiles[t];
     const P2Group g = groups[tl.desc];
     const SysPtrs S = sp[g.sys];
-    const double *__restrict__ thp = S.tauhat + g.th_off;
-    const double *__restrict__ thm = thp + int64_t(g.n_ij) * g.th_ld;
-    const double *__restrict__ xr = xbuf + g.xoff;
-    const int4 *__restrict__ kt = ktab + g.ktab_off;
     const int m0 = tl.tm * BM, n0 = tl.tn * BN;
+    const CDCC_GLOBAL double *gthp = as_global(S.tauhat) + g.th_off;
+    const CDCC_GLOBAL double *gthm = gthp + int64_t(g.n_ij) * g.th_ld;
+    const CDCC_GLOBAL double *gxr = as_global(xbuf) + g.xoff;
+    const CDCC_GLOBAL int *gkt = as_global(reinterpret_cast<const int *>(ktab + g.ktab_off));  // int4 entries
 
     d4 accS[FM][FN], accA[FM][FN];
 #pragma unroll
@@ -279,30 +283,30 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
         accA[i][j] = d4{0.0, 0.0, 0.0, 0.0};
       }
 
-    const CDCC_GLOBAL double *gthp = as_global(thp);
-    const CDCC_GLOBAL double *gthm = as_global(thm);
-    const CDCC_GLOBAL double *gxr = as_global(xr);
-    const CDCC_GLOBAL int *gkt = as_global(reinterpret_cast<const int *>(kt));  // int4 entries
-    double rap[RA][4], ram[RA][4], rbp[CB], rbm[CB];
+    const int r = m0 + lr;
+    const int64_t arow = int64_t(r < g.n_ij ? r : g.n_ij - 1) * g.th_ld;
+    const double rm = r < g.n_ij ? 1.0 : 0.0;
+    double rap[EPT], ram[EPT], rbp[CB], rbm[CB];
+    // K-table entries are fetched one stage ahead of the data they index
+    int kcA[EPT], r1B, r2B;
+    auto kload = [&](int k0) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) kcA[e] = gkt[4 * (k0 + lk + e)];
+      r1B = gkt[4 * (k0 + bk) + 1];
+      r2B = gkt[4 * (k0 + bk) + 2];
+    };
     // branch-free staging: clamped indices, masked by a multiply
-    auto gload = [&](int k0) {
+    auto gload = [&]() {
 #pragma unroll
-      for (int q = 0; q < RA; ++q) {
-        const int r = m0 + lr + 64 * q;
-        const int rc = r < g.n_ij ? r : g.n_ij - 1;
-        const double rm = r < g.n_ij ? 1.0 : 0.0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int kc = gkt[4 * (k0 + lk + e)];
-          const double mk = kc >= 0 ? rm : 0.0;
-          const int64_t off = int64_t(rc) * g.th_ld + (kc >= 0 ? kc : 0);
-          rap[q][e] = gthp[off] * mk;
-          ram[q][e] = gthm[off] * mk;
-        }
+      for (int e = 0; e < EPT; ++e) {
+        const int kc = kcA[e];
+        const double mk = kc >= 0 ? rm : 0.0;
+        const int64_t off = arow + (kc >= 0 ? kc : 0);
+        rap[e] = gthp[off] * mk;
+        ram[e] = gthm[off] * mk;
       }
-      const int r1 = gkt[4 * (k0 + bk) + 1], r2 = gkt[4 * (k0 + bk) + 2];
-      const double m1 = r1 >= 0 ? 1.0 : 0.0, m2 = r2 >= 0 ? 1.0 : 0.0;
-      const int64_t o1 = int64_t(r1 >= 0 ? r1 : 0) * g.ldx, o2 = int64_t(r2 >= 0 ? r2 : 0) * g.ldx;
+      const double m1 = r1B >= 0 ? 1.0 : 0.0, m2 = r2B >= 0 ? 1.0 : 0.0;
+      const int64_t o1 = int64_t(r1B >= 0 ? r1B : 0) * g.ldx, o2 = int64_t(r2B >= 0 ? r2B : 0) * g.ldx;
 #pragma unroll
       for (int e = 0; e < CB; ++e) {
         const int n = n0 + bc + e;
@@ -314,38 +318,44 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
         rbm[e] = x1 - x2;
       }
     };
-
-    const int klast = g.ktab_len - BK;
-    if (g.ktab_len > 0) gload(0);
-    for (int k0 = 0; k0 < g.ktab_len; k0 += BK) {
-      __syncthreads();
+    auto lstore = [&](int buf) {
 #pragma unroll
-      for (int q = 0; q < RA; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          Ap[lk + e][lr + 64 * q] = rap[q][e];
-          Am[lk + e][lr + 64 * q] = ram[q][e];
-        }
+      for (int e = 0; e < EPT; ++e) {
+        Ap[buf][lk + e][lr] = rap[e];
+        Am[buf][lk + e][lr] = ram[e];
+      }
 #pragma unroll
       for (int e = 0; e < CB; ++e) {
-        Bp[bk][bc + e] = rbp[e];
-        Bm[bk][bc + e] = rbm[e];
+        Bp[buf][bk][bc + e] = rbp[e];
+        Bm[buf][bk][bc + e] = rbm[e];
       }
-      __syncthreads();
-      gload(k0 + BK < g.ktab_len ? k0 + BK : klast);  // unconditional (last one redundant)
+    };
+
+    const int nk = g.ktab_len / BK;
+    if (nk > 0) {
+      kload(0);
+      gload();
+      lstore(0);
+      kload((nk > 1 ? 1 : 0) * BK);
+    }
+    __syncthreads();
+    for (int kb = 0; kb < nk; ++kb) {
+      const int cur = kb & 1;
+      gload();                                       // stage kb+1 (redundant on the last step)
+      kload((kb + 2 < nk ? kb + 2 : nk - 1) * BK);   // table entries of stage kb+2
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
         double fap[FM], fam[FM], fbp[FN], fbm[FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-          fap[i] = Ap[kr][wm * WM + i * 16 + (lane & 15)];
-          fam[i] = Am[kr][wm * WM + i * 16 + (lane & 15)];
+          fap[i] = Ap[cur][kr][wm * WM + i * 16 + (lane & 15)];
+          fam[i] = Am[cur][kr][wm * WM + i * 16 + (lane & 15)];
         }
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-          fbp[j] = Bp[kr][wn * WN + j * 16 + (lane & 15)];
-          fbm[j] = Bm[kr][wn * WN + j * 16 + (lane & 15)];
+          fbp[j] = Bp[cur][kr][wn * WN + j * 16 + (lane & 15)];
+          fbm[j] = Bm[cur][kr][wn * WN + j * 16 + (lane & 15)];
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -355,6 +365,8 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
             accA[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fam[i], fbm[j], accA[i][j], 0, 0, 0);
           }
       }
+      lstore(cur ^ 1);
+      __syncthreads();
     }
 
     double *__restrict__ R = S.R + g.r_off;
@@ -364,14 +376,14 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
 #pragma unroll
       for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * r;
+        for (int rr = 0; rr < 4; ++rr) {
+          const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * rr;
           const int n = n0 + wn * WN + j * 16 + (lane & 15);
           if (m >= g.n_ij || n >= g.ncols) continue;
           const int4 ij = ijtab[g.ij_off + m];
           const int4 ab = vvtab[g.col_off + n];
-          const double s = accS[i][j][r], a = accA[i][j][r];
-          const double pp = s + a, pm = s - a;
+          const double sv = accS[i][j][rr], av = accA[i][j][rr];
+          const double pp = sv + av, pm = sv - av;
           const int64_t ld = g.ldr;
           const bool oab = ab.x != ab.y, oij = ij.x != ij.y;
           R[int64_t(ij.x) * ld + ab.x] = pp;
@@ -432,7 +444,7 @@ hipError_t launch_pack(const PackJob *jobs, const int2 *rows, int nrows, const S
 
 hipError_t launch_dress(const DressJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
-  dress_kernel<<<nrows, 256, 0, s>>>(jobs, rows, sp, nullptr);
+  dress_kernel<<<nrows, 256, 0, s>>>(jobs, rows, sp);
   return hipGetLastError();
 }
 
@@ -452,7 +464,8 @@ hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const T
                                const int4 *vvtab, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   switch (cls) {
-    case 0: contract_f64_kernel<64, 64><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab); break;
+    case 0: contract_f64_kernel<32, 64><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab); break;
+    case 1: contract_f64_kernel<64, 64><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab); break;
     default: contract_f64_kernel<128, 64><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab); break;
   }
   return hipGetLastError();
@@ -467,7 +480,8 @@ int occupancy_f64(int which, int cls) {
     else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 64>, 256, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 128>, 256, 0);
   } else {
-    if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<64, 64>, 256, 0);
+    if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<32, 64>, 256, 0);
+    else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<64, 64>, 256, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<128, 64>, 256, 0);
   }
   return (e == hipSuccess && n > 0) ? n : 1;

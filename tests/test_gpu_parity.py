@@ -199,3 +199,68 @@ def test_mixed_batched_equal_alone(gpu_lib):
         run(gpu_lib, alone, precision="mixed")
         assert np.array_equal(alone["R"].cpu().numpy(), d["R"].cpu().numpy())
         _check(blocks(d), oracle_result(p), MIXED_TOL, str(p["sym"]))
+
+
+def test_graph_replay_with_new_pointers(gpu_lib):
+    """The captured launch sequence is replayed for new buffers of the same
+    shape: alternating calls on two inputs give each input's own result, and
+    the graph path equals the direct launches bitwise."""
+    import os
+    import torch
+    sym = S.sym_custom([2, 1, 1, 1], [9, 5, 7, 4], [30, 11, 6, 7])
+    probs = [problem(sym, seed=s) for s in (21, 22)]
+    ds = [device_problem(gpu_lib, p, want_energy=True) for p in probs]
+    refs = [oracle_result(p) for p in probs]
+    first = []
+    for rep in range(3):
+        for d, ref in zip(ds, refs):
+            d["R"].fill_(float("nan"))
+            run(gpu_lib, d)
+            _check(blocks(d), ref, FP64_TOL, f"replay {rep}")
+            if rep == 0:
+                first.append(d["R"].cpu().numpy().copy())
+            else:
+                assert np.array_equal(d["R"].cpu().numpy(), first[ds.index(d)])
+    os.environ["CDCC_GRAPH"] = "0"
+    try:
+        for d, f in zip(ds, first):
+            d["R"].fill_(float("nan"))
+            run(gpu_lib, d)
+            assert np.array_equal(d["R"].cpu().numpy(), f)
+    finally:
+        del os.environ["CDCC_GRAPH"]
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_uneven_batch_of_64_systems(gpu_lib, precision):
+    """64 systems (o in [5,20], v in [40,160], N = 7.5(o+v), 1/2/4/8 irreps
+    with Dirichlet splits) in one batched call: every system matches its
+    standalone result bitwise and sampled oracle elements."""
+    syms = S.batch_syms(64, seed=0)
+    probs = [problem(s, seed=k) for k, s in enumerate(syms)]
+    ds = [device_problem(gpu_lib, p, nan_fill=True) for p in probs]
+    run(gpu_lib, ds, precision=precision)
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    rng = np.random.default_rng(77)
+    for k, (p, d) in enumerate(zip(probs, ds)):
+        R = d["R"].cpu().numpy()
+        assert np.all(np.isfinite(R)), k
+        if k % 8 == 0:
+            alone = device_problem(gpu_lib, p)
+            run(gpu_lib, alone, precision=precision)
+            assert np.array_equal(alone["R"].cpu().numpy(), R), k
+        lay, sym = d["layout"], p["sym"]
+        Rb = lay.unpack_amp(R)
+        scale = max(float(np.max(np.abs(b))) for b in Rb.values() if b.size)
+        h, no, nv = sym["h"], sym["nocc"], sym["nvir"]
+        for _ in range(12):
+            G, gi, ga = (int(x) for x in rng.integers(0, h, 3))
+            gj, gb = gi ^ G, ga ^ G
+            if not (no[gi] and no[gj] and nv[ga] and nv[gb]):
+                continue
+            i, j = int(rng.integers(no[gi])), int(rng.integers(no[gj]))
+            a, b = int(rng.integers(nv[ga])), int(rng.integers(nv[gb]))
+            ref = O.element_t2(sym, p["B"], p["X"], lay.occ_off[gi] + i, lay.occ_off[gj] + j,
+                               lay.vir_off[ga] + a, lay.vir_off[gb] + b)
+            assert abs(Rb[(G, gi, ga)][i, j, a, b] - ref) <= tol * scale, (k, G, gi, ga)
