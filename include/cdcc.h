@@ -119,7 +119,8 @@ typedef struct {
 
 typedef struct {
   int32_t precision;         /* CDCC_FP64 or CDCC_MIXED                         */
-  int32_t tile_policy;       /* 0 = autotuned table, 1..3 = force a tile class  */
+  int32_t tile_policy;       /* 0 = tile table, k = force assembly class k-1:   */
+                             /* 1..3 (FP64), 1..4 (CDCC_MIXED)                 */
   int64_t batch_bytes;       /* cap of the (ac|bd) batch buffer, 0 = default    */
 } cdcc_opts_t;
 

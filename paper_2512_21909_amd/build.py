@@ -66,7 +66,7 @@ def build(verbose: bool = False) -> str:
         list(ex.map(lambda c: _run(c, verbose), jobs))
     tmp = OUT + ".tmp"
     _run([hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
-         + ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"], verbose)
+         + ["-L/opt/rocm/lib", "-lamdhip64", "-ldl", "-Wl,-rpath,/opt/rocm/lib"], verbose)
     os.replace(tmp, OUT)
     return OUT
 

@@ -10,8 +10,12 @@
 // enqueued on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -31,7 +35,9 @@ hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Til
                                int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
 hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,
                                const SysPtrs *sp, const double *xbuf, const int4 *ktab, const int4 *ijtab,
-                               const int4 *vvtab, hipStream_t s);
+                               const int4 *vvtab, double *part, hipStream_t s);
+hipError_t launch_reduce_unpack(int cls, int njobs, const P2Group *groups, const Tile *jobs, const SysPtrs *sp,
+                                const double *part, const int4 *ijtab, const int4 *vvtab, hipStream_t s);
 int occupancy_f64(int which, int cls);
 hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s);
 // mixed path (kernels_mixed.hip)
@@ -51,10 +57,10 @@ inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a 
 // P1 (assembly) tile classes and P2 (contraction) tile classes.
 constexpr int kP1BM[3] = {64, 128, 128};
 constexpr int kP1BN[3] = {64, 64, 128};
-constexpr int kMixBM[3] = {64, 128, 128};   // mixed path assembly tiles
-constexpr int kMixBN[3] = {128, 64, 128};
+constexpr int kMixBM[4] = {64, 128, 128, 64};   // mixed path assembly tiles
+constexpr int kMixBN[4] = {128, 64, 128, 64};
 constexpr int kP2BM[3] = {32, 64, 128};
-constexpr int kP2BN[3] = {64, 64, 64};
+constexpr int kP2BN[3] = {64, 64, 128};
 
 struct Launch {
   int cls = 0, start = 0, count = 0, grid = 0;
@@ -62,7 +68,12 @@ struct Launch {
 };
 struct BatchPlan {
   std::vector<Launch> p1, p2;
+  Launch red;  // split-K reduce + unpack jobs (count 0: none)
 };
+
+// Split-K segment of the contraction: fixed per group shape (never per
+// batch), so a system's result is the same alone and in any batch.
+constexpr int kKSeg = 1024;
 
 struct SysPlan {
   cdcc_layout_t lay{};
@@ -90,6 +101,8 @@ struct Plan {
   Tile *p1tiles = nullptr;
   P2Group *p2 = nullptr;
   Tile *p2tiles = nullptr;
+  Tile *redjobs = nullptr;
+  int64_t part_elems = 0;
   int4 *ktab = nullptr, *ijtab = nullptr, *vvtab = nullptr;
   int *vvfull = nullptr;
   EnergyJob *ejobs = nullptr;
@@ -223,8 +236,51 @@ std::string plan_key(int dev, int nsys, const cdcc_problem_t *p, int lambda, int
   return k;
 }
 
-int choose_p1_class(const cdcc_layout_t &L, int policy) {
-  if (policy >= 1 && policy <= 3) return policy - 1;
+// Tile table written by the autotuner (paper_2512_21909_amd/autotune.py):
+// lines "<fp64|mixed> <t2|lambda> h nocc[h] nvir[h] ncd[h] class", looked up by
+// the exact shape of each system.  Read once from $CDCC_TILE_TABLE or from
+// tile_table.txt next to this library.
+std::map<std::string, int> *g_tile_table = nullptr;
+
+std::string shape_key(const cdcc_sym_t &y, int mixed, int lambda) {
+  std::ostringstream k;
+  k << (mixed ? "mixed" : "fp64") << ' ' << (lambda ? "lambda" : "t2") << ' ' << y.nirrep;
+  for (const int32_t *a : {y.nocc, y.nvir, y.ncd})
+    for (int g = 0; g < y.nirrep; ++g) k << ' ' << a[g];
+  return k.str();
+}
+
+const std::map<std::string, int> &tile_table() {
+  if (g_tile_table) return *g_tile_table;
+  g_tile_table = new std::map<std::string, int>();
+  std::string path;
+  if (const char *e = std::getenv("CDCC_TILE_TABLE")) {
+    path = e;
+  } else {
+    Dl_info info;
+    if (dladdr(reinterpret_cast<void *>(&cdcc_irrep_layout), &info) && info.dli_fname) {
+      path = info.dli_fname;
+      const size_t cut = path.find_last_of('/');
+      path = (cut == std::string::npos ? std::string(".") : path.substr(0, cut)) + "/tile_table.txt";
+    }
+  }
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    const size_t cut = line.find_last_of(' ');
+    if (cut == std::string::npos) continue;
+    (*g_tile_table)[line.substr(0, cut)] = std::atoi(line.c_str() + cut + 1);
+  }
+  return *g_tile_table;
+}
+
+int choose_p1_class(const cdcc_layout_t &L, int policy, int mixed, int lambda) {
+  if (policy >= 1 && policy <= (mixed ? 4 : 3)) return policy - 1;
+  const auto &T = tile_table();
+  const auto it = T.find(shape_key(L.sym, mixed, lambda));
+  if (it != T.end() && it->second >= 0 && it->second <= (mixed ? 3 : 2)) return it->second;
+  if (mixed) return 1;  // 128 x 64: best measured default for the split-BF16 kernel
   // Tile-table heuristic: the largest tile that still gives >= 2 tiles per CU.
   const int h = L.sym.nirrep;
   const int32_t *nv = L.sym.nvir, *nc = L.sym.ncd;
@@ -297,7 +353,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     const int32_t *no = L.sym.nocc, *nv = L.sym.nvir, *nc = L.sym.ncd;
     const int kmul = (lambda && dressed) ? 2 : 1;
     const bool mixed = opts.precision == CDCC_MIXED;
-    SP.p1cls = mixed ? (opts.tile_policy >= 1 ? opts.tile_policy - 1 : 1) : choose_p1_class(L, opts.tile_policy);
+    SP.p1cls = choose_p1_class(L, opts.tile_policy, mixed, lambda);
     if (lambda) SP.u_elems = kmul * L.b_size;
     // mixed path: slice every operand block once per call
     int64_t blk_s[CDCC_MAX_IRREP][CDCC_MAX_IRREP], blk_sc[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
@@ -457,6 +513,9 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           g.th_ld = int(L.n_vv_pk[G]);
           g.th_off = th_off[G];
           g.r_off = L.amp_off[G];
+          g.nsplit = std::max(1, (kt_len + kKSeg / 2) / kKSeg);
+          g.kseg = ((kt_len + g.nsplit - 1) / g.nsplit + 15) / 16 * 16;
+          if (g.nsplit > 1) g.nsplit = (kt_len + g.kseg - 1) / g.kseg;
           R.region = nrows * g.ncols;
           R.p2cls = n_ij > 64 ? 2 : (n_ij > 32 ? 1 : 0);  // unified per batch below
           // assembly GEMMs
@@ -507,6 +566,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
   std::vector<Tile> p1tiles;
   std::vector<P2Group> p2;
   std::vector<Tile> p2tiles;
+  std::vector<Tile> redjobs;
   size_t gi = 0;
   while (gi < groups.size()) {
     int64_t used = 0;
@@ -517,7 +577,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     }
     BatchPlan B;
     // gather tiles by class
-    std::vector<std::vector<std::pair<int64_t, Tile>>> t1(3), t2(3);
+    std::vector<std::vector<std::pair<int64_t, Tile>>> t1(4), t2(3);
     // deal chunks of consecutive tiles round-robin to the 8 XCD queues
     auto emit = [&](std::vector<std::pair<int64_t, Tile>> &v, int chunk, int cls, int occ,
                     std::vector<Tile> &out, std::vector<Launch> &launches) {
@@ -545,19 +605,32 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     // second launch of a few tiles would serialise behind the first
     int c2max = 0;
     for (size_t k = gi; k < gj; ++k) c2max = std::max(c2max, groups[k].p2cls);
+    int64_t po = 0;
+    Launch red;
+    red.cls = c2max;
+    red.start = int(redjobs.size());
     for (size_t k = gi; k < gj; ++k) {
       GroupRec &R = groups[k];
       R.p2cls = c2max;
       R.g.xoff = xo;
       xo += align_up(R.region, 32);
       const int gid = int(p2.size());
-      p2.push_back(R.g);
       const int c2 = R.p2cls;
+      const int tm = (R.g.n_ij + kP2BM[c2] - 1) / kP2BM[c2], tn = (R.g.ncols + kP2BN[c2] - 1) / kP2BN[c2];
+      R.g.tiles_n = tn;
+      R.g.part_off = po;
       if (R.g.n_ij > 0 && R.g.ncols > 0) {
-        const int tm = (R.g.n_ij + kP2BM[c2] - 1) / kP2BM[c2], tn = (R.g.ncols + kP2BN[c2] - 1) / kP2BN[c2];
         for (int a = 0; a < tm; ++a)
-          for (int b = 0; b < tn; ++b) t2[c2].push_back({int64_t(R.g.ktab_len) + 1, Tile{gid, a, b, c2}});
+          for (int b = 0; b < tn; ++b) {
+            for (int ks = 0; ks < R.g.nsplit; ++ks) {
+              const int len = std::min(R.g.kseg, R.g.ktab_len - ks * R.g.kseg);
+              t2[c2].push_back({int64_t(len) + 1, Tile{gid, a, b, ks}});
+            }
+            if (R.g.nsplit > 1) redjobs.push_back(Tile{gid, a, b, 0});
+          }
+        if (R.g.nsplit > 1) po += int64_t(tm) * tn * R.g.nsplit * 2 * kP2BM[c2] * kP2BN[c2];
       }
+      p2.push_back(R.g);
       const int c1 = P.sys[R.sys].p1cls;
       const bool mixed = P.precision == CDCC_MIXED;
       for (P1Desc d : R.descs) {
@@ -582,8 +655,11 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
       }
     }
     P.xbuf_elems = std::max(P.xbuf_elems, xo);
+    P.part_elems = std::max(P.part_elems, po);
+    red.count = int(redjobs.size()) - red.start;
+    B.red = red;
     const bool mixedp = P.precision == CDCC_MIXED;
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 4; ++c)
       emit(t1[c], 32, c, mixedp ? occupancy_mixed(c) : occupancy_f64(0, c), p1tiles, B.p1);
     for (int c = 0; c < 3; ++c) emit(t2[c], 8, c, occupancy_f64(1, c), p2tiles, B.p2);
     P.batches.push_back(std::move(B));
@@ -600,6 +676,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
   const int64_t o_p1 = T.add(p1), o_t1 = T.add(p1tiles), o_p2 = T.add(p2), o_t2 = T.add(p2tiles);
   const int64_t o_kt = T.add(ktab), o_ij = T.add(ijtab), o_vv = T.add(vvtab), o_vf = T.add(vvfull);
   const int64_t o_ej = T.add(ejobs), o_sj = T.add(slicejobs), o_sr = T.add(slicerows);
+  const int64_t o_rj = T.add(redjobs);
   if (hipMalloc(&P.dtab, std::max<size_t>(T.bytes.size(), 256)) != hipSuccess) return CDCC_ENOMEM;
   if (hipMemcpy(P.dtab, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return CDCC_EDEVICE;
   char *b = static_cast<char *>(P.dtab);
@@ -613,6 +690,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
   P.p1tiles = reinterpret_cast<Tile *>(b + o_t1);
   P.p2 = reinterpret_cast<P2Group *>(b + o_p2);
   P.p2tiles = reinterpret_cast<Tile *>(b + o_t2);
+  P.redjobs = reinterpret_cast<Tile *>(b + o_rj);
   P.ktab = reinterpret_cast<int4 *>(b + o_kt);
   P.ijtab = reinterpret_cast<int4 *>(b + o_ij);
   P.vvtab = reinterpret_cast<int4 *>(b + o_vv);
@@ -627,7 +705,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
 
 // Workspace layout of one call.
 struct WsLayout {
-  int64_t counters = 0, sysptrs = 0, xbuf = 0, total = 0;
+  int64_t counters = 0, sysptrs = 0, xbuf = 0, part = 0, total = 0;
   std::vector<int64_t> th, u, sl, sc;
 };
 
@@ -640,6 +718,8 @@ WsLayout ws_layout(const Plan &P) {
   o = align_up(o + int64_t(P.nsys) * int64_t(sizeof(SysPtrs)));
   W.xbuf = o;
   o = align_up(o + P.xbuf_elems * 8);
+  W.part = o;
+  o = align_up(o + P.part_elems * 8);
   W.th.resize(P.nsys);
   W.u.resize(P.nsys);
   W.sl.resize(P.nsys);
@@ -748,7 +828,7 @@ int get_workspace(int dev, hipStream_t stream, int64_t bytes, int64_t staging, W
   } while (0)
 
 // Every kernel of one evaluation, in order, on stream s.
-int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, hipStream_t stream) {
+int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, double *part, hipStream_t stream) {
   const Plan *P = &Pl;
   HIPCHK(launch_fill_int(counters, P->ncounters, 0, stream));
   if (P->lambda) {
@@ -779,7 +859,9 @@ int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, 
       Span sp(3, int(B.p2.size()), stream);
       for (const Launch &l : B.p2)
         HIPCHK(launch_contract_f64(l.cls, l.grid, P->p2, P->p2tiles + l.start, l.q, counters + 8 * ci++, dsp, xbuf,
-                                   P->ktab, P->ijtab, P->vvtab, stream));
+                                   P->ktab, P->ijtab, P->vvtab, part, stream));
+      HIPCHK(launch_reduce_unpack(B.red.cls, B.red.count, P->p2, P->redjobs + B.red.start, dsp, part, P->ijtab,
+                                  P->vvtab, stream));
     }
   }
   {
@@ -804,7 +886,8 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
   cdcc_opts_t opts{};
   if (popts) opts = *popts;
   if (opts.precision != CDCC_FP64 && opts.precision != CDCC_MIXED) return CDCC_EINVAL;
-  if (opts.tile_policy < 0 || opts.tile_policy > 3) return CDCC_EINVAL;
+  if (opts.tile_policy < 0 || opts.tile_policy > 4) return CDCC_EINVAL;
+  if (opts.tile_policy == 4 && opts.precision != CDCC_MIXED) return CDCC_EINVAL;
   int dressed = 0;
   int rc = validate(nsys, probs, lambda, &dressed);
   if (rc != CDCC_OK) return rc;
@@ -850,15 +933,16 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
 
   int *counters = reinterpret_cast<int *>(base + W.counters);
   double *xbuf = reinterpret_cast<double *>(base + W.xbuf);
+  double *part = reinterpret_cast<double *>(base + W.part);
   const bool use_graph = !g_timing && env_i64("CDCC_GRAPH", 1) != 0;
-  if (!use_graph) return enqueue_sequence(*P, dsp, counters, xbuf, stream);
+  if (!use_graph) return enqueue_sequence(*P, dsp, counters, xbuf, part, stream);
   auto it = P->graphs.find(ws->dev);
   if (it == P->graphs.end()) {
     // capture the kernel sequence once per (plan, workspace) on a private stream
     hipStream_t cap = capture_stream(dev);
     if (!cap) return CDCC_EDEVICE;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    const int rc2 = enqueue_sequence(*P, dsp, counters, xbuf, cap);
+    const int rc2 = enqueue_sequence(*P, dsp, counters, xbuf, part, cap);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(cap, &graph);
     if (rc2 != CDCC_OK || e != hipSuccess) {
@@ -931,6 +1015,8 @@ extern "C" int cdcc_timing_read(double ms[8], int64_t launches[8]) {
 
 extern "C" int cdcc_release(void) {
   std::lock_guard<std::mutex> lock(g_mu);
+  delete g_tile_table;  // re-read on the next plan
+  g_tile_table = nullptr;
   if (hipDeviceSynchronize() != hipSuccess) return CDCC_EDEVICE;
   g_ws.clear();
   g_plans.clear();

@@ -227,6 +227,32 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
   }
 }
 
+// Unpack one (S, A) pair of packed row m (i>=j) and group column n (a>=b)
+// into R: (ij,ab) = S+A, (ij,ba) = (ji,ab) = S-A, (ji,ba) = S+A; and R/D.
+__device__ __forceinline__ void unpack_store(const SysPtrs &S, const P2Group &g, int m, int n, double sv,
+                                             double av, const int4 *__restrict__ ijtab,
+                                             const int4 *__restrict__ vvtab) {
+  const int4 ij = ijtab[g.ij_off + m];
+  const int4 ab = vvtab[g.col_off + n];
+  const double pp = sv + av, pm = sv - av;
+  const int64_t ld = g.ldr;
+  const bool oab = ab.x != ab.y, oij = ij.x != ij.y;
+  double *__restrict__ R = S.R + g.r_off;
+  R[int64_t(ij.x) * ld + ab.x] = pp;
+  if (oab) R[int64_t(ij.x) * ld + ab.y] = pm;
+  if (oij) R[int64_t(ij.y) * ld + ab.x] = pm;
+  if (oab && oij) R[int64_t(ij.y) * ld + ab.y] = pp;
+  if (S.delta) {
+    double *__restrict__ Dl = S.delta + g.r_off;
+    const double den = (S.eps_occ[ij.z] + S.eps_occ[ij.w]) - (S.eps_vir[ab.z] + S.eps_vir[ab.w]);
+    const double inv = 1.0 / den;
+    Dl[int64_t(ij.x) * ld + ab.x] = pp * inv;
+    if (oab) Dl[int64_t(ij.x) * ld + ab.y] = pm * inv;
+    if (oij) Dl[int64_t(ij.y) * ld + ab.x] = pm * inv;
+    if (oab && oij) Dl[int64_t(ij.y) * ld + ab.y] = pp * inv;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // contract (FP64): S = tauhat(+) W(+), A = tauhat(-) W(-) over the K table of
 // the group (entries: tauhat column, X rows of (c,d) and (d,c), -1 = absent).
@@ -235,31 +261,34 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
 // Epilogue writes R (and R/D) at the four permutations (ij,ab),
 // (ij,ba) = S-A, (ji,ab) = S-A, (ji,ba) = S+A.
 // ---------------------------------------------------------------------------
-template <int BM, int BN>
-__global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__restrict__ groups,
+template <int BM, int BN, int NT>
+__global__ __launch_bounds__(NT) void contract_f64_kernel(const P2Group *__restrict__ groups,
                                                            const Tile *__restrict__ tiles, Queues Q,
                                                            int *__restrict__ cnt,
                                                            const SysPtrs *__restrict__ sp,
                                                            const double *__restrict__ xbuf,
                                                            const int4 *__restrict__ ktab,
                                                            const int4 *__restrict__ ijtab,
-                                                           const int4 *__restrict__ vvtab) {
+                                                           const int4 *__restrict__ vvtab,
+                                                           double *__restrict__ part) {
   constexpr int BK = 16;
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int NW = NT / 64;                // waves: 2 along M, NW/2 along N
+  constexpr int WM = BM / 2, WN = BN / (NW / 2);
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int EPT = BM * BK / 256;         // A elements per thread (one row, EPT consecutive k)
+  constexpr int EPT = BM * BK / NT;          // A elements per thread (one row, EPT consecutive k)
   constexpr int TPR = BK / EPT;              // threads per A row
-  constexpr int CB = BN / 16;                // B columns per thread (16 threads per k row)
+  constexpr int CB = BN * BK / NT;           // B columns per thread (one k row)
+  constexpr int TPK = BN / CB;               // threads per B k row
   constexpr int LA = BM + 2, LB = BN + 2;
-  static_assert(EPT >= 1 && BK % EPT == 0, "A staging");
+  static_assert(EPT >= 1 && BK % EPT == 0 && CB >= 1 && FN >= 1, "staging");
   __shared__ double Ap[2][BK][LA], Am[2][BK][LA];
   __shared__ double Bp[2][BK][LB], Bm[2][BK][LB];
   __shared__ int s_tile;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave & 1, wn = wave >> 1;
   const int lr = tid / TPR, lk = (tid % TPR) * EPT;  // A staging
-  const int bk = tid >> 4, bc = (tid & 15) * CB;     // B staging
+  const int bk = tid / TPK, bc = (tid % TPK) * CB;   // B staging
   int tries = 0;
 
   for (;;) {
@@ -272,7 +301,10 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
     const CDCC_GLOBAL double *gthp = as_global(S.tauhat) + g.th_off;
     const CDCC_GLOBAL double *gthm = gthp + int64_t(g.n_ij) * g.th_ld;
     const CDCC_GLOBAL double *gxr = as_global(xbuf) + g.xoff;
-    const CDCC_GLOBAL int *gkt = as_global(reinterpret_cast<const int *>(ktab + g.ktab_off));  // int4 entries
+    // K segment of this tile (the whole table unless the group is split)
+    const int kbeg = tl.aux * g.kseg;
+    const int klen = (g.nsplit > 1 ? (g.ktab_len - kbeg < g.kseg ? g.ktab_len - kbeg : g.kseg) : g.ktab_len);
+    const CDCC_GLOBAL int *gkt = as_global(reinterpret_cast<const int *>(ktab + g.ktab_off + kbeg));  // int4 entries
 
     d4 accS[FM][FN], accA[FM][FN];
 #pragma unroll
@@ -331,7 +363,7 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
       }
     };
 
-    const int nk = g.ktab_len / BK;
+    const int nk = klen / BK;
     if (nk > 0) {
       kload(0);
       gload();
@@ -369,8 +401,24 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
       __syncthreads();
     }
 
-    double *__restrict__ R = S.R + g.r_off;
-    double *__restrict__ Dl = S.delta ? S.delta + g.r_off : nullptr;
+    if (g.nsplit > 1) {
+      // split K: store this segment's S and A partials; the reduce kernel
+      // sums the segments in order and unpacks
+      double *__restrict__ pb =
+          part + g.part_off + (int64_t(tl.tm * g.tiles_n + tl.tn) * g.nsplit + tl.aux) * (2 * BM * BN);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int lm = wm * WM + i * 16 + (lane >> 4) + 4 * rr;
+            const int ln = wn * WN + j * 16 + (lane & 15);
+            pb[lm * BN + ln] = accS[i][j][rr];
+            pb[BM * BN + lm * BN + ln] = accA[i][j][rr];
+          }
+      continue;
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -380,25 +428,37 @@ __global__ __launch_bounds__(256) void contract_f64_kernel(const P2Group *__rest
           const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * rr;
           const int n = n0 + wn * WN + j * 16 + (lane & 15);
           if (m >= g.n_ij || n >= g.ncols) continue;
-          const int4 ij = ijtab[g.ij_off + m];
-          const int4 ab = vvtab[g.col_off + n];
-          const double sv = accS[i][j][rr], av = accA[i][j][rr];
-          const double pp = sv + av, pm = sv - av;
-          const int64_t ld = g.ldr;
-          const bool oab = ab.x != ab.y, oij = ij.x != ij.y;
-          R[int64_t(ij.x) * ld + ab.x] = pp;
-          if (oab) R[int64_t(ij.x) * ld + ab.y] = pm;
-          if (oij) R[int64_t(ij.y) * ld + ab.x] = pm;
-          if (oab && oij) R[int64_t(ij.y) * ld + ab.y] = pp;
-          if (Dl) {
-            const double den = (S.eps_occ[ij.z] + S.eps_occ[ij.w]) - (S.eps_vir[ab.z] + S.eps_vir[ab.w]);
-            const double inv = 1.0 / den;
-            Dl[int64_t(ij.x) * ld + ab.x] = pp * inv;
-            if (oab) Dl[int64_t(ij.x) * ld + ab.y] = pm * inv;
-            if (oij) Dl[int64_t(ij.y) * ld + ab.x] = pm * inv;
-            if (oab && oij) Dl[int64_t(ij.y) * ld + ab.y] = pp * inv;
-          }
+          unpack_store(S, g, m, n, accS[i][j][rr], accA[i][j][rr], ijtab, vvtab);
         }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reduce (split K): one workgroup per contraction tile; S and A summed over
+// the K segments in segment order, then the same unpack as above.
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void reduce_unpack_kernel(const P2Group *__restrict__ groups,
+                                                            const Tile *__restrict__ jobs,
+                                                            const SysPtrs *__restrict__ sp,
+                                                            const double *__restrict__ part,
+                                                            const int4 *__restrict__ ijtab,
+                                                            const int4 *__restrict__ vvtab) {
+  const Tile tl = jobs[blockIdx.x];
+  const P2Group g = groups[tl.desc];
+  const SysPtrs S = sp[g.sys];
+  const double *__restrict__ pb =
+      part + g.part_off + int64_t(tl.tm * g.tiles_n + tl.tn) * g.nsplit * (2 * BM * BN);
+  for (int e = threadIdx.x; e < BM * BN; e += 256) {
+    const int lm = e / BN, ln = e - lm * BN;
+    const int m = tl.tm * BM + lm, n = tl.tn * BN + ln;
+    if (m >= g.n_ij || n >= g.ncols) continue;
+    double sv = 0.0, av = 0.0;
+    for (int k = 0; k < g.nsplit; ++k) {
+      sv += pb[int64_t(k) * (2 * BM * BN) + e];
+      av += pb[int64_t(k) * (2 * BM * BN) + BM * BN + e];
+    }
+    unpack_store(S, g, m, n, sv, av, ijtab, vvtab);
   }
 }
 
@@ -461,12 +521,23 @@ hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Til
 
 hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,
                                const SysPtrs *sp, const double *xbuf, const int4 *ktab, const int4 *ijtab,
-                               const int4 *vvtab, hipStream_t s) {
+                               const int4 *vvtab, double *part, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   switch (cls) {
-    case 0: contract_f64_kernel<32, 64><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab); break;
-    case 1: contract_f64_kernel<64, 64><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab); break;
-    default: contract_f64_kernel<128, 64><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab); break;
+    case 0: contract_f64_kernel<32, 64, 256><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part); break;
+    case 1: contract_f64_kernel<64, 64, 256><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part); break;
+    default: contract_f64_kernel<128, 128, 512><<<grid, 512, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_unpack(int cls, int njobs, const P2Group *groups, const Tile *jobs, const SysPtrs *sp,
+                                const double *part, const int4 *ijtab, const int4 *vvtab, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  switch (cls) {
+    case 0: reduce_unpack_kernel<32, 64><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
+    case 1: reduce_unpack_kernel<64, 64><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
+    default: reduce_unpack_kernel<128, 128><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
   }
   return hipGetLastError();
 }
@@ -480,9 +551,9 @@ int occupancy_f64(int which, int cls) {
     else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 64>, 256, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 128>, 256, 0);
   } else {
-    if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<32, 64>, 256, 0);
-    else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<64, 64>, 256, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<128, 64>, 256, 0);
+    if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<32, 64, 256>, 256, 0);
+    else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<64, 64, 256>, 256, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<128, 128, 512>, 512, 0);
   }
   return (e == hipSuccess && n > 0) ? n : 1;
 }

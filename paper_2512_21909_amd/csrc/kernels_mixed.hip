@@ -82,11 +82,12 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
 // 32x32 blocks each).  An LDS row holds one 16-wide K block of all four
 // slices (128 B + 16 B pad); double-buffered, one barrier per K block.
 // ---------------------------------------------------------------------------
-template <int BM, int BN>
-__global__ __launch_bounds__(64 * (BM / 32) * (BN / 64)) void assemble_mixed_kernel(
+template <int BM, int BN, int WN>
+__global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_kernel(
     const P1Desc *__restrict__ descs, const Tile *__restrict__ tiles, Queues Q, int *__restrict__ cnt,
     const SysPtrs *__restrict__ sp, double *__restrict__ xbuf) {
-  constexpr int WAVES_N = BN / 64, WAVES_M = BM / 32;
+  constexpr int NJ = WN / 32;                  // 32x32 output blocks per wave along N
+  constexpr int WAVES_N = BN / WN, WAVES_M = BM / 32;
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int ROWB = 144;                    // bytes per LDS row
   constexpr int CPT = (BM + BN) * 8 / NT;      // 16-byte chunks per thread per K block
@@ -128,10 +129,10 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 64)) void assemble_mixed_ker
       }
     }
 
-    f16v acc0[2], acc1[2];
-    double tot[2][16];
+    f16v acc0[NJ], acc1[NJ];
+    double tot[NJ][16];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       acc0[j] = f16v{};
       acc1[j] = f16v{};
 #pragma unroll
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 64)) void assemble_mixed_ker
     };
     auto flush = [&]() {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NJ; ++j) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) tot[j][r] += double(acc0[j][r]) + double(acc1[j][r]);
         acc0[j] = f16v{};
@@ -185,8 +186,8 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 64)) void assemble_mixed_ker
         for (int s = 0; s < 4; ++s)
           a[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + arow * ROWB + s * 32 + koff));
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int brow = BM + wn * 64 + j * 32 + (lane & 31);
+        for (int j = 0; j < NJ; ++j) {
+          const int brow = BM + wn * WN + j * 32 + (lane & 31);
           bf8 b[4];
 #pragma unroll
           for (int s = 0; s < 4; ++s)
@@ -210,11 +211,11 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / 64)) void assemble_mixed_ker
 
     // epilogue: scale and permuted store (same numbering as the FP64 path)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+        const int n = n0 + wn * WN + j * 32 + (lane & 31);
         if (m >= D.M || n >= D.N) continue;
         const int am = m / D.vc, c = m - am * D.vc;
         const int a = D.a_first + am;
@@ -240,9 +241,10 @@ hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const T
                                  int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   switch (cls) {
-    case 0: assemble_mixed_kernel<64, 128><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
-    case 1: assemble_mixed_kernel<128, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
-    default: assemble_mixed_kernel<128, 128><<<grid, 512, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    case 0: assemble_mixed_kernel<64, 128, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    case 1: assemble_mixed_kernel<128, 64, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    case 2: assemble_mixed_kernel<128, 128, 64><<<grid, 512, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    default: assemble_mixed_kernel<64, 64, 32><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
   }
   return hipGetLastError();
 }
@@ -250,9 +252,10 @@ hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const T
 int occupancy_mixed(int cls) {
   int n = 0;
   hipError_t e;
-  if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 128>, 256, 0);
-  else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 64>, 256, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 128>, 512, 0);
+  if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 128, 64>, 256, 0);
+  else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 64, 64>, 256, 0);
+  else if (cls == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 128, 64>, 512, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 64, 32>, 256, 0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 

@@ -61,10 +61,13 @@ struct P2Group {
   int32_t col_off;     // offset into the vv-pair table for column 0 of the group
   int32_t ldr;         // n_vv(G): R row length
   int32_t th_ld;       // n_vv_pk(G): tauhat row length
-  int32_t pad0;
+  int32_t kseg;        // K-table entries per split-K segment (multiple of 16)
+  int32_t nsplit;      // number of K segments (1: the tile writes R itself)
+  int32_t tiles_n;     // column tiles of the group (partial-block numbering)
   int64_t xoff;        // X region in the batch buffer
   int64_t th_off;      // tauhat(+) offset; (-) at th_off + n_ij * th_ld
   int64_t r_off;       // amp_off[G]
+  int64_t part_off;    // first partial block of the group in the split-K buffer
 };
 
 // Per-row data of the pair-energy reduction.
@@ -75,7 +78,7 @@ struct EnergyJob {
 };
 
 struct Tile {
-  int32_t desc, tm, tn, cls;
+  int32_t desc, tm, tn, aux;   // aux: K segment of a split contraction tile
 };
 
 // Per-XCD tile queues of one launch: queue x holds tiles [qb[x], qb[x+1]) of
