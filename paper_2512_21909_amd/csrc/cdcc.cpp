@@ -60,7 +60,7 @@ constexpr int kP1BN[3] = {64, 64, 128};
 constexpr int kMixBM[4] = {64, 128, 128, 64};   // mixed path assembly tiles
 constexpr int kMixBN[4] = {128, 64, 128, 64};
 constexpr int kP2BM[3] = {32, 64, 128};
-constexpr int kP2BN[3] = {64, 64, 128};
+constexpr int kP2BN[3] = {64, 64, 64};
 
 struct Launch {
   int cls = 0, start = 0, count = 0, grid = 0;
@@ -626,9 +626,9 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
               const int len = std::min(R.g.kseg, R.g.ktab_len - ks * R.g.kseg);
               t2[c2].push_back({int64_t(len) + 1, Tile{gid, a, b, ks}});
             }
-            if (R.g.nsplit > 1) redjobs.push_back(Tile{gid, a, b, 0});
+            if (R.g.nsplit > 1 || c2 == 2) redjobs.push_back(Tile{gid, a, b, 0});
           }
-        if (R.g.nsplit > 1) po += int64_t(tm) * tn * R.g.nsplit * 2 * kP2BM[c2] * kP2BN[c2];
+        if (R.g.nsplit > 1 || c2 == 2) po += int64_t(tm) * tn * R.g.nsplit * 2 * kP2BM[c2] * kP2BN[c2];
       }
       p2.push_back(R.g);
       const int c1 = P.sys[R.sys].p1cls;

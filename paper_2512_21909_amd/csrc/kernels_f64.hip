@@ -261,7 +261,7 @@ __device__ __forceinline__ void unpack_store(const SysPtrs &S, const P2Group &g,
 // Epilogue writes R (and R/D) at the four permutations (ij,ab),
 // (ij,ba) = S-A, (ji,ab) = S-A, (ji,ba) = S+A.
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int NT>
+template <int BM, int BN, int NT, bool PARTIAL>
 __global__ __launch_bounds__(NT) void contract_f64_kernel(const P2Group *__restrict__ groups,
                                                            const Tile *__restrict__ tiles, Queues Q,
                                                            int *__restrict__ cnt,
@@ -401,9 +401,10 @@ __global__ __launch_bounds__(NT) void contract_f64_kernel(const P2Group *__restr
       __syncthreads();
     }
 
-    if (g.nsplit > 1) {
-      // split K: store this segment's S and A partials; the reduce kernel
-      // sums the segments in order and unpacks
+    if (PARTIAL || g.nsplit > 1) {
+      // store this segment's S and A partials; the reduce kernel sums the
+      // segments in order and unpacks (PARTIAL: always, to keep the unpack
+      // epilogue out of this kernel's register budget)
       double *__restrict__ pb =
           part + g.part_off + (int64_t(tl.tm * g.tiles_n + tl.tn) * g.nsplit + tl.aux) * (2 * BM * BN);
 #pragma unroll
@@ -419,17 +420,19 @@ __global__ __launch_bounds__(NT) void contract_f64_kernel(const P2Group *__restr
           }
       continue;
     }
+    if constexpr (!PARTIAL) {
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * rr;
-          const int n = n0 + wn * WN + j * 16 + (lane & 15);
-          if (m >= g.n_ij || n >= g.ncols) continue;
-          unpack_store(S, g, m, n, accS[i][j][rr], accA[i][j][rr], ijtab, vvtab);
-        }
+          for (int rr = 0; rr < 4; ++rr) {
+            const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * rr;
+            const int n = n0 + wn * WN + j * 16 + (lane & 15);
+            if (m >= g.n_ij || n >= g.ncols) continue;
+            unpack_store(S, g, m, n, accS[i][j][rr], accA[i][j][rr], ijtab, vvtab);
+          }
+    }
   }
 }
 
@@ -519,14 +522,22 @@ hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Til
   return hipGetLastError();
 }
 
+// Contraction tile classes: 0 = 32 x 64, 1 = 64 x 64 (LDS kernel, unpack in
+// the epilogue unless split), 2 = 128 x 64 (always through the partial buffer).
 hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,
                                const SysPtrs *sp, const double *xbuf, const int4 *ktab, const int4 *ijtab,
                                const int4 *vvtab, double *part, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   switch (cls) {
-    case 0: contract_f64_kernel<32, 64, 256><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part); break;
-    case 1: contract_f64_kernel<64, 64, 256><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part); break;
-    default: contract_f64_kernel<128, 128, 512><<<grid, 512, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part); break;
+    case 0:
+      contract_f64_kernel<32, 64, 256, false><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part);
+      break;
+    case 1:
+      contract_f64_kernel<64, 64, 256, false><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part);
+      break;
+    default:
+      contract_f64_kernel<128, 64, 256, true><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part);
+      break;
   }
   return hipGetLastError();
 }
@@ -537,7 +548,7 @@ hipError_t launch_reduce_unpack(int cls, int njobs, const P2Group *groups, const
   switch (cls) {
     case 0: reduce_unpack_kernel<32, 64><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
     case 1: reduce_unpack_kernel<64, 64><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
-    default: reduce_unpack_kernel<128, 128><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
+    default: reduce_unpack_kernel<128, 64><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
   }
   return hipGetLastError();
 }
@@ -551,9 +562,9 @@ int occupancy_f64(int which, int cls) {
     else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 64>, 256, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 128>, 256, 0);
   } else {
-    if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<32, 64, 256>, 256, 0);
-    else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<64, 64, 256>, 256, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<128, 128, 512>, 512, 0);
+    if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<32, 64, 256, false>, 256, 0);
+    else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<64, 64, 256, false>, 256, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<128, 64, 256, true>, 256, 0);
   }
   return (e == hipSuccess && n > 0) ? n : 1;
 }

@@ -78,8 +78,8 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// assemble (mixed): tile BM x BN, (BM/32) x (BN/64) waves of 32 x 64 (two
-// 32x32 blocks each).  An LDS row holds one 16-wide K block of all four
+// assemble (mixed): tile BM x BN, (BM/32) x (BN/WN) waves of 32 x WN (WN/32
+// blocks of 32x32 each).  An LDS row holds one 16-wide K block of all four
 // slices (128 B + 16 B pad); double-buffered, one barrier per K block.
 // ---------------------------------------------------------------------------
 template <int BM, int BN, int WN>
