@@ -13,6 +13,7 @@
 #include <dlfcn.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <fstream>
 #include <sstream>
@@ -33,10 +34,10 @@ hipError_t launch_pack(const PackJob *jobs, const int2 *rows, int nrows, const S
 hipError_t launch_dress(const DressJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s);
 hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q,
                                int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
-hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,
+hipError_t launch_contract_f64(int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,
                                const SysPtrs *sp, const double *xbuf, const int4 *ktab, const int4 *ijtab,
                                const int4 *vvtab, double *part, hipStream_t s);
-hipError_t launch_reduce_unpack(int cls, int njobs, const P2Group *groups, const Tile *jobs, const SysPtrs *sp,
+hipError_t launch_reduce_unpack(int njobs, const P2Group *groups, const Tile *jobs, const SysPtrs *sp,
                                 const double *part, const int4 *ijtab, const int4 *vvtab, hipStream_t s);
 int occupancy_f64(int which, int cls);
 hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s);
@@ -54,13 +55,20 @@ namespace {
 constexpr int64_t kAlign = 256;
 inline int64_t align_up(int64_t x, int64_t a = kAlign) { return (x + a - 1) / a * a; }
 
-// P1 (assembly) tile classes and P2 (contraction) tile classes.
+// P1 (assembly) tile classes.
 constexpr int kP1BM[3] = {64, 128, 128};
 constexpr int kP1BN[3] = {64, 64, 128};
 constexpr int kMixBM[4] = {64, 128, 128, 64};   // mixed path assembly tiles
 constexpr int kMixBN[4] = {128, 64, 128, 64};
-constexpr int kP2BM[3] = {32, 64, 128};
-constexpr int kP2BN[3] = {64, 64, 64};
+// Contraction tiles: 16 * fm packed (ij) rows x 32 group columns, fm = 1..4
+// per group (the kernel switches on it per tile).
+constexpr int kP2BN = 32;
+inline int contract_fm(int n_ij) {
+  if (n_ij <= 64) return std::max(1, (n_ij + 15) / 16);
+  // least row padding over 48- and 64-row tiles, ties to 64
+  const int p3 = (n_ij + 47) / 48 * 48, p4 = (n_ij + 63) / 64 * 64;
+  return p3 < p4 ? 3 : 4;
+}
 
 struct Launch {
   int cls = 0, start = 0, count = 0, grid = 0;
@@ -340,7 +348,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     P2Group g;
     std::vector<P1Desc> descs;
     int64_t region = 0;
-    int sys = 0, p2cls = 0;
+    int sys = 0;
   };
   std::vector<GroupRec> groups;
   const int64_t cap_elems = std::max<int64_t>(cap / 8, 1);
@@ -409,7 +417,9 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
         J.th_off = SP.th_elems;
         const int jid = int(packjobs.size());
         packjobs.push_back(J);
-        for (int r = 0; r < nr; ++r) packrows.push_back(int2{jid, r});
+        // 64 x 64 (row, column) tiles, numbered rb * column_tiles + kb
+        const int nrb = int((nr + 63) / 64), nkb = int((ncl + 63) / 64);
+        for (int t = 0; t < nrb * nkb; ++t) packrows.push_back(int2{jid, t});
         SP.th_elems += 2 * nr * ncl;
       }
       if (probs[s].pair_energy)
@@ -517,7 +527,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           g.kseg = ((kt_len + g.nsplit - 1) / g.nsplit + 15) / 16 * 16;
           if (g.nsplit > 1) g.nsplit = (kt_len + g.kseg - 1) / g.kseg;
           R.region = nrows * g.ncols;
-          R.p2cls = n_ij > 64 ? 2 : (n_ij > 32 ? 1 : 0);  // unified per batch below
+          g.fm = contract_fm(int(n_ij));
           // assembly GEMMs
           const int bm = mixed ? kMixBM[SP.p1cls] : kP1BM[SP.p1cls];
           for (int gc = 0; gc < h; ++gc) {
@@ -577,7 +587,22 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     }
     BatchPlan B;
     // gather tiles by class
-    std::vector<std::vector<std::pair<int64_t, Tile>>> t1(4), t2(3);
+    std::vector<std::vector<std::pair<int64_t, Tile>>> t1(4), t2(1);
+    // supertile shape per assembly class: as many tiles as one XCD runs at
+    // once, with balanced A and B row counts
+    int st_m[4], st_n[4], st_chunk[4];
+    for (int c = 0; c < 4; ++c) {
+      const bool mx = P.precision == CDCC_MIXED;
+      if (!mx && c == 3) {
+        st_m[c] = st_n[c] = st_chunk[c] = 1;
+        continue;
+      }
+      const int bm = mx ? kMixBM[c] : kP1BM[c], bn = mx ? kMixBN[c] : kP1BN[c];
+      const int conc = std::max(1, g_num_cu / 8 * (mx ? occupancy_mixed(c) : occupancy_f64(0, c)));
+      st_m[c] = std::max(1, int(std::lround(std::sqrt(double(conc) * bn / bm))));
+      st_n[c] = std::max(1, conc / st_m[c]);
+      st_chunk[c] = st_m[c] * st_n[c];
+    }
     // deal chunks of consecutive tiles round-robin to the 8 XCD queues
     auto emit = [&](std::vector<std::pair<int64_t, Tile>> &v, int chunk, int cls, int occ,
                     std::vector<Tile> &out, std::vector<Launch> &launches) {
@@ -601,22 +626,16 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
       launches.push_back(l);
     };
     int64_t xo = 0;
-    // one contraction tile class per batch (the largest any group needs): a
-    // second launch of a few tiles would serialise behind the first
-    int c2max = 0;
-    for (size_t k = gi; k < gj; ++k) c2max = std::max(c2max, groups[k].p2cls);
     int64_t po = 0;
     Launch red;
-    red.cls = c2max;
     red.start = int(redjobs.size());
     for (size_t k = gi; k < gj; ++k) {
       GroupRec &R = groups[k];
-      R.p2cls = c2max;
       R.g.xoff = xo;
       xo += align_up(R.region, 32);
       const int gid = int(p2.size());
-      const int c2 = R.p2cls;
-      const int tm = (R.g.n_ij + kP2BM[c2] - 1) / kP2BM[c2], tn = (R.g.ncols + kP2BN[c2] - 1) / kP2BN[c2];
+      const int bm2 = 16 * R.g.fm;
+      const int tm = (R.g.n_ij + bm2 - 1) / bm2, tn = (R.g.ncols + kP2BN - 1) / kP2BN;
       R.g.tiles_n = tn;
       R.g.part_off = po;
       if (R.g.n_ij > 0 && R.g.ncols > 0) {
@@ -624,26 +643,28 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           for (int b = 0; b < tn; ++b) {
             for (int ks = 0; ks < R.g.nsplit; ++ks) {
               const int len = std::min(R.g.kseg, R.g.ktab_len - ks * R.g.kseg);
-              t2[c2].push_back({int64_t(len) + 1, Tile{gid, a, b, ks}});
+              t2[0].push_back({int64_t(len) * R.g.fm + 1, Tile{gid, a, b, ks}});
             }
-            if (R.g.nsplit > 1 || c2 == 2) redjobs.push_back(Tile{gid, a, b, 0});
+            if (R.g.nsplit > 1) redjobs.push_back(Tile{gid, a, b, 0});
           }
-        if (R.g.nsplit > 1 || c2 == 2) po += int64_t(tm) * tn * R.g.nsplit * 2 * kP2BM[c2] * kP2BN[c2];
+        if (R.g.nsplit > 1) po += int64_t(tm) * tn * R.g.nsplit * 2 * bm2 * kP2BN;
       }
       p2.push_back(R.g);
       const int c1 = P.sys[R.sys].p1cls;
       const bool mixed = P.precision == CDCC_MIXED;
+      const int bm = mixed ? kMixBM[c1] : kP1BM[c1], bn = mixed ? kMixBN[c1] : kP1BN[c1];
+      const int stm = st_m[c1], stn = st_n[c1];
       for (P1Desc d : R.descs) {
         d.xoff = R.g.xoff;
         const int did = int(p1.size());
         p1.push_back(d);
-        const int bm = mixed ? kMixBM[c1] : kP1BM[c1], bn = mixed ? kMixBN[c1] : kP1BN[c1];
         const int tm = (d.M + bm - 1) / bm, tn = (d.N + bn - 1) / bn;
-        // 4 x 8 supertiles: neighbours share operand rows in one XCD's L2
-        for (int sa = 0; sa < tm; sa += 4)
-          for (int sb = 0; sb < tn; sb += 8)
-            for (int a = sa; a < std::min(tm, sa + 4); ++a)
-              for (int b = sb; b < std::min(tn, sb + 8); ++b) {
+        // stm x stn supertiles, one XCD's worth of concurrent tiles: they
+        // share stm*bm A rows and stn*bn B rows in that XCD's L2
+        for (int sa = 0; sa < tm; sa += stm)
+          for (int sb = 0; sb < tn; sb += stn)
+            for (int a = sa; a < std::min(tm, sa + stm); ++a)
+              for (int b = sb; b < std::min(tn, sb + stn); ++b) {
                 if (d.tri) {  // skip tiles that lie entirely above the a>=b triangle
                   const int n0 = b * bn, n1 = std::min(d.N, n0 + bn) - 1;
                   const int minb = (n0 / d.nb == n1 / d.nb) ? n0 % d.nb : 0;
@@ -660,8 +681,8 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     B.red = red;
     const bool mixedp = P.precision == CDCC_MIXED;
     for (int c = 0; c < 4; ++c)
-      emit(t1[c], 32, c, mixedp ? occupancy_mixed(c) : occupancy_f64(0, c), p1tiles, B.p1);
-    for (int c = 0; c < 3; ++c) emit(t2[c], 8, c, occupancy_f64(1, c), p2tiles, B.p2);
+      emit(t1[c], st_chunk[c], c, mixedp ? occupancy_mixed(c) : occupancy_f64(0, c), p1tiles, B.p1);
+    emit(t2[0], 8, 0, occupancy_f64(1, 0), p2tiles, B.p2);
     P.batches.push_back(std::move(B));
     gi = gj;
   }
@@ -858,9 +879,9 @@ int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, 
     {
       Span sp(3, int(B.p2.size()), stream);
       for (const Launch &l : B.p2)
-        HIPCHK(launch_contract_f64(l.cls, l.grid, P->p2, P->p2tiles + l.start, l.q, counters + 8 * ci++, dsp, xbuf,
+        HIPCHK(launch_contract_f64(l.grid, P->p2, P->p2tiles + l.start, l.q, counters + 8 * ci++, dsp, xbuf,
                                    P->ktab, P->ijtab, P->vvtab, part, stream));
-      HIPCHK(launch_reduce_unpack(B.red.cls, B.red.count, P->p2, P->redjobs + B.red.start, dsp, part, P->ijtab,
+      HIPCHK(launch_reduce_unpack(B.red.count, P->p2, P->redjobs + B.red.start, dsp, part, P->ijtab,
                                   P->vvtab, stream));
     }
   }

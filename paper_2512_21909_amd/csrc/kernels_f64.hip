@@ -28,31 +28,48 @@ __global__ void fill_int_kernel(int *p, int n, int v) {
 }
 
 // ---------------------------------------------------------------------------
-// pack: one workgroup per packed row (i>=j) of one (system, G).
+// pack: one workgroup per 64 x 64 tile of (packed row i>=j, packed column
+// c>=d) of one (system, G).
 //   tauhat(+)_ij^cd = X_ij^cd + X_ij^dc   (c>d),   X_ij^cc   (c=d)
 //   tauhat(-)_ij^cd = X_ij^cd - X_ij^dc   (c>d),   0         (c=d or i=j)
+// The halves are stored column-major (element (r, k) at k * nrow + r) for
+// the contraction; the tile is read along rows of X and written along
+// columns of tauhat through LDS, so both sides are coalesced.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void pack_kernel(const PackJob *__restrict__ jobs,
-                                                   const int2 *__restrict__ rows,
+                                                   const int2 *__restrict__ tiles,
                                                    const SysPtrs *__restrict__ sp,
                                                    const int4 *__restrict__ ijtab,
                                                    const int4 *__restrict__ vvtab) {
-  const int2 jr = rows[blockIdx.x];
-  const PackJob J = jobs[jr.x];
-  const int r = jr.y;
+  __shared__ double lp[64][65], lm[64][65];
+  const int2 jt = tiles[blockIdx.x];
+  const PackJob J = jobs[jt.x];
+  const int nkb = (J.ncol + 63) / 64;
+  const int r0 = (jt.y / nkb) * 64, k0 = (jt.y % nkb) * 64;
   const SysPtrs S = sp[J.sys];
-  const int4 ij = ijtab[J.ij_off + r];
-  const bool diag_ij = ij.x == ij.y;
-  const double *__restrict__ xr = S.X + J.x_off + int64_t(ij.x) * J.ldx;
-  double *__restrict__ tp = S.tauhat + J.th_off + int64_t(r) * J.ncol;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int k = k0 + tx;
+  int4 cd = int4{0, 0, 0, 0};
+  if (k < J.ncol) cd = vvtab[J.vv_off + k];
+  const bool dcd = cd.x == cd.y;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int r = r0 + rr;
+    if (r >= J.nrow || k >= J.ncol) continue;
+    const int4 ij = ijtab[J.ij_off + r];
+    const double *__restrict__ xr = S.X + J.x_off + int64_t(ij.x) * J.ldx;
+    const double x1 = xr[cd.x], x2 = xr[cd.y];
+    lp[rr][tx] = dcd ? x1 : x1 + x2;
+    lm[rr][tx] = (dcd || ij.x == ij.y) ? 0.0 : x1 - x2;
+  }
+  __syncthreads();
+  double *__restrict__ tp = S.tauhat + J.th_off;
   double *__restrict__ tm = tp + int64_t(J.nrow) * J.ncol;
-  for (int k = threadIdx.x; k < J.ncol; k += blockDim.x) {
-    const int4 cd = vvtab[J.vv_off + k];
-    const double x1 = xr[cd.x];
-    const double x2 = xr[cd.y];
-    const bool dcd = cd.x == cd.y;
-    tp[k] = dcd ? x1 : x1 + x2;
-    tm[k] = (dcd || diag_ij) ? 0.0 : x1 - x2;
+  const int r = r0 + tx;
+  for (int kk = ty; kk < 64; kk += 4) {
+    const int kc = k0 + kk;
+    if (r >= J.nrow || kc >= J.ncol) continue;
+    tp[int64_t(kc) * J.nrow + r] = lp[tx][kk];
+    tm[int64_t(kc) * J.nrow + r] = lm[tx][kk];
   }
 }
 
@@ -256,182 +273,237 @@ __device__ __forceinline__ void unpack_store(const SysPtrs &S, const P2Group &g,
 // ---------------------------------------------------------------------------
 // contract (FP64): S = tauhat(+) W(+), A = tauhat(-) W(-) over the K table of
 // the group (entries: tauhat column, X rows of (c,d) and (d,c), -1 = absent).
-// Tile BM x BN of (packed ij) x (group columns); 2x2 waves; both products
-// share the staged X rows; double-buffered LDS, one barrier per K step.
-// Epilogue writes R (and R/D) at the four permutations (ij,ab),
-// (ij,ba) = S-A, (ji,ab) = S-A, (ji,ba) = S+A.
+// One workgroup of four waves per tile of 16*FM packed (ij) rows x 32 group
+// columns.  The waves take interleaved K steps of four table entries (wave w:
+// steps w, w+4, ...) and stream their operands from global memory straight
+// into MFMA registers: tauhat is stored column-major (k-major), so a lane
+// quarter reads 16 consecutive rows of one column; the X rows of (c,d) and
+// (d,c) are summed and subtracted in registers.  A ring of NS stages keeps
+// table entries 2*NS steps and data NS steps ahead; the K loop has no LDS
+// traffic and no barrier.  The four partial sums are combined in LDS in the
+// fixed order (w0 + w2) + (w1 + w3), so every element depends only on the
+// group's K table and segment length, never on the tile shape.
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int NT, bool PARTIAL>
-__global__ __launch_bounds__(NT) void contract_f64_kernel(const P2Group *__restrict__ groups,
-                                                           const Tile *__restrict__ tiles, Queues Q,
-                                                           int *__restrict__ cnt,
-                                                           const SysPtrs *__restrict__ sp,
-                                                           const double *__restrict__ xbuf,
-                                                           const int4 *__restrict__ ktab,
-                                                           const int4 *__restrict__ ijtab,
-                                                           const int4 *__restrict__ vvtab,
-                                                           double *__restrict__ part) {
-  constexpr int BK = 16;
-  constexpr int NW = NT / 64;                // waves: 2 along M, NW/2 along N
-  constexpr int WM = BM / 2, WN = BN / (NW / 2);
-  constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int EPT = BM * BK / NT;          // A elements per thread (one row, EPT consecutive k)
-  constexpr int TPR = BK / EPT;              // threads per A row
-  constexpr int CB = BN * BK / NT;           // B columns per thread (one k row)
-  constexpr int TPK = BN / CB;               // threads per B k row
-  constexpr int LA = BM + 2, LB = BN + 2;
-  static_assert(EPT >= 1 && BK % EPT == 0 && CB >= 1 && FN >= 1, "staging");
-  __shared__ double Ap[2][BK][LA], Am[2][BK][LA];
-  __shared__ double Bp[2][BK][LB], Bm[2][BK][LB];
+constexpr int kCtBN = 32;                     // group columns per tile
+constexpr int kCtMaxBM = 64;                  // rows per tile for FM = 4
+
+// prefetch stages: fewer for the widest tile, whose accumulators take half
+// of the 256 registers a wave has at two waves per SIMD
+template <int FM>
+struct CtStages {
+  static constexpr int value = FM == 4 ? 2 : 4;
+};
+
+template <int FM>
+__device__ __forceinline__ void contract_tile(const P2Group &g, const Tile &tl, const SysPtrs &S,
+                                              const double *__restrict__ xbuf, const int4 *__restrict__ ktab,
+                                              const int4 *__restrict__ ijtab, const int4 *__restrict__ vvtab,
+                                              double *__restrict__ part, double (*red)[2 * kCtMaxBM * kCtBN]) {
+  constexpr int FN = 2, BN = kCtBN, BM = 16 * FM, NS = CtStages<FM>::value;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int kq = lane >> 4, li = lane & 15;
+  const int m0 = tl.tm * BM, n0 = tl.tn * BN;
+  const int kbeg = tl.aux * g.kseg;
+  const int klen = g.nsplit > 1 ? (g.ktab_len - kbeg < g.kseg ? g.ktab_len - kbeg : g.kseg) : g.ktab_len;
+  const int ns = klen / 16;  // K steps of each wave (segments are multiples of 16 entries)
+  const CDCC_GLOBAL int *gkt = as_global(reinterpret_cast<const int *>(ktab + g.ktab_off + kbeg));
+  const CDCC_GLOBAL double *thp = as_global(S.tauhat) + g.th_off;  // [kcol][n_ij]
+  const CDCC_GLOBAL double *thm = thp + int64_t(g.n_ij) * g.th_ld;
+  const CDCC_GLOBAL double *gx = as_global(xbuf) + g.xoff;
+
+  // rows and columns past the tile's edge read clamped addresses; they only
+  // feed result rows / columns that are never stored, so need no mask
+  int rowc[FM], colc[FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int m = m0 + 16 * i + li;
+    rowc[i] = m < g.n_ij ? m : g.n_ij - 1;
+  }
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int n = n0 + 16 * j + li;
+    colc[j] = n < g.ncols ? n : g.ncols - 1;
+  }
+
+  d4 accS[FM][FN], accA[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      accS[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accA[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  if (ns > 0) {
+    int kc[NS], r1[NS], r2[NS], fl[NS];
+    double ap[NS][FM], am[NS][FM], x1[NS][FN], x2[NS][FN];
+    // raw table entry of this lane for wave step s (index clamped into the
+    // segment); the values are not touched here, so the loads stay in flight
+    auto ktload = [&](int q, int s) {
+      const int e0 = 4 * (4 * s + w) + kq;
+      const int e = e0 < klen ? e0 : klen - 1;
+      kc[q] = gkt[4 * e];
+      r1[q] = gkt[4 * e + 1];
+      r2[q] = gkt[4 * e + 2];
+    };
+    // operands of wave step s, whose entry is in slot q, from clamped
+    // addresses; which of them are present is kept in fl[q] and applied
+    // when they are used, so no instruction waits on these loads until then
+    // (steps past the end load but count as absent)
+    auto dload = [&](int q, int s) {
+      const bool in = s < ns;
+      fl[q] = ((in && kc[q] >= 0) ? 1 : 0) | ((in && r1[q] >= 0) ? 2 : 0) | ((in && r2[q] >= 0) ? 4 : 0);
+      const int64_t ko = int64_t(kc[q] >= 0 ? kc[q] : 0) * g.n_ij;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        ap[q][i] = thp[ko + rowc[i]];
+        am[q][i] = thm[ko + rowc[i]];
+      }
+      const int64_t o1 = int64_t(r1[q] >= 0 ? r1[q] : 0) * g.ldx, o2 = int64_t(r2[q] >= 0 ? r2[q] : 0) * g.ldx;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        x1[q][j] = gx[o1 + colc[j]];
+        x2[q][j] = gx[o2 + colc[j]];
+      }
+    };
+    auto mfma = [&](int q) {
+      // an empty asm that takes and returns each loaded value: the wait for
+      // these loads lands here, and no arithmetic on them is moved above it
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        __asm__ volatile("" : "+v"(ap[q][i]));
+        __asm__ volatile("" : "+v"(am[q][i]));
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        __asm__ volatile("" : "+v"(x1[q][j]));
+        __asm__ volatile("" : "+v"(x2[q][j]));
+      }
+      const bool ha = fl[q] & 1, h1 = fl[q] & 2, h2 = fl[q] & 4;
+      double fa[FM], fb[FM], bp[FN], bmv[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        fa[i] = ha ? ap[q][i] : 0.0;
+        fb[i] = ha ? am[q][i] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const double v1 = h1 ? x1[q][j] : 0.0, v2 = h2 ? x2[q][j] : 0.0;
+        bp[j] = v1 + v2;
+        bmv[j] = v1 - v2;
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          accS[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], bp[j], accS[i][j], 0, 0, 0);
+          accA[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[i], bmv[j], accA[i][j], 0, 0, 0);
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      ktload(q, q);
+      fl[q] = 0;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) ap[q][i] = am[q][i] = 0.0;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) x1[q][j] = x2[q][j] = 0.0;
+    }
+    // stage q holds data of step s0 + q and the table entry of step
+    // s0 + q + NS.  The first pass (s0 = -NS) only loads; the ring starts
+    // from registers, not loads, so the compiler keeps the loads of a pass
+    // in flight across the next one.  Steps past the end are zero.
+    for (int s0 = -NS; s0 < ns; s0 += NS) {
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        if (s0 >= 0) mfma(q);
+        dload(q, s0 + q + NS);
+        ktload(q, s0 + q + 2 * NS);
+        // compiler-only barrier: keeps the optimiser from turning the
+        // loop-carried loaded values into loads at the top of the next pass
+        // and the scheduler from hoisting a later stage's address
+        // arithmetic (which waits for its table entry) above this stage
+        __asm__ volatile("" ::: "memory");
+      }
+    }
+  }
+
+  // fixed-order combination of the four wave partials through LDS
+  auto put = [&](double *dst) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = (16 * i + kq + 4 * r) * BN + 16 * j + li;
+          dst[e] = accS[i][j][r];
+          dst[BM * BN + e] = accA[i][j][r];
+        }
+  };
+  auto add = [&](const double *src) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = (16 * i + kq + 4 * r) * BN + 16 * j + li;
+          accS[i][j][r] += src[e];
+          accA[i][j][r] += src[BM * BN + e];
+        }
+  };
+  if (w >= 2) put(red[w - 2]);
+  __syncthreads();
+  if (w < 2) add(red[w]);
+  __syncthreads();
+  if (w == 1) put(red[0]);
+  __syncthreads();
+  if (w == 0) {
+    add(red[0]);
+    put(red[1]);
+  }
+  __syncthreads();
+
+  const double *fin = red[1];
+  if (g.nsplit > 1) {
+    // this segment's S and A partials; the reduce kernel sums the segments
+    // in order and unpacks
+    double *__restrict__ pb = part + g.part_off + (int64_t(tl.tm * g.tiles_n + tl.tn) * g.nsplit + tl.aux) * (2 * BM * BN);
+    for (int e = tid; e < 2 * BM * BN; e += 256) pb[e] = fin[e];
+    return;
+  }
+  for (int e = tid; e < BM * BN; e += 256) {
+    const int lm = e / BN, ln = e - lm * BN;
+    const int m = m0 + lm, n = n0 + ln;
+    if (m >= g.n_ij || n >= g.ncols) continue;
+    unpack_store(S, g, m, n, fin[e], fin[BM * BN + e], ijtab, vvtab);
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void contract_f64_kernel(const P2Group *__restrict__ groups,
+                                                              const Tile *__restrict__ tiles, Queues Q,
+                                                              int *__restrict__ cnt,
+                                                              const SysPtrs *__restrict__ sp,
+                                                              const double *__restrict__ xbuf,
+                                                              const int4 *__restrict__ ktab,
+                                                              const int4 *__restrict__ ijtab,
+                                                              const int4 *__restrict__ vvtab,
+                                                              double *__restrict__ part) {
+  __shared__ double red[2][2 * kCtMaxBM * kCtBN];
   __shared__ int s_tile;
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int lr = tid / TPR, lk = (tid % TPR) * EPT;  // A staging
-  const int bk = tid / TPK, bc = (tid % TPK) * CB;   // B staging
   int tries = 0;
-
   for (;;) {
     const int t = next_tile(cnt, Q, tries, &s_tile);
     if (t < 0) break;
     const Tile tl = tiles[t];
     const P2Group g = groups[tl.desc];
     const SysPtrs S = sp[g.sys];
-    const int m0 = tl.tm * BM, n0 = tl.tn * BN;
-    const CDCC_GLOBAL double *gthp = as_global(S.tauhat) + g.th_off;
-    const CDCC_GLOBAL double *gthm = gthp + int64_t(g.n_ij) * g.th_ld;
-    const CDCC_GLOBAL double *gxr = as_global(xbuf) + g.xoff;
-    // K segment of this tile (the whole table unless the group is split)
-    const int kbeg = tl.aux * g.kseg;
-    const int klen = (g.nsplit > 1 ? (g.ktab_len - kbeg < g.kseg ? g.ktab_len - kbeg : g.kseg) : g.ktab_len);
-    const CDCC_GLOBAL int *gkt = as_global(reinterpret_cast<const int *>(ktab + g.ktab_off + kbeg));  // int4 entries
-
-    d4 accS[FM][FN], accA[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        accS[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-        accA[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      }
-
-    const int r = m0 + lr;
-    const int64_t arow = int64_t(r < g.n_ij ? r : g.n_ij - 1) * g.th_ld;
-    const double rm = r < g.n_ij ? 1.0 : 0.0;
-    double rap[EPT], ram[EPT], rbp[CB], rbm[CB];
-    // K-table entries are fetched one stage ahead of the data they index
-    int kcA[EPT], r1B, r2B;
-    auto kload = [&](int k0) {
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) kcA[e] = gkt[4 * (k0 + lk + e)];
-      r1B = gkt[4 * (k0 + bk) + 1];
-      r2B = gkt[4 * (k0 + bk) + 2];
-    };
-    // branch-free staging: clamped indices, masked by a multiply
-    auto gload = [&]() {
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int kc = kcA[e];
-        const double mk = kc >= 0 ? rm : 0.0;
-        const int64_t off = arow + (kc >= 0 ? kc : 0);
-        rap[e] = gthp[off] * mk;
-        ram[e] = gthm[off] * mk;
-      }
-      const double m1 = r1B >= 0 ? 1.0 : 0.0, m2 = r2B >= 0 ? 1.0 : 0.0;
-      const int64_t o1 = int64_t(r1B >= 0 ? r1B : 0) * g.ldx, o2 = int64_t(r2B >= 0 ? r2B : 0) * g.ldx;
-#pragma unroll
-      for (int e = 0; e < CB; ++e) {
-        const int n = n0 + bc + e;
-        const int nc = n < g.ncols ? n : g.ncols - 1;
-        const double nm = n < g.ncols ? 1.0 : 0.0;
-        const double x1 = gxr[o1 + nc] * (m1 * nm);
-        const double x2 = gxr[o2 + nc] * (m2 * nm);
-        rbp[e] = x1 + x2;
-        rbm[e] = x1 - x2;
-      }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        Ap[buf][lk + e][lr] = rap[e];
-        Am[buf][lk + e][lr] = ram[e];
-      }
-#pragma unroll
-      for (int e = 0; e < CB; ++e) {
-        Bp[buf][bk][bc + e] = rbp[e];
-        Bm[buf][bk][bc + e] = rbm[e];
-      }
-    };
-
-    const int nk = klen / BK;
-    if (nk > 0) {
-      kload(0);
-      gload();
-      lstore(0);
-      kload((nk > 1 ? 1 : 0) * BK);
-    }
-    __syncthreads();
-    for (int kb = 0; kb < nk; ++kb) {
-      const int cur = kb & 1;
-      gload();                                       // stage kb+1 (redundant on the last step)
-      kload((kb + 2 < nk ? kb + 2 : nk - 1) * BK);   // table entries of stage kb+2
-#pragma unroll
-      for (int ks = 0; ks < BK / 4; ++ks) {
-        const int kr = ks * 4 + (lane >> 4);
-        double fap[FM], fam[FM], fbp[FN], fbm[FN];
-#pragma unroll
-        for (int i = 0; i < FM; ++i) {
-          fap[i] = Ap[cur][kr][wm * WM + i * 16 + (lane & 15)];
-          fam[i] = Am[cur][kr][wm * WM + i * 16 + (lane & 15)];
-        }
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          fbp[j] = Bp[cur][kr][wn * WN + j * 16 + (lane & 15)];
-          fbm[j] = Bm[cur][kr][wn * WN + j * 16 + (lane & 15)];
-        }
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int j = 0; j < FN; ++j) {
-            accS[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fap[i], fbp[j], accS[i][j], 0, 0, 0);
-            accA[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fam[i], fbm[j], accA[i][j], 0, 0, 0);
-          }
-      }
-      lstore(cur ^ 1);
-      __syncthreads();
-    }
-
-    if (PARTIAL || g.nsplit > 1) {
-      // store this segment's S and A partials; the reduce kernel sums the
-      // segments in order and unpacks (PARTIAL: always, to keep the unpack
-      // epilogue out of this kernel's register budget)
-      double *__restrict__ pb =
-          part + g.part_off + (int64_t(tl.tm * g.tiles_n + tl.tn) * g.nsplit + tl.aux) * (2 * BM * BN);
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const int lm = wm * WM + i * 16 + (lane >> 4) + 4 * rr;
-            const int ln = wn * WN + j * 16 + (lane & 15);
-            pb[lm * BN + ln] = accS[i][j][rr];
-            pb[BM * BN + lm * BN + ln] = accA[i][j][rr];
-          }
-      continue;
-    }
-    if constexpr (!PARTIAL) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * rr;
-            const int n = n0 + wn * WN + j * 16 + (lane & 15);
-            if (m >= g.n_ij || n >= g.ncols) continue;
-            unpack_store(S, g, m, n, accS[i][j][rr], accA[i][j][rr], ijtab, vvtab);
-          }
+    switch (g.fm) {
+      case 1: contract_tile<1>(g, tl, S, xbuf, ktab, ijtab, vvtab, part, red); break;
+      case 2: contract_tile<2>(g, tl, S, xbuf, ktab, ijtab, vvtab, part, red); break;
+      case 3: contract_tile<3>(g, tl, S, xbuf, ktab, ijtab, vvtab, part, red); break;
+      default: contract_tile<4>(g, tl, S, xbuf, ktab, ijtab, vvtab, part, red); break;
     }
   }
 }
@@ -440,7 +512,6 @@ __global__ __launch_bounds__(NT) void contract_f64_kernel(const P2Group *__restr
 // reduce (split K): one workgroup per contraction tile; S and A summed over
 // the K segments in segment order, then the same unpack as above.
 // ---------------------------------------------------------------------------
-template <int BM, int BN>
 __global__ __launch_bounds__(256) void reduce_unpack_kernel(const P2Group *__restrict__ groups,
                                                             const Tile *__restrict__ jobs,
                                                             const SysPtrs *__restrict__ sp,
@@ -450,6 +521,7 @@ __global__ __launch_bounds__(256) void reduce_unpack_kernel(const P2Group *__res
   const Tile tl = jobs[blockIdx.x];
   const P2Group g = groups[tl.desc];
   const SysPtrs S = sp[g.sys];
+  const int BM = 16 * g.fm, BN = kCtBN;
   const double *__restrict__ pb =
       part + g.part_off + int64_t(tl.tm * g.tiles_n + tl.tn) * g.nsplit * (2 * BM * BN);
   for (int e = threadIdx.x; e < BM * BN; e += 256) {
@@ -464,7 +536,6 @@ __global__ __launch_bounds__(256) void reduce_unpack_kernel(const P2Group *__res
     unpack_store(S, g, m, n, sv, av, ijtab, vvtab);
   }
 }
-
 // ---------------------------------------------------------------------------
 // pair energies: one workgroup per amplitude row (i,j); fixed-order tree.
 // ---------------------------------------------------------------------------
@@ -522,34 +593,18 @@ hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Til
   return hipGetLastError();
 }
 
-// Contraction tile classes: 0 = 32 x 64, 1 = 64 x 64 (LDS kernel, unpack in
-// the epilogue unless split), 2 = 128 x 64 (always through the partial buffer).
-hipError_t launch_contract_f64(int cls, int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,
+hipError_t launch_contract_f64(int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,
                                const SysPtrs *sp, const double *xbuf, const int4 *ktab, const int4 *ijtab,
                                const int4 *vvtab, double *part, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  switch (cls) {
-    case 0:
-      contract_f64_kernel<32, 64, 256, false><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part);
-      break;
-    case 1:
-      contract_f64_kernel<64, 64, 256, false><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part);
-      break;
-    default:
-      contract_f64_kernel<128, 64, 256, true><<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part);
-      break;
-  }
+  contract_f64_kernel<<<grid, 256, 0, s>>>(groups, tiles, Q, cnt, sp, xbuf, ktab, ijtab, vvtab, part);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_unpack(int cls, int njobs, const P2Group *groups, const Tile *jobs, const SysPtrs *sp,
+hipError_t launch_reduce_unpack(int njobs, const P2Group *groups, const Tile *jobs, const SysPtrs *sp,
                                 const double *part, const int4 *ijtab, const int4 *vvtab, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  switch (cls) {
-    case 0: reduce_unpack_kernel<32, 64><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
-    case 1: reduce_unpack_kernel<64, 64><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
-    default: reduce_unpack_kernel<128, 64><<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab); break;
-  }
+  reduce_unpack_kernel<<<njobs, 256, 0, s>>>(groups, jobs, sp, part, ijtab, vvtab);
   return hipGetLastError();
 }
 
@@ -562,9 +617,7 @@ int occupancy_f64(int which, int cls) {
     else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 64>, 256, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 128>, 256, 0);
   } else {
-    if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<32, 64, 256, false>, 256, 0);
-    else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<64, 64, 256, false>, 256, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel<128, 64, 256, true>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, contract_f64_kernel, 256, 0);
   }
   return (e == hipSuccess && n > 0) ? n : 1;
 }

@@ -64,6 +64,8 @@ struct P2Group {
   int32_t kseg;        // K-table entries per split-K segment (multiple of 16)
   int32_t nsplit;      // number of K segments (1: the tile writes R itself)
   int32_t tiles_n;     // column tiles of the group (partial-block numbering)
+  int32_t fm;          // 16-row MFMA fragments per contraction tile (tile rows = 16 fm)
+  int32_t pad0;
   int64_t xoff;        // X region in the batch buffer
   int64_t th_off;      // tauhat(+) offset; (-) at th_off + n_ij * th_ld
   int64_t r_off;       // amp_off[G]
