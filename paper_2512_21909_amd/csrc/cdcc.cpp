@@ -415,12 +415,13 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
         J.vv_off = vv_off[G];
         J.x_off = L.amp_off[G];
         J.th_off = SP.th_elems;
+        J.ldt = int(align_up(nr, 16));  // k-major tauhat: 128-byte columns
         const int jid = int(packjobs.size());
         packjobs.push_back(J);
         // 64 x 64 (row, column) tiles, numbered rb * column_tiles + kb
         const int nrb = int((nr + 63) / 64), nkb = int((ncl + 63) / 64);
         for (int t = 0; t < nrb * nkb; ++t) packrows.push_back(int2{jid, t});
-        SP.th_elems += 2 * nr * ncl;
+        SP.th_elems += 2 * int64_t(J.ldt) * ncl;
       }
       if (probs[s].pair_energy)
         for (int gi = 0; gi < h; ++gi) {
@@ -514,7 +515,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           g.G = G;
           g.n_ij = int(n_ij);
           g.ncols = int(ncols_of(a0, a1));
-          g.ldx = g.ncols;
+          g.ldx = int(align_up(g.ncols, 16));  // 128-byte rows: whole cache lines per MFMA fragment
           g.ktab_len = kt_len;
           g.ktab_off = kt_off;
           g.ij_off = ij_off[G];
@@ -522,11 +523,12 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           g.ldr = int(L.n_vv[G]);
           g.th_ld = int(L.n_vv_pk[G]);
           g.th_off = th_off[G];
+          g.th_rs = int(align_up(n_ij, 16));
           g.r_off = L.amp_off[G];
           g.nsplit = std::max(1, (kt_len + kKSeg / 2) / kKSeg);
           g.kseg = ((kt_len + g.nsplit - 1) / g.nsplit + 15) / 16 * 16;
           if (g.nsplit > 1) g.nsplit = (kt_len + g.kseg - 1) / g.kseg;
-          R.region = nrows * g.ncols;
+          R.region = nrows * g.ldx;
           g.fm = contract_fm(int(n_ij));
           // assembly GEMMs
           const int bm = mixed ? kMixBM[SP.p1cls] : kP1BM[SP.p1cls];
@@ -689,7 +691,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
   P.np1 = int(p1.size());
   int nl = 0;
   for (auto &b : P.batches) nl += int(b.p1.size() + b.p2.size());
-  P.ncounters = 8 * nl;
+  P.ncounters = 8 * nl * kQueueStride;
 
   // upload all tables in one allocation
   TableBuilder T;
@@ -869,7 +871,7 @@ int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, 
     {
       Span sp(2, int(B.p1.size()), stream);
       for (const Launch &l : B.p1) {
-        int *cnt = counters + 8 * ci++;
+        int *cnt = counters + 8 * kQueueStride * ci++;
         if (P->precision == CDCC_MIXED)
           HIPCHK(launch_assemble_mixed(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
         else
@@ -879,7 +881,7 @@ int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, 
     {
       Span sp(3, int(B.p2.size()), stream);
       for (const Launch &l : B.p2)
-        HIPCHK(launch_contract_f64(l.grid, P->p2, P->p2tiles + l.start, l.q, counters + 8 * ci++, dsp, xbuf,
+        HIPCHK(launch_contract_f64(l.grid, P->p2, P->p2tiles + l.start, l.q, counters + 8 * kQueueStride * ci++, dsp, xbuf,
                                    P->ktab, P->ijtab, P->vvtab, part, stream));
       HIPCHK(launch_reduce_unpack(B.red.count, P->p2, P->redjobs + B.red.start, dsp, part, P->ijtab,
                                   P->vvtab, stream));

@@ -16,23 +16,46 @@ __device__ __forceinline__ const CDCC_GLOBAL T *as_global(const T *p) {
   return (const CDCC_GLOBAL T *)(p);
 }
 
-// Claim the next tile (thread 0 only); returns -1 when every queue is empty.
-// `tries` persists across calls and counts the queues found empty.
-__device__ __forceinline__ int claim_tile(int *__restrict__ cnt, const Queues &Q, int xcd, int &tries) {
-  while (tries < 8) {
-    const int q = (xcd + tries) & 7;
-    const int i = atomicAdd(cnt + q, 1);
+// Claim the next tile; called by every lane of wave 0, the result is valid in
+// all of them (-1 when every queue is empty).  `dead` is per-workgroup state
+// (bit l: queue (xcd + l) % 8 known to be empty, in the XCD's stealing order).
+// A claim is one atomic on the first live queue; a failed claim marks that
+// queue dead, so a workgroup issues at most 8 failed atomics.  When its own
+// queue runs dry, the other seven counters are read at once and the queues
+// already drained are skipped (counters only grow, so a drained reading is
+// final; a stale one just costs an atomic).
+__device__ __forceinline__ int claim_tile(int *__restrict__ cnt, const Queues &Q, int xcd, unsigned &dead) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    if (dead == 0xffu) return -1;
+    const int l = __builtin_ctz(~dead);
+    const int q = (xcd + l) & 7;
+    int i = 0;
+    if (lane == 0) i = atomicAdd(cnt + q * kQueueStride, 1);
+    i = __builtin_amdgcn_readfirstlane(i);
     if (i < Q.qb[q + 1] - Q.qb[q]) return Q.qb[q] + i;
-    ++tries;
+    dead |= 1u << l;
+    if (l == 0) {
+      int e = 1;
+      if (lane < 8) {
+        const int qq = (xcd + lane) & 7;
+        e = __hip_atomic_load(cnt + qq * kQueueStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+            Q.qb[qq + 1] - Q.qb[qq];
+      }
+      dead |= unsigned(__ballot(e)) & 0xffu;
+    }
   }
-  return -1;
 }
 
-// Broadcast a tile index claimed by thread 0 to the workgroup.
-__device__ __forceinline__ int next_tile(int *__restrict__ cnt, const Queues &Q, int &tries, int *s_slot) {
-  if (threadIdx.x == 0) *s_slot = claim_tile(cnt, Q, int(blockIdx.x & 7), tries);
+// Claim a tile for the workgroup (wave 0 claims, LDS broadcasts); the result
+// is wave-uniform, so the tile's descriptors are read with scalar loads.
+__device__ __forceinline__ int next_tile(int *__restrict__ cnt, const Queues &Q, unsigned &dead, int *s_slot) {
+  if (threadIdx.x < 64) {
+    const int t = claim_tile(cnt, Q, int(blockIdx.x & 7), dead);
+    if (threadIdx.x == 0) *s_slot = t;
+  }
   __syncthreads();
-  const int t = *s_slot;
+  const int t = __builtin_amdgcn_readfirstlane(*s_slot);
   __syncthreads();
   return t;
 }

@@ -32,7 +32,7 @@ __global__ void fill_int_kernel(int *p, int n, int v) {
 // c>=d) of one (system, G).
 //   tauhat(+)_ij^cd = X_ij^cd + X_ij^dc   (c>d),   X_ij^cc   (c=d)
 //   tauhat(-)_ij^cd = X_ij^cd - X_ij^dc   (c>d),   0         (c=d or i=j)
-// The halves are stored column-major (element (r, k) at k * nrow + r) for
+// The halves are stored column-major (element (r, k) at k * ldt + r) for
 // the contraction; the tile is read along rows of X and written along
 // columns of tauhat through LDS, so both sides are coalesced.
 // ---------------------------------------------------------------------------
@@ -63,13 +63,13 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackJob *__restrict__ j
   }
   __syncthreads();
   double *__restrict__ tp = S.tauhat + J.th_off;
-  double *__restrict__ tm = tp + int64_t(J.nrow) * J.ncol;
+  double *__restrict__ tm = tp + int64_t(J.ldt) * J.ncol;
   const int r = r0 + tx;
   for (int kk = ty; kk < 64; kk += 4) {
     const int kc = k0 + kk;
     if (r >= J.nrow || kc >= J.ncol) continue;
-    tp[int64_t(kc) * J.nrow + r] = lp[tx][kk];
-    tm[int64_t(kc) * J.nrow + r] = lm[tx][kk];
+    tp[int64_t(kc) * J.ldt + r] = lp[tx][kk];
+    tm[int64_t(kc) * J.ldt + r] = lm[tx][kk];
   }
 }
 
@@ -132,10 +132,10 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = tid >> 2, lk = (tid & 3) * 4;
-  int tries = 0;
+  unsigned dead = 0;
 
   for (;;) {
-    const int t = next_tile(cnt, Q, tries, &s_tile);
+    const int t = next_tile(cnt, Q, dead, &s_tile);
     if (t < 0) break;
     const Tile tl = tiles[t];
     const P1Desc D = descs[tl.desc];
@@ -291,7 +291,7 @@ constexpr int kCtMaxBM = 64;                  // rows per tile for FM = 4
 // of the 256 registers a wave has at two waves per SIMD
 template <int FM>
 struct CtStages {
-  static constexpr int value = FM == 4 ? 2 : 4;
+  static constexpr int value = FM == 4 ? 2 : (FM == 3 ? 4 : (FM == 2 ? 6 : 8));
 };
 
 template <int FM>
@@ -307,8 +307,8 @@ __device__ __forceinline__ void contract_tile(const P2Group &g, const Tile &tl, 
   const int klen = g.nsplit > 1 ? (g.ktab_len - kbeg < g.kseg ? g.ktab_len - kbeg : g.kseg) : g.ktab_len;
   const int ns = klen / 16;  // K steps of each wave (segments are multiples of 16 entries)
   const CDCC_GLOBAL int *gkt = as_global(reinterpret_cast<const int *>(ktab + g.ktab_off + kbeg));
-  const CDCC_GLOBAL double *thp = as_global(S.tauhat) + g.th_off;  // [kcol][n_ij]
-  const CDCC_GLOBAL double *thm = thp + int64_t(g.n_ij) * g.th_ld;
+  const CDCC_GLOBAL double *thp = as_global(S.tauhat) + g.th_off;  // [kcol][th_rs]
+  const CDCC_GLOBAL double *thm = thp + int64_t(g.th_rs) * g.th_ld;
   const CDCC_GLOBAL double *gx = as_global(xbuf) + g.xoff;
 
   // rows and columns past the tile's edge read clamped addresses; they only
@@ -353,7 +353,7 @@ __device__ __forceinline__ void contract_tile(const P2Group &g, const Tile &tl, 
     auto dload = [&](int q, int s) {
       const bool in = s < ns;
       fl[q] = ((in && kc[q] >= 0) ? 1 : 0) | ((in && r1[q] >= 0) ? 2 : 0) | ((in && r2[q] >= 0) ? 4 : 0);
-      const int64_t ko = int64_t(kc[q] >= 0 ? kc[q] : 0) * g.n_ij;
+      const int64_t ko = int64_t(kc[q] >= 0 ? kc[q] : 0) * g.th_rs;
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         ap[q][i] = thp[ko + rowc[i]];
@@ -492,9 +492,9 @@ __global__ __launch_bounds__(256, 2) void contract_f64_kernel(const P2Group *__r
                                                               double *__restrict__ part) {
   __shared__ double red[2][2 * kCtMaxBM * kCtBN];
   __shared__ int s_tile;
-  int tries = 0;
+  unsigned dead = 0;
   for (;;) {
-    const int t = next_tile(cnt, Q, tries, &s_tile);
+    const int t = next_tile(cnt, Q, dead, &s_tile);
     if (t < 0) break;
     const Tile tl = tiles[t];
     const P2Group g = groups[tl.desc];

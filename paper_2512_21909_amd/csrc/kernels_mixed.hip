@@ -98,10 +98,10 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-  int tries = 0;
+  unsigned dead = 0;
 
   for (;;) {
-    const int t = next_tile(cnt, Q, tries, &s_tile);
+    const int t = next_tile(cnt, Q, dead, &s_tile);
     if (t < 0) break;
     const Tile tl = tiles[t];
     const P1Desc D = descs[tl.desc];

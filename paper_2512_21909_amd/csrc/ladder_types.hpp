@@ -26,7 +26,9 @@ struct SysPtrs {
 // Packing of X into the +/- halves for one (system, pair irrep G).
 struct PackJob {
   int32_t sys, nrow, ncol, ldx;   // nrow = n_oo_pk(G), ncol = n_vv_pk(G), ldx = n_vv(G)
-  int32_t ij_off, vv_off, pad0, pad1;
+  int32_t ij_off, vv_off;
+  int32_t ldt;                    // tauhat column stride (k-major halves, >= nrow)
+  int32_t pad1;
   int64_t x_off;                  // amp_off[G]
   int64_t th_off;                 // element offset of tauhat(+) in SysPtrs::tauhat; (-) follows
 };
@@ -65,9 +67,9 @@ struct P2Group {
   int32_t nsplit;      // number of K segments (1: the tile writes R itself)
   int32_t tiles_n;     // column tiles of the group (partial-block numbering)
   int32_t fm;          // 16-row MFMA fragments per contraction tile (tile rows = 16 fm)
-  int32_t pad0;
+  int32_t th_rs;       // tauhat column stride (k-major: element (ij, k) at k * th_rs + ij)
   int64_t xoff;        // X region in the batch buffer
-  int64_t th_off;      // tauhat(+) offset; (-) at th_off + n_ij * th_ld
+  int64_t th_off;      // tauhat(+) offset; (-) at th_off + th_rs * th_ld
   int64_t r_off;       // amp_off[G]
   int64_t part_off;    // first partial block of the group in the split-K buffer
 };
@@ -89,6 +91,11 @@ struct Tile {
 struct Queues {
   int32_t qb[9];
 };
+
+// Queue counters of one launch sit kQueueStride ints (256 bytes) apart, each
+// in a cache line of its own, so claims on different queues do not serialise
+// on one line.
+constexpr int kQueueStride = 64;
 
 
 // Lambda dressing of one (system, GP, Ga) block.
