@@ -24,6 +24,18 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // element k%8; B[k][j] in lane j + 32(k/8); result register r of lane l is
 // D[8(r/4) + 4(l/32) + r%4][l%32].
 
+// s_waitcnt immediate (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8): wait for vmcnt <= v and lgkmcnt <= l.
+constexpr int waitcnt_imm(int v, int l) { return (v & 15) | ((v >> 4) << 14) | (7 << 4) | (l << 8); }
+
+// One 16-byte chunk per lane from global memory straight into LDS: lane l
+// writes bytes [16 l, 16 l + 16) after the wave-uniform LDS pointer dst.
+// The copies are counted on vmcnt; the caller waits for them with explicit
+// s_waitcnt vmcnt and a barrier.
+__device__ __forceinline__ void lds_copy16(const CDCC_GLOBAL unsigned char *src, unsigned char *dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst), 16, 0, 0);
+}
+
 __device__ __forceinline__ uint16_t bf16_bits_exact(double v) {
   // v is a small integer times a power of two: exact in float and in BF16
   return uint16_t(__float_as_uint(float(v)) >> 16);
@@ -80,7 +92,16 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
 // ---------------------------------------------------------------------------
 // assemble (mixed): tile BM x BN, (BM/32) x (BN/WN) waves of 32 x WN (WN/32
 // blocks of 32x32 each).  An LDS row holds one 16-wide K block of all four
-// slices (128 B + 16 B pad); double-buffered, one barrier per K block.
+// slices of one operand row (128 B, eight 16-byte chunks).  Rows are copied
+// from global memory straight into LDS (global_load_lds_dwordx4) through a
+// ring of three stages (three LDS arrays, the K loop unrolled by three),
+// two K blocks ahead of the MFMAs, with one barrier per K block.  A copy instruction writes 64 consecutive 16-byte chunks, so
+// the chunk order inside a row is permuted on the source side (physical
+// chunk c of row r holds logical chunk c ^ ((r / 2) % 8)): the 16 rows a
+// 16-lane group of a fragment read touches then fall on 16 different
+// 16-byte bank groups of the 256-byte bank width.  Rows past the tile edge are read
+// clamped: they only reach results that are never stored.  The sign of the
+// subtracted part of the Lambda stack is applied to the B fragments.
 // ---------------------------------------------------------------------------
 template <int BM, int BN, int WN>
 __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_kernel(
@@ -88,12 +109,15 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
     const SysPtrs *__restrict__ sp, double *__restrict__ xbuf) {
   constexpr int NJ = WN / 32;                  // 32x32 output blocks per wave along N
   constexpr int WAVES_N = BN / WN, WAVES_M = BM / 32;
-  constexpr int NT = 64 * WAVES_M * WAVES_N;
-  constexpr int ROWB = 144;                    // bytes per LDS row
-  constexpr int CPT = (BM + BN) * 8 / NT;      // 16-byte chunks per thread per K block
-  constexpr int QA = BM * 8 / NT;              // the first QA chunks of a thread are A rows
-  static_assert((BM + BN) * 8 % NT == 0 && BM * 8 % NT == 0, "chunk split");
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2][(BM + BN) * ROWB];
+  constexpr int NW = WAVES_M * WAVES_N;
+  constexpr int ROWB = 128;                    // bytes per LDS row
+  constexpr int STAGE = (BM + BN) * ROWB;      // bytes per ring stage
+  constexpr int NI = (BM + BN) / (8 * NW);     // copy instructions per wave per K block (8 rows each)
+  static_assert((BM + BN) % (8 * NW) == 0, "staging");
+  __shared__ __attribute__((aligned(16))) unsigned char st0[STAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char st1[STAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char st2[STAGE];
+  unsigned char *const stage[3] = {st0, st1, st2};
   __shared__ int s_tile;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -108,26 +132,31 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
     const SysPtrs S = sp[D.sys];
     const int m0 = tl.tm * BM, n0 = tl.tn * BN;
     const int nkb = D.Kp / 16;
-    const int64_t rowstride = int64_t(D.Kp) * 4;  // uint16 per sliced row
+    const int64_t rowstride = int64_t(D.Kp) * 8;  // bytes per sliced row
 
-    // source of every staged chunk (clamped row) and whether it is real
-    const CDCC_GLOBAL u32x4 *src[CPT];
-    bool ok[CPT];
+    // source of the 16-byte chunk this lane copies in each instruction
+    const CDCC_GLOBAL unsigned char *src[NI];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int r = (tid >> 3) + (NT / 8) * q, part = tid & 7;
-      if (q < QA) {
-        const int m = m0 + r;
-        ok[q] = m < D.M;
-        src[q] = as_global(reinterpret_cast<const u32x4 *>(S.slices + D.a_soff + int64_t(ok[q] ? m : D.M - 1) * rowstride)) + part;
+    for (int i = 0; i < NI; ++i) {
+      const int r = (i * NW + wave) * 8 + (lane >> 3);
+      const int part = (lane & 7) ^ ((r >> 1) & 7);
+      const unsigned char *base;
+      if (r < BM) {
+        const int m = m0 + r < D.M ? m0 + r : D.M - 1;
+        base = reinterpret_cast<const unsigned char *>(S.slices + D.a_soff) + int64_t(m) * rowstride;
       } else {
-        const int n = n0 + (r - BM);
-        ok[q] = n < D.N;
-        const int nn = ok[q] ? n : D.N - 1;
-        const int dd = nn / D.nb, b = nn - dd * D.nb;
-        src[q] = as_global(reinterpret_cast<const u32x4 *>(S.slices + D.b_soff + (int64_t(b) * D.vd + dd) * rowstride)) + part;
+        const int n = n0 + (r - BM) < D.N ? n0 + (r - BM) : D.N - 1;
+        const int dd = n / D.nb, b = n - dd * D.nb;
+        base = reinterpret_cast<const unsigned char *>(S.slices + D.b_soff) + (int64_t(b) * D.vd + dd) * rowstride;
       }
+      src[i] = as_global(base) + part * 16;
     }
+    auto issue = [&](unsigned char *st, int kbr) {
+      const int kb = kbr < nkb ? kbr : nkb - 1;  // clamped: the last copies are redundant
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+        lds_copy16(src[i] + int64_t(kb) * ROWB, st + (i * NW + wave) * 8 * ROWB);
+    };
 
     f16v acc0[NJ], acc1[NJ];
     double tot[NJ][16];
@@ -138,26 +167,6 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
 #pragma unroll
       for (int r = 0; r < 16; ++r) tot[j][r] = 0.0;
     }
-
-    u32x4 pre[CPT];
-    auto gload = [&](int kbr) {
-      const int kb = kbr < nkb ? kbr : nkb - 1;  // clamped: the last prefetch is redundant
-      const unsigned flip = kb >= D.kneg_blk ? 0x80008000u : 0u;
-#pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        u32x4 v = src[q][int64_t(kb) * 8];
-        if (q >= QA) v ^= flip;
-        v &= ok[q] ? 0xffffffffu : 0u;
-        pre[q] = v;
-      }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int r = (tid >> 3) + (NT / 8) * q;
-        *reinterpret_cast<u32x4 *>(&lds[buf][r * ROWB + (tid & 7) * 16]) = pre[q];
-      }
-    };
     auto flush = [&]() {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -167,47 +176,69 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
         acc1[j] = f16v{};
       }
     };
-
-    if (nkb > 0) {
-      gload(0);
-      lstore(0);
-    }
-    __syncthreads();
+    // fragment byte offsets inside a stage: slice s of row r is logical
+    // chunk 2s + (lane >= 32)
+    const int hi = lane >> 5;
     const int arow = wm * 32 + (lane & 31);
-    const int koff = (lane >> 5) * 16;
-    // chunks of 16 K blocks (256 K); the inner loop is one basic block
-    for (int kc = 0; kc < nkb; kc += 16) {
-      const int kend = kc + 16 < nkb ? kc + 16 : nkb;
-      for (int kb = kc; kb < kend; ++kb) {
-        const unsigned char *L = lds[kb & 1];
-        gload(kb + 1);
-        bf8 a[4];
+    int aoff[4], boff[NJ][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      aoff[s] = arow * ROWB + (((2 * s + hi) ^ ((arow >> 1) & 7)) * 16);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int brow = BM + wn * WN + j * 32 + (lane & 31);
+        boff[j][s] = brow * ROWB + (((2 * s + hi) ^ ((brow >> 1) & 7)) * 16);
+      }
+    }
+
+    auto step = [&](const unsigned char *L, int kb) {
+      const unsigned flip = kb >= D.kneg_blk ? 0x80008000u : 0u;
+      bf8 a[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + aoff[s]));
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        bf8 b[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-          a[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + arow * ROWB + s * 32 + koff));
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int brow = BM + wn * WN + j * 32 + (lane & 31);
-          bf8 b[4];
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-            b[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + brow * ROWB + s * 32 + koff));
-          acc0[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], acc0[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[3], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[2], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[1], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[0], acc1[j], 0, 0, 0);
-        }
-        lstore((kb + 1) & 1);
-        __syncthreads();
+          b[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + boff[j][s]) ^ flip);
+        acc0[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], acc0[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], acc1[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], acc1[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc1[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], acc1[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], acc1[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[3], acc1[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[2], acc1[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[1], acc1[j], 0, 0, 0);
+        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[0], acc1[j], 0, 0, 0);
       }
-      flush();  // 256 K: keep the leading accumulator exact
+      if ((kb & 15) == 15 || kb == nkb - 1) flush();  // every 256 K: keep the leading accumulator exact
+    };
+
+    if (nkb > 0) {
+      issue(stage[0], 0);
+      issue(stage[1], 1);
     }
+    for (int kb = 0; kb < nkb; kb += 3) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (kb + q < nkb) {
+          // this wave's copies of block kb + q have landed once only the NI
+          // copies of the next block are in flight, and its fragment reads of
+          // the previous block are done; the barrier then makes every wave's
+          // copies visible and frees the stage read in the previous step
+          __builtin_amdgcn_s_waitcnt(waitcnt_imm(NI, 0));
+          __builtin_amdgcn_s_barrier();
+          __asm__ volatile("" ::: "memory");  // no LDS access moves above the barrier
+          issue(stage[(q + 2) % 3], kb + q + 2);
+          step(stage[q], kb + q);
+        }
+      }
+    }
+    // the redundant copies issued past the end must land before the stage
+    // memory is reused by the next tile
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
 
     // epilogue: scale and permuted store (same numbering as the FP64 path)
 #pragma unroll
