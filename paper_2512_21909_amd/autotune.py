@@ -99,7 +99,7 @@ def main():
         elif w == "d2h_medium_B":
             syms.append((S.sym_d2h_medium("B"), ("t2", "lambda")))
         elif w == "d2h_large":
-            syms.append((S.sym_d2h_large(), ("t2",)))
+            syms.append((S.sym_d2h_large(), ("t2", "lambda")))
         elif w == "serving_large":
             syms.append((S.sym_serving_large(), ("t2",)))
         elif w == "batch64":
