@@ -240,25 +240,38 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
     // memory is reused by the next tile
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
 
-    // epilogue: scale and permuted store (same numbering as the FP64 path)
+    // epilogue: scale and permuted store (same numbering as the FP64 path).
+    // Quotients by vc and nb come from a float reciprocal estimate and are
+    // corrected to the exact floor (the estimate is off by at most one).
+    const float rvc = 1.0f / float(D.vc), rnb = 1.0f / float(D.nb);
+    auto qdiv = [](int x, int d, float rd) {
+      int q = int(float(x) * rd);
+      while (q * d > x) --q;
+      while ((q + 1) * d <= x) ++q;
+      return q;
+    };
+    const CDCC_GLOBAL double *rs = as_global(S.rowscale);
+    const int mb = m0 + wm * 32 + 4 * (lane >> 5);
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
+    for (int j = 0; j < NJ; ++j) {
+      const int n = n0 + wn * WN + j * 32 + (lane & 31);
+      if (n >= D.N) continue;
+      const int dd = qdiv(n, D.nb, rnb), b = n - dd * D.nb;
+      const double sb = rs[D.b_scoff + int64_t(b) * D.vd + dd];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int m = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int n = n0 + wn * WN + j * 32 + (lane & 31);
-        if (m >= D.M || n >= D.N) continue;
-        const int am = m / D.vc, c = m - am * D.vc;
+        const int m = mb + 8 * (r >> 2) + (r & 3);
+        if (m >= D.M) continue;
+        const int am = qdiv(m, D.vc, rvc), c = m - am * D.vc;
         const int a = D.a_first + am;
-        const int dd = n / D.nb, b = n - dd * D.nb;
         if (D.tri && b > a) continue;
-        const double sa = S.rowscale[D.a_scoff + m];
-        const double sb = S.rowscale[D.b_scoff + int64_t(b) * D.vd + dd];
+        const double sa = rs[D.a_scoff + m];
         const int64_t xcol = D.tri ? (int64_t(a) * (a + 1) / 2 - int64_t(D.ga0) * (D.ga0 + 1) / 2 + b)
                                    : (int64_t(a - D.ga0) * D.vb + b);
         const int64_t xrow = D.xrow0 + int64_t(c) * D.vd + dd;
         xbuf[D.xoff + xrow * D.ldx + xcol] = 0.5 * (sa * sb) * tot[j][r];
       }
+    }
   }
 }
 
