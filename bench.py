@@ -29,10 +29,11 @@ sys.path.insert(0, ROOT)
 METRIC = "CD ladder residual TFLOP/s, FP64 vs split-precision at 1e-7; p50/p99 latency"
 PEAK = {"fp64": 78.6, "bf16": 2500.0}  # MI355X dense MFMA, TFLOP/s
 HBM_PEAK = 8000.0  # GB/s
-# HBM bytes of one assembly launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (x2.0 and
-# x1.0 copy-kernel calibration), per (workload, path); None until measured for
-# the current kernels.
-TRAFFIC = {}
+# Bytes one assembly launch moves between L2 and the memory fabric, from
+# rocprofv3 FETCH_SIZE + WRITE_SIZE per dispatch (scaled x2.0 and x1.0 by a
+# plain 256 MiB device copy), averaged over the T2 and Lambda launches of a
+# step; per (workload, path), for the kernels as committed (profiles/).
+TRAFFIC = {("d2h_medium", "mixed"): 2.8905e9, ("d2h_medium", "fp64"): 1.6339e9}
 
 
 def workload(name):
