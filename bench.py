@@ -293,7 +293,8 @@ def main():
         fa_ms, fa_n = f["kernels"].get("assemble", (0.0, 0))
         fa = flops_assemble * args.steps / max(fa_n, 1) / (fa_ms / max(fa_n, 1) * 1e-3) / 1e12 if fa_ms else 0.0
         line["roofline_fp64"] = {"bound": "mfma", "achieved": round(fa, 3), "peak": PEAK["fp64"],
-                                 "unit": "TFLOP/s", "frac": round(fa / PEAK["fp64"], 4)}
+                                 "unit": "TFLOP/s", "frac": round(fa / PEAK["fp64"], 4),
+                                 "traffic": TRAFFIC.get((args.workload, "fp64"))}
     if "fp64" in results and "mixed" in results:
         line["mixed_speedup_vs_fp64"] = results["mixed"]["tflops"] / results["fp64"]["tflops"]
     if args.serving:
