@@ -42,7 +42,8 @@ hipError_t launch_reduce_unpack(int njobs, const P2Group *groups, const Tile *jo
 int occupancy_f64(int which, int cls);
 hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s);
 // mixed path (kernels_mixed.hip)
-hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s);
+hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, int stage_bytes,
+                        hipStream_t s);
 hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q,
                                  int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
 int occupancy_mixed(int cls);
@@ -118,6 +119,8 @@ struct Plan {
   SliceJob *slicejobs = nullptr;
   int2 *slicerows = nullptr;
   int nslicerows = 0;
+  int slice_stage = 0;   // dynamic LDS bytes of the slice launch (0: rows read twice)
+  bool fuse_dress = false;  // mixed Lambda: the slice launch builds the stack, no dress launch
   std::vector<BatchPlan> batches;
   int ncounters = 0;
   int64_t xbuf_elems = 0;
@@ -353,6 +356,18 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
   std::vector<GroupRec> groups;
   const int64_t cap_elems = std::max<int64_t>(cap / 8, 1);
 
+  // rows of up to kSliceStageMax bytes are staged in LDS by the slice launch;
+  // the mixed Lambda stack is then built there and never stored
+  constexpr int kSliceStageMax = 48 * 1024;
+  {
+    int64_t mxrow = 0;
+    const int km = (lambda && dressed) ? 2 : 1;
+    for (int s = 0; s < nsys; ++s)
+      for (int g = 0; g < probs[s].lay->sym.nirrep; ++g) mxrow = std::max<int64_t>(mxrow, int64_t(km) * probs[s].lay->sym.ncd[g] * 8);
+    const bool fits = mxrow <= kSliceStageMax;
+    P.slice_stage = fits ? int(std::max<int64_t>(mxrow, 8)) : 0;
+    P.fuse_dress = fits && lambda && opts.precision == CDCC_MIXED;
+  }
   for (int s = 0; s < nsys; ++s) {
     SysPlan &SP = P.sys[s];
     SP.lay = *probs[s].lay;
@@ -362,7 +377,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     const int kmul = (lambda && dressed) ? 2 : 1;
     const bool mixed = opts.precision == CDCC_MIXED;
     SP.p1cls = choose_p1_class(L, opts.tile_policy, mixed, lambda);
-    if (lambda) SP.u_elems = kmul * L.b_size;
+    if (lambda && !P.fuse_dress) SP.u_elems = kmul * L.b_size;
     // mixed path: slice every operand block once per call
     int64_t blk_s[CDCC_MAX_IRREP][CDCC_MAX_IRREP], blk_sc[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
     int blk_kp[CDCC_MAX_IRREP];
@@ -382,6 +397,15 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
         J.src_off = kmul * L.b_off[gP][ga];
         J.dst_off = SP.slice_u16;
         J.scale_off = SP.scale_rows;
+        if (P.fuse_dress) {
+          const int ge = ga ^ gP;
+          J.dress = 1;
+          J.ve = nv[ge];
+          J.om = no[ge];
+          J.b_off = L.b_off[gP][ge];
+          J.bvo_off = L.bvo_off[gP][ga];
+          J.t1_off = L.t1_off[ge];
+        }
         const int jid = int(slicejobs.size());
         slicejobs.push_back(J);
         for (int q = 0; q < r; ++q) slicerows.push_back(int2{jid, q});
@@ -442,8 +466,8 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
             }
         }
     }
-    // Lambda operand stack
-    if (lambda)
+    // Lambda operand stack (in the mixed path the slice launch builds it)
+    if (lambda && !P.fuse_dress)
       for (int gP = 0; gP < h; ++gP)
         for (int ga = 0; ga < h; ++ga) {
           const int ge = ga ^ gP;
@@ -854,13 +878,13 @@ int get_workspace(int dev, hipStream_t stream, int64_t bytes, int64_t staging, W
 int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, double *part, hipStream_t stream) {
   const Plan *P = &Pl;
   HIPCHK(launch_fill_int(counters, P->ncounters, 0, stream));
-  if (P->lambda) {
+  if (P->lambda && !P->fuse_dress) {
     Span sp(0, P->ndressrows > 0, stream);
     HIPCHK(launch_dress(P->dressjobs, P->dressrows, P->ndressrows, dsp, stream));
   }
   if (P->precision == CDCC_MIXED) {
     Span sp(5, P->nslicerows > 0, stream);
-    HIPCHK(launch_slice(P->slicejobs, P->slicerows, P->nslicerows, dsp, stream));
+    HIPCHK(launch_slice(P->slicejobs, P->slicerows, P->nslicerows, dsp, P->slice_stage, stream));
   }
   {
     Span sp(1, P->npackrows > 0, stream);

@@ -52,14 +52,29 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackJob *__restrict__ j
   int4 cd = int4{0, 0, 0, 0};
   if (k < J.ncol) cd = vvtab[J.vv_off + k];
   const bool dcd = cd.x == cd.y;
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int r = r0 + rr;
-    if (r >= J.nrow || k >= J.ncol) continue;
-    const int4 ij = ijtab[J.ij_off + r];
-    const double *__restrict__ xr = S.X + J.x_off + int64_t(ij.x) * J.ldx;
-    const double x1 = xr[cd.x], x2 = xr[cd.y];
-    lp[rr][tx] = dcd ? x1 : x1 + x2;
-    lm[rr][tx] = (dcd || ij.x == ij.y) ? 0.0 : x1 - x2;
+  // all 16 rows of this thread: table entries first, then the amplitude
+  // loads, then the arithmetic (clamped rows are computed and not stored)
+  int2 ijr[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = r0 + ty + 4 * q;
+    const int4 ij = ijtab[J.ij_off + (r < J.nrow ? r : J.nrow - 1)];
+    ijr[q] = int2{ij.x, ij.y};
+  }
+  double v1[16], v2[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const CDCC_GLOBAL double *xr = as_global(S.X) + J.x_off + int64_t(ijr[q].x) * J.ldx;
+    v1[q] = xr[cd.x];
+    v2[q] = xr[cd.y];
+  }
+  if (k < J.ncol) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int rr = ty + 4 * q;
+      lp[rr][tx] = dcd ? v1[q] : v1[q] + v2[q];
+      lm[rr][tx] = (dcd || ijr[q].x == ijr[q].y) ? 0.0 : v1[q] - v2[q];
+    }
   }
   __syncthreads();
   double *__restrict__ tp = S.tauhat + J.th_off;
@@ -98,6 +113,7 @@ __global__ __launch_bounds__(256) void dress_kernel(const DressJob *__restrict__
   }
   const CDCC_GLOBAL double *lam = as_global(S.Bvo) + J.bvo_off + int64_t(a) * J.om * J.np;
   const CDCC_GLOBAL double *t1e = as_global(S.t1) + J.t1_off + e;
+#pragma unroll 2
   for (int P = threadIdx.x; P < J.np; P += 256) {
     double tea = 0.0;
     for (int m = 0; m < J.om; ++m) tea += t1e[int64_t(m) * J.ve] * lam[int64_t(m) * J.np + P];
@@ -539,21 +555,40 @@ __global__ __launch_bounds__(256) void reduce_unpack_kernel(const P2Group *__res
 // ---------------------------------------------------------------------------
 // pair energies: one workgroup per amplitude row (i,j); fixed-order tree.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void energy_kernel(const EnergyJob *__restrict__ jobs,
+__global__ __launch_bounds__(512) void energy_kernel(const EnergyJob *__restrict__ jobs,
                                                      const SysPtrs *__restrict__ sp,
                                                      const int *__restrict__ vvfull) {
-  __shared__ double red[256];
+  constexpr int NT = 512, U = 4;
+  __shared__ double red[NT];
   const EnergyJob J = jobs[blockIdx.x];
   const SysPtrs S = sp[J.sys];
   if (!S.epair) return;
-  const double *__restrict__ xr = S.X + J.r_off + int64_t(J.row) * J.ldr;
-  const double *__restrict__ rr = S.R + J.r_off + int64_t(J.row) * J.ldr;
-  const int *__restrict__ tc = vvfull + J.vvfull_off;
+  const CDCC_GLOBAL double *xr = as_global(S.X) + J.r_off + int64_t(J.row) * J.ldr;
+  const CDCC_GLOBAL double *rr = as_global(S.R) + J.r_off + int64_t(J.row) * J.ldr;
+  const CDCC_GLOBAL int *tc = as_global(vvfull) + J.vvfull_off;
+  // U columns per thread per pass: all loads of a pass are issued before the
+  // (in-order) accumulation
   double acc = 0.0;
-  for (int c = threadIdx.x; c < J.ncol; c += 256) acc += (2.0 * xr[c] - xr[tc[c]]) * rr[c];
+  for (int c0 = threadIdx.x; c0 < J.ncol; c0 += NT * U) {
+    double x[U], xt[U], r[U];
+    int t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * NT;
+      const int cc = c < J.ncol ? c : J.ncol - 1;
+      t[u] = tc[cc];
+      x[u] = xr[cc];
+      r[u] = rr[cc];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xt[u] = xr[t[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (c0 + u * NT < J.ncol) acc += (2.0 * x[u] - xt[u]) * r[u];
+  }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
@@ -624,7 +659,7 @@ int occupancy_f64(int which, int cls) {
 
 hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  energy_kernel<<<njobs, 256, 0, s>>>(jobs, sp, vvfull);
+  energy_kernel<<<njobs, 512, 0, s>>>(jobs, sp, vvfull);
   return hipGetLastError();
 }
 

@@ -42,20 +42,60 @@ __device__ __forceinline__ uint16_t bf16_bits_exact(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// slice: one workgroup per operand row.
+// slice: one workgroup per operand row.  With STAGE the row is first written
+// to LDS (dynamic size: halves * np doubles) and read from there twice (for
+// the maximum and for the slices); without it, it is read from global memory
+// twice.  Rows of a dress job are the Lambda stack built on the fly, exactly
+// as the dress kernel builds them:
+//   U[P] = B^P_ea - t^P_ea,  U[np + P] = t^P_ea,  t^P_ea = sum_m t_m^e L^P_am
+// (without singles, U = B), so the FP64 stack never goes to memory.
 // ---------------------------------------------------------------------------
+template <bool STAGE>
 __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__ jobs,
                                                     const int2 *__restrict__ rows,
                                                     const SysPtrs *__restrict__ sp) {
+  extern __shared__ double srow[];
   __shared__ double red[256];
   const int2 jr = rows[blockIdx.x];
   const SliceJob J = jobs[jr.x];
   const int row = jr.y;
   const SysPtrs S = sp[J.sys];
   const int K = J.halves * J.np;
-  const double *__restrict__ src = S.opnd + J.src_off + int64_t(row) * K;
   double mx = 0.0;
-  for (int k = threadIdx.x; k < K; k += 256) mx = fmax(mx, fabs(src[k]));
+  const double *src = nullptr;
+  if (J.dress) {
+    // (STAGE is always set for dress jobs)
+    const int a = row / J.ve, e = row - a * J.ve;
+    const int va = J.rows / J.ve;
+    const CDCC_GLOBAL double *bea = as_global(S.B) + J.b_off + (int64_t(e) * va + a) * J.np;
+    if (J.halves == 1) {
+      for (int P = threadIdx.x; P < J.np; P += 256) {
+        const double u = bea[P];
+        srow[P] = u;
+        mx = fmax(mx, fabs(u));
+      }
+    } else {
+      const CDCC_GLOBAL double *lam = as_global(S.Bvo) + J.bvo_off + int64_t(a) * J.om * J.np;
+      const CDCC_GLOBAL double *t1e = as_global(S.t1) + J.t1_off + e;
+#pragma unroll 2
+      for (int P = threadIdx.x; P < J.np; P += 256) {
+        double tea = 0.0;
+        for (int m = 0; m < J.om; ++m) tea += t1e[int64_t(m) * J.ve] * lam[int64_t(m) * J.np + P];
+        const double u = bea[P] - tea;
+        srow[P] = u;
+        srow[J.np + P] = tea;
+        mx = fmax(mx, fmax(fabs(u), fabs(tea)));
+      }
+    }
+  } else {
+    src = S.opnd + J.src_off + int64_t(row) * K;
+#pragma unroll 4
+    for (int k = threadIdx.x; k < K; k += 256) {
+      const double u = src[k];
+      if (STAGE) srow[k] = u;
+      mx = fmax(mx, fabs(u));
+    }
+  }
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -69,10 +109,11 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
   if (threadIdx.x == 0) S.rowscale[J.scale_off + row] = sigma;
   const int Kh = J.Kp / J.halves;
   uint16_t *__restrict__ dst = S.slices + J.dst_off + int64_t(row) * J.Kp * 4;
+#pragma unroll 4
   for (int kp = threadIdx.x; kp < J.Kp; kp += 256) {
     const int half = kp >= Kh ? 1 : 0;
     const int k = kp - half * Kh;
-    const double x = k < J.np ? src[half * J.np + k] : 0.0;
+    const double x = k < J.np ? (STAGE ? srow[half * J.np + k] : src[half * J.np + k]) : 0.0;
     const double y = x * inv;
     const double s0 = rint(y * 256.0) * (1.0 / 256.0);
     double r = y - s0;
@@ -275,9 +316,15 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
   }
 }
 
-hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, hipStream_t s) {
+// stage_bytes > 0: rows staged in that much dynamic LDS (required for dress
+// jobs); 0: rows read from global memory twice.
+hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, int stage_bytes,
+                        hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
-  slice_kernel<<<nrows, 256, 0, s>>>(jobs, rows, sp);
+  if (stage_bytes > 0)
+    slice_kernel<true><<<nrows, 256, stage_bytes, s>>>(jobs, rows, sp);
+  else
+    slice_kernel<false><<<nrows, 256, 0, s>>>(jobs, rows, sp);
   return hipGetLastError();
 }
 

@@ -113,10 +113,15 @@ struct DressJob {
 // padded K, 4 BF16 slices per element.
 struct SliceJob {
   int32_t sys, rows, np, halves;
-  int32_t Kp, pad0, pad1, pad2;
-  int64_t src_off;     // element offset of row 0 in the operand
+  int32_t Kp;
+  int32_t dress;       // 1: rows of the Lambda stack built here from B, L and t1 (no U)
+  int32_t ve, om;      // dress: rows are (a, e), e fastest; om = occupied count of irrep Ge
+  int64_t src_off;     // element offset of row 0 in the operand (dress == 0)
   int64_t dst_off;     // uint16 offset of row 0 in the slice buffer
   int64_t scale_off;   // row-scale index of row 0
+  int64_t b_off;       // dress: B block (GP, Ge), [e][a][P]
+  int64_t bvo_off;     // dress: L block (GP, Ga), [a][m][P]
+  int64_t t1_off;      // dress: t1 block Ge, [m][e]
 };
 
 }  // namespace cdcc
