@@ -39,7 +39,7 @@ __all__ = [
     "SPLIT_D2H", "largest_remainder_split", "sym_c1_small", "sym_d2h_medium",
     "sym_d2h_large", "sym_serving_large", "sym_custom", "dirichlet_sym",
     "batch_syms", "make_eps", "make_B", "make_Bvo", "make_t1", "make_t2",
-    "make_tau", "make_lambda", "make_problem", "irrep_pairs",
+    "make_tau", "make_lambda", "make_problem", "make_density_problem", "irrep_pairs",
     "serving_stream", "TENSOR_IDS",
 ]
 
@@ -266,6 +266,16 @@ def make_problem(sym: dict, seed: int = 0, kind: str = "t2",
         raise ValueError(kind)
     prob["kind"] = kind
     return prob
+
+
+def make_density_problem(sym: dict, seed: int = 0) -> dict:
+    """Inputs of one vvvv two-body-density contraction, as blocks: the
+    transformed Cholesky vectors ``L`` (same blocks and distribution as B),
+    ``X`` = tau~ (the tau recipe) and ``Y`` = lambda (the lambda recipe)."""
+    eps = make_eps(sym, seed)
+    t1 = make_t1(sym, seed)
+    return {"sym": sym, "kind": "density", "L": make_B(sym, seed + 7919, True),
+            "X": make_tau(sym, make_t2(sym, seed, eps), t1), "Y": make_lambda(sym, seed, eps)}
 
 
 def serving_stream(n_requests: int, rate_hz: float, seed: int = 5, p_large: float = 0.1):
