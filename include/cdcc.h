@@ -152,6 +152,46 @@ int cdcc_ladder_lambda(int32_t nsys, const cdcc_problem_t *probs,
                        const cdcc_opts_t *opts, void *stream);
 
 /*
+ * One vvvv two-body-density contraction (Appendix "CCSD two-body density
+ * matrices": Gamma_AbCd = 1/2 P_+(ab,cd) V_AbCd, V_AbCd = sum_mn
+ * tau~_Mn^Cd lambda_Ab^Mn; gradient section: Gamma^P_pr = sum_qs
+ * Gamma_pqrs L~^P_qs, contracted on the fly), closed-shell spatial form:
+ *
+ *   G^P_ac = 1/2 sum_bd sum_mn [Y_mn^ab X_mn^cd + Y_mn^cd X_mn^ab] L^P_bd
+ *
+ * X = tau~ and Y = lambda in the amplitude layout (any values; the paper
+ * leaves tau~ to the caller), L = the transformed Cholesky vectors L~^P_bd
+ * and G = the result G^P_ac, both in the Cholesky-vector layout of B
+ * (block (GP, Ga) = [a][c][P]).  G receives every stored element.
+ */
+typedef struct {
+  const cdcc_layout_t *lay;  /* host pointer, read during the call only        */
+  const double *L;           /* device, lay->b_size                             */
+  const double *X;           /* device, lay->amp_size                           */
+  const double *Y;           /* device, lay->amp_size                           */
+  double *G;                 /* device out, lay->b_size                         */
+} cdcc_density_problem_t;
+
+/*
+ * vvvv density contraction for nsys >= 0 independent systems, FP64 MFMA,
+ * asynchronous on `stream`.  The (ab|cd) intermediate exists only in bounded
+ * batches (opts->batch_bytes, default 1 GiB).  opts may be NULL; precision
+ * must be CDCC_FP64 (CDCC_MIXED returns CDCC_EUNSUPPORTED); tile_policy is
+ * ignored.  Errors as for cdcc_ladder_t2 (CDCC_EINVAL for a NULL required
+ * pointer); inputs must not overlap G.
+ */
+int cdcc_vvvv_density(int32_t nsys, const cdcc_density_problem_t *probs,
+                      const cdcc_opts_t *opts, void *stream);
+
+/*
+ * Algorithmic flop count of one vvvv density contraction (host only):
+ * flops[0] = the (ab|cd) products (2 flops per (a,b,c,d,m,n) term, both
+ * orders of the P_+ pair), flops[1] = the contraction with L (2 flops per
+ * (a,c,b,d,P) term); symmetry-allowed blocks only.
+ */
+int cdcc_density_flops(const cdcc_layout_t *lay, double flops[2]);
+
+/*
  * Algorithmic flop count of one evaluation (host only): flops[0] = (ac|bd)
  * assembly, flops[1] = contraction, flops[2] = T1 dressing (Lambda with t1).
  * kind: 0 = T2, 1 = Lambda, 2 = Lambda with dressing.  Counts the stored
@@ -171,7 +211,8 @@ int cdcc_workspace_bytes(int32_t nsys, const cdcc_problem_t *probs,
  * Kernel timing (instrumentation for benchmarks).  While enabled, every ladder
  * call records a HIP event pair on its own stream around each kernel class:
  * 0 = T1 dressing, 1 = amplitude packing, 2 = (ac|bd) batch assembly,
- * 3 = contraction + unpack, 4 = pair energies, 5 = operand slicing (mixed).
+ * 3 = contraction + unpack, 4 = pair energies, 5 = operand slicing (mixed),
+ * 6 = vvvv density (ab|cd) batch, 7 = vvvv density contraction with L.
  * cdcc_timing_read waits for the recorded events, returns the summed elapsed
  * milliseconds and launch counts per class (arrays of 8) and clears the record.
  */

@@ -1,5 +1,6 @@
 """MI355X-native particle-particle ladder of Cholesky-decomposed CCSD
-(T2 and Lambda residual terms, Abelian point-group symmetry).
+(T2 and Lambda residual terms, Abelian point-group symmetry), and the vvvv
+two-body-density contraction with Cholesky vectors.
 
 The computation lives in ``libcdcc.so`` (HIP, gfx950) behind the C ABI of
 ``include/cdcc.h``; this package only marshals arguments.
@@ -7,4 +8,4 @@ The computation lives in ``libcdcc.so`` (HIP, gfx950) behind the C ABI of
 from ._lib import CdccError, LIB_PATH  # noqa: F401
 from .layout import Layout  # noqa: F401
 from .ladder import (ladder_lambda, ladder_t2, release, require_gpu, timing_enable,  # noqa: F401
-                     timing_read, workspace_bytes)
+                     timing_read, vvvv_density, workspace_bytes)

@@ -43,13 +43,20 @@ class Problem(ctypes.Structure):
     ]
 
 
+class DensityProblem(ctypes.Structure):
+    _fields_ = [
+        ("lay", ctypes.POINTER(LayoutC)),
+        ("L", ctypes.c_void_p), ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("G", ctypes.c_void_p),
+    ]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("precision", _i32), ("tile_policy", _i32), ("batch_bytes", _i64)]
 
 
 EXPORTS = ["cdcc_irrep_layout", "cdcc_ladder_t2", "cdcc_ladder_lambda", "cdcc_ladder_flops",
            "cdcc_workspace_bytes", "cdcc_timing_enable", "cdcc_timing_read", "cdcc_status_string",
-           "cdcc_release"]
+           "cdcc_release", "cdcc_vvvv_density", "cdcc_density_flops"]
 
 _lib = None
 
@@ -79,6 +86,10 @@ def load() -> ctypes.CDLL:
     lib.cdcc_timing_enable.restype = ctypes.c_int
     lib.cdcc_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     lib.cdcc_timing_read.restype = ctypes.c_int
+    lib.cdcc_vvvv_density.argtypes = [_i32, ctypes.POINTER(DensityProblem), ctypes.POINTER(Opts), ctypes.c_void_p]
+    lib.cdcc_vvvv_density.restype = ctypes.c_int
+    lib.cdcc_density_flops.argtypes = [ctypes.POINTER(LayoutC), ctypes.POINTER(ctypes.c_double)]
+    lib.cdcc_density_flops.restype = ctypes.c_int
     lib.cdcc_release.argtypes = []
     lib.cdcc_release.restype = ctypes.c_int
     _lib = lib

@@ -47,6 +47,15 @@ hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const
 hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q,
                                  int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
 int occupancy_mixed(int cls);
+// vvvv density (kernels_f64.hip, kernels_density.hip)
+hipError_t launch_assemble_density(int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
+                                   const SysPtrs *sp, double *xbuf, hipStream_t s);
+int occupancy_density_w();
+hipError_t launch_density_pack(const DensPackJob *jobs, const int2 *tiles, int ntiles, const DensPtrs *dp,
+                               hipStream_t s);
+hipError_t launch_density_gemm(int grid, const GemmDesc *descs, const Tile *tiles, const Queues &Q, int *cnt,
+                               const DensPtrs *dp, const double *xbuf, hipStream_t s);
+int occupancy_density_gemm();
 }  // namespace cdcc
 
 using namespace cdcc;
@@ -1006,6 +1015,335 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
   return CDCC_OK;
 }
 
+// ===========================================================================
+// vvvv two-body density (Appendix two-body densities; gradient section):
+//   W_(ab),(cd) = sum_mn [Y_mn^ab X_mn^cd + X_mn^ab Y_mn^cd]
+//   G^P_ac      = 1/2 sum_bd W_(ab),(cd) L^P_bd
+// Regions: for each (system, Cholesky irrep GP, Ga) and range of a, the W
+// rows (a, c) (c in Ga^GP) times all (b, d) pairs of GP go to the batch
+// buffer (first stage: one T T'^T GEMM per Gb, K = 2 n_oo(Ga^Gb)); the second
+// stage multiplies the region by the GP block of L and writes the result rows
+// (a, c) of block (GP, Ga) directly.  Every result element is written once.
+// ===========================================================================
+struct DensBatch {
+  Launch w, g;
+};
+
+struct DensPlan {
+  int nsys = 0;
+  void *dtab = nullptr;
+  DensPackJob *packjobs = nullptr;
+  int2 *packtiles = nullptr;
+  int npacktiles = 0;
+  P1Desc *wdesc = nullptr;
+  Tile *wtiles = nullptr;
+  GemmDesc *gdesc = nullptr;
+  Tile *gtiles = nullptr;
+  std::vector<DensBatch> batches;
+  int ncounters = 0;
+  int64_t xbuf_elems = 0;
+  std::vector<int64_t> t_elems;
+  ~DensPlan() {
+    if (dtab) (void)hipFree(dtab);
+  }
+};
+std::map<std::string, std::shared_ptr<DensPlan>> g_dplans;
+
+int64_t vv_count(const cdcc_layout_t &L, int G) { return L.n_vv[G]; }
+
+// Deal a tile list to the eight XCD queues in chunks (longest first).
+Launch deal_tiles(std::vector<std::pair<int64_t, Tile>> &v, int chunk, int occ, std::vector<Tile> &out) {
+  Launch l;
+  std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+  std::vector<std::vector<Tile>> qs(8);
+  for (size_t i = 0; i < v.size(); ++i) qs[(i / chunk) % 8].push_back(v[i].second);
+  l.start = int(out.size());
+  int acc = 0;
+  for (int x = 0; x < 8; ++x) {
+    l.q.qb[x] = acc;
+    for (const Tile &t : qs[x]) out.push_back(t);
+    acc += int(qs[x].size());
+  }
+  l.q.qb[8] = acc;
+  l.count = acc;
+  const int cap = std::max(8, g_num_cu * std::max(occ, 1));
+  l.grid = acc > 0 ? std::min(cap, (acc + 7) / 8 * 8) : 0;
+  return l;
+}
+
+int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t cap, DensPlan &P) {
+  constexpr int WBM = 128, WBN = 64, GBM = 128, GBN = 64;
+  P.nsys = nsys;
+  P.t_elems.assign(nsys, 0);
+  const int64_t cap_elems = std::max<int64_t>(cap / 8, 1);
+  std::vector<DensPackJob> packjobs;
+  std::vector<int2> packtiles;
+  struct Region {
+    int sys;
+    int64_t elems;
+    std::vector<P1Desc> w;
+    GemmDesc g;
+  };
+  std::vector<Region> regions;
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_layout_t &L = *probs[s].lay;
+    const int h = L.sym.nirrep;
+    const int32_t *no = L.sym.nocc, *nv = L.sym.nvir, *nc = L.sym.ncd;
+    // T tables: per pair irrep G, [Y | X] rows then [X | Y] rows (K = 2 n_oo)
+    int64_t tw_off[CDCC_MAX_IRREP], tv_off[CDCC_MAX_IRREP];
+    int64_t t = 0;
+    for (int G = 0; G < h; ++G) {
+      const int64_t K2 = 2 * L.n_oo[G], nr = L.n_vv[G];
+      tw_off[G] = t;
+      tv_off[G] = t + nr * K2;
+      if (K2 > 0 && nr > 0) {
+        DensPackJob J{};
+        J.sys = s;
+        J.nrow = int(L.n_oo[G]);
+        J.ncol = int(nr);
+        J.x_off = L.amp_off[G];
+        J.tw_off = t;
+        const int jid = int(packjobs.size());
+        packjobs.push_back(J);
+        const int nt = int((L.n_oo[G] + 63) / 64 * ((nr + 63) / 64));
+        for (int q = 0; q < nt; ++q) packtiles.push_back(int2{jid, q});
+      }
+      t += 2 * nr * K2;
+    }
+    P.t_elems[s] = t + 64;  // padding: a K = 0 block reads (masked) at offset 0
+    for (int gP = 0; gP < h; ++gP) {
+      const int64_t kvv = L.n_vv[gP];
+      if (nc[gP] == 0 || kvv == 0) continue;
+      for (int ga = 0; ga < h; ++ga) {
+        const int gc = ga ^ gP;
+        if (nv[ga] == 0 || nv[gc] == 0) continue;
+        const int64_t per_a = int64_t(nv[gc]) * kvv;
+        const int step = int(std::max<int64_t>(1, std::min<int64_t>(nv[ga], cap_elems / std::max<int64_t>(per_a, 1))));
+        for (int a0 = 0; a0 < nv[ga]; a0 += step) {
+          const int a1 = std::min(nv[ga], a0 + step);
+          Region R;
+          R.sys = s;
+          R.elems = int64_t(a1 - a0) * per_a;
+          for (int gb = 0; gb < h; ++gb) {
+            const int gd = gb ^ gP, G = ga ^ gb;
+            if (nv[gb] == 0 || nv[gd] == 0) continue;
+            const int K = int(2 * L.n_oo[G]);
+            P1Desc d{};
+            d.sys = s;
+            d.M = (a1 - a0) * nv[gb];
+            d.N = nv[gc] * nv[gd];
+            d.K = K;
+            d.kneg = K;
+            d.vc = nv[gb];
+            d.vd = nv[gd];
+            d.vb = nv[gb];
+            d.nb = nv[gc];
+            d.a_first = a0;
+            d.ga0 = a0;
+            d.tri = 0;
+            d.ldx = int(kvv);
+            d.xrow0 = int(L.vv_off[gP][gb]);
+            d.aoff = K > 0 ? tw_off[G] + (L.vv_off[G][ga] + int64_t(a0) * nv[gb]) * K : 0;
+            d.boff = K > 0 ? tv_off[G] + L.vv_off[G][gc] * K : 0;
+            R.w.push_back(d);
+          }
+          GemmDesc g{};
+          g.sys = s;
+          g.M = (a1 - a0) * nv[gc];
+          g.N = nc[gP];
+          g.K = int(kvv);
+          g.lda = int(kvv);
+          g.ldb = nc[gP];
+          g.ldc = nc[gP];
+          g.boff = L.b_off[gP][0];
+          g.coff = L.b_off[gP][ga] + int64_t(a0) * nv[gc] * nc[gP];
+          g.alpha = 0.5;
+          R.g = g;
+          regions.push_back(std::move(R));
+        }
+      }
+    }
+  }
+  // batches of regions under the cap
+  std::vector<P1Desc> wd;
+  std::vector<GemmDesc> gd;
+  std::vector<Tile> wt, gt;
+  const int occw = occupancy_density_w(), occg = occupancy_density_gemm();
+  size_t ri = 0;
+  int nl = 0;
+  while (ri < regions.size()) {
+    size_t rj = ri;
+    int64_t used = 0;
+    while (rj < regions.size() && (rj == ri || used + align_up(regions[rj].elems, 32) <= cap_elems)) {
+      used += align_up(regions[rj].elems, 32);
+      ++rj;
+    }
+    std::vector<std::pair<int64_t, Tile>> tw, tg;
+    int64_t xo = 0;
+    for (size_t k = ri; k < rj; ++k) {
+      Region &R = regions[k];
+      for (P1Desc d : R.w) {
+        d.xoff = xo;
+        const int did = int(wd.size());
+        wd.push_back(d);
+        const int tm = (d.M + WBM - 1) / WBM, tn = (d.N + WBN - 1) / WBN;
+        for (int a = 0; a < tm; ++a)
+          for (int b = 0; b < tn; ++b) tw.push_back({int64_t(d.K) + 1, Tile{did, a, b, 0}});
+      }
+      GemmDesc g = R.g;
+      g.aoff = xo;
+      const int gid = int(gd.size());
+      gd.push_back(g);
+      const int tm = (g.M + GBM - 1) / GBM, tn = (g.N + GBN - 1) / GBN;
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b) tg.push_back({int64_t(g.K) + 1, Tile{gid, a, b, 0}});
+      xo += align_up(R.elems, 32);
+    }
+    P.xbuf_elems = std::max(P.xbuf_elems, xo);
+    DensBatch B;
+    B.w = deal_tiles(tw, 16, occw, wt);
+    B.g = deal_tiles(tg, 16, occg, gt);
+    P.batches.push_back(B);
+    nl += 2;
+    ri = rj;
+  }
+  P.ncounters = 8 * std::max(nl, 1) * kQueueStride;
+  TableBuilder T;
+  const int64_t o_pj = T.add(packjobs), o_pt = T.add(packtiles), o_wd = T.add(wd), o_wt = T.add(wt);
+  const int64_t o_gd = T.add(gd), o_gt = T.add(gt);
+  if (hipMalloc(&P.dtab, std::max<size_t>(T.bytes.size(), 256)) != hipSuccess) return CDCC_ENOMEM;
+  if (hipMemcpy(P.dtab, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return CDCC_EDEVICE;
+  char *b = static_cast<char *>(P.dtab);
+  P.packjobs = reinterpret_cast<DensPackJob *>(b + o_pj);
+  P.packtiles = reinterpret_cast<int2 *>(b + o_pt);
+  P.npacktiles = int(packtiles.size());
+  P.wdesc = reinterpret_cast<P1Desc *>(b + o_wd);
+  P.wtiles = reinterpret_cast<Tile *>(b + o_wt);
+  P.gdesc = reinterpret_cast<GemmDesc *>(b + o_gd);
+  P.gtiles = reinterpret_cast<Tile *>(b + o_gt);
+  return CDCC_OK;
+}
+
+int validate_density(int32_t nsys, const cdcc_density_problem_t *probs) {
+  if (nsys < 0 || (nsys > 0 && !probs)) return CDCC_EINVAL;
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_density_problem_t &p = probs[s];
+    if (!p.lay) return CDCC_EINVAL;
+    if (!valid_sym(p.lay->sym)) return p.lay->sym.nirrep > 0 ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+    if (p.lay->amp_size > 0 && (!p.X || !p.Y)) return CDCC_EINVAL;
+    if (p.lay->b_size > 0 && (!p.L || !p.G)) return CDCC_EINVAL;
+  }
+  return CDCC_OK;
+}
+
+struct DensWs {
+  int64_t counters = 0, dptrs = 0, sptrs = 0, xbuf = 0, total = 0;
+  std::vector<int64_t> t;
+};
+DensWs dens_ws_layout(const DensPlan &P) {
+  DensWs W;
+  int64_t o = 0;
+  W.counters = o;
+  o = align_up(o + int64_t(std::max(P.ncounters, 1)) * 4);
+  W.dptrs = o;
+  o = align_up(o + int64_t(P.nsys) * int64_t(sizeof(DensPtrs)));
+  W.sptrs = o;
+  o = align_up(o + int64_t(P.nsys) * int64_t(sizeof(SysPtrs)));
+  W.xbuf = o;
+  o = align_up(o + P.xbuf_elems * 8);
+  W.t.resize(P.nsys);
+  for (int s = 0; s < P.nsys; ++s) {
+    W.t[s] = o;
+    o = align_up(o + P.t_elems[s] * 8);
+  }
+  W.total = o;
+  return W;
+}
+
+int run_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_opts_t *popts, void *vstream) {
+  cdcc_opts_t opts{};
+  if (popts) opts = *popts;
+  if (opts.precision != CDCC_FP64) return opts.precision == CDCC_MIXED ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+  int rc = validate_density(nsys, probs);
+  if (rc != CDCC_OK) return rc;
+  if (nsys == 0) return CDCC_OK;
+  hipStream_t stream = static_cast<hipStream_t>(vstream);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_mu);
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) g_num_cu = ncu;
+  }
+  const int64_t cap = opts.batch_bytes > 0 ? opts.batch_bytes : env_i64("CDCC_BATCH_MB", 1024) * (int64_t(1) << 20);
+  std::string key = "density|" + std::to_string(dev) + "|" + std::to_string(cap) + "|" + std::to_string(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_sym_t &y = probs[s].lay->sym;
+    key += "|" + std::to_string(y.nirrep);
+    for (int g = 0; g < y.nirrep; ++g)
+      key += "," + std::to_string(y.nocc[g]) + "," + std::to_string(y.nvir[g]) + "," + std::to_string(y.ncd[g]);
+  }
+  std::shared_ptr<DensPlan> P;
+  auto it = g_dplans.find(key);
+  if (it != g_dplans.end()) {
+    P = it->second;
+  } else {
+    P = std::make_shared<DensPlan>();
+    rc = build_density_plan(nsys, probs, cap, *P);
+    if (rc != CDCC_OK) return rc;
+    if (g_dplans.size() > 64) g_dplans.clear();
+    g_dplans[key] = P;
+  }
+  const DensWs W = dens_ws_layout(*P);
+  Workspace *ws = nullptr;
+  rc = get_workspace(dev, stream, W.total, int64_t(nsys) * int64_t(sizeof(DensPtrs) + sizeof(SysPtrs)), ws);
+  if (rc != CDCC_OK) return rc;
+  char *base = static_cast<char *>(ws->dev);
+  if (ws->ev_recorded) HIPCHK(hipEventSynchronize(ws->ev));
+  DensPtrs *hd = static_cast<DensPtrs *>(ws->staging);
+  SysPtrs *hs = reinterpret_cast<SysPtrs *>(hd + nsys);
+  for (int s = 0; s < nsys; ++s) {
+    DensPtrs d{};
+    d.X = probs[s].X;
+    d.Y = probs[s].Y;
+    d.L = probs[s].L;
+    d.G = probs[s].G;
+    d.T = reinterpret_cast<double *>(base + W.t[s]);
+    hd[s] = d;
+    SysPtrs q{};
+    q.opnd = d.T;
+    hs[s] = q;
+  }
+  DensPtrs *ddp = reinterpret_cast<DensPtrs *>(base + W.dptrs);
+  SysPtrs *dsp = reinterpret_cast<SysPtrs *>(base + W.sptrs);
+  HIPCHK(hipMemcpyAsync(ddp, hd, size_t(nsys) * sizeof(DensPtrs), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(dsp, hs, size_t(nsys) * sizeof(SysPtrs), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(ws->ev, stream));
+  ws->ev_recorded = true;
+
+  int *counters = reinterpret_cast<int *>(base + W.counters);
+  double *xbuf = reinterpret_cast<double *>(base + W.xbuf);
+  HIPCHK(launch_fill_int(counters, P->ncounters, 0, stream));
+  {
+    Span sp(1, P->npacktiles > 0, stream);
+    HIPCHK(launch_density_pack(P->packjobs, P->packtiles, P->npacktiles, ddp, stream));
+  }
+  int ci = 0;
+  for (const DensBatch &B : P->batches) {
+    {
+      Span sp(6, B.w.count > 0, stream);
+      HIPCHK(launch_assemble_density(B.w.grid, P->wdesc, P->wtiles + B.w.start, B.w.q,
+                                     counters + 8 * kQueueStride * ci++, dsp, xbuf, stream));
+    }
+    {
+      Span sp(7, B.g.count > 0, stream);
+      HIPCHK(launch_density_gemm(B.g.grid, P->gdesc, P->gtiles + B.g.start, B.g.q,
+                                 counters + 8 * kQueueStride * ci++, ddp, xbuf, stream));
+    }
+  }
+  return CDCC_OK;
+}
+
 }  // namespace
 
 extern "C" int cdcc_ladder_t2(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *opts, void *stream) {
@@ -1060,8 +1398,14 @@ extern "C" int cdcc_timing_read(double ms[8], int64_t launches[8]) {
   return rc;
 }
 
+extern "C" int cdcc_vvvv_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_opts_t *opts,
+                                 void *stream) {
+  return run_density(nsys, probs, opts, stream);
+}
+
 extern "C" int cdcc_release(void) {
   std::lock_guard<std::mutex> lock(g_mu);
+  g_dplans.clear();
   delete g_tile_table;  // re-read on the next plan
   g_tile_table = nullptr;
   if (hipDeviceSynchronize() != hipSuccess) return CDCC_EDEVICE;

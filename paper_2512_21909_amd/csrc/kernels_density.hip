@@ -1,0 +1,223 @@
+// vvvv block of the CCSD two-body density contracted with Cholesky vectors,
+// FP64 kernels for gfx950 (CDNA4).
+//
+// Paper: Appendix "CCSD two-body density matrices" (Gamma_AbCd =
+// 1/2 P_+(ab,cd) V_AbCd, V_AbEf = sum_mn tau_Mn^Ef lambda_Ab^Mn) and the
+// gradient section (Gamma^P_pr = sum_qs Gamma_pqrs L~^P_qs, contracted on the
+// fly).  Closed-shell spatial form computed here:
+//
+//   W_(ab),(cd) = sum_mn [Y_mn^ab X_mn^cd + X_mn^ab Y_mn^cd]   = 2 Gamma_abcd
+//   G^P_ac      = 1/2 sum_bd W_(ab),(cd) L^P_bd
+//
+// Pipeline of one call:
+//   pack   amplitude blocks (rows mn, columns ab) -> T tables, rows (ab) of
+//          [Y | X] and of [X | Y] (K = 2 n_oo(G), contiguous), so W is one
+//          GEMM T T'^T with K = 2 n_oo (the assembly kernel, mode 1, writes
+//          W with rows (a, c) and columns (b, d) into a bounded batch buffer)
+//   gemm   G[(a,c)][P] = 1/2 W[(a,c)][(b,d)] L[(b,d)][P] over the (b, d) pairs
+//          of the Cholesky irrep (below)
+#include <hip/hip_runtime.h>
+
+#include "kernel_common.hpp"
+
+namespace cdcc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// pack: one workgroup per 64 x 64 tile (64 mn rows x 64 ab columns) of one
+// (system, G) amplitude block; read along ab, written along mn through LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void density_pack_kernel(const DensPackJob *__restrict__ jobs,
+                                                           const int2 *__restrict__ tiles,
+                                                           const DensPtrs *__restrict__ dp) {
+  __shared__ double ly[64][65], lx[64][65];
+  const int2 jt = tiles[blockIdx.x];
+  const DensPackJob J = jobs[jt.x];
+  const DensPtrs P = dp[J.sys];
+  const int ncb = (J.ncol + 63) / 64;
+  const int k0 = (jt.y / ncb) * 64, c0 = (jt.y % ncb) * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const CDCC_GLOBAL double *y = as_global(P.Y) + J.x_off;
+  const CDCC_GLOBAL double *x = as_global(P.X) + J.x_off;
+  const int c = c0 + tx;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int kk = ty + 4 * q, k = k0 + kk;
+    const bool in = k < J.nrow && c < J.ncol;
+    const int64_t o = int64_t(in ? k : 0) * J.ncol + (in ? c : 0);
+    const double yv = y[o], xv = x[o];
+    ly[kk][tx] = in ? yv : 0.0;
+    lx[kk][tx] = in ? xv : 0.0;
+  }
+  __syncthreads();
+  const int K2 = 2 * J.nrow;
+  double *__restrict__ tw = P.T + J.tw_off;                  // [Y | X]
+  double *__restrict__ tv = tw + int64_t(J.ncol) * K2;       // [X | Y]
+  const int k = k0 + tx;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int cc = ty + 4 * q, col = c0 + cc;
+    if (k >= J.nrow || col >= J.ncol) continue;
+    const int64_t r = int64_t(col) * K2;
+    tw[r + k] = ly[tx][cc];
+    tw[r + J.nrow + k] = lx[tx][cc];
+    tv[r + k] = lx[tx][cc];
+    tv[r + J.nrow + k] = ly[tx][cc];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gemm (second stage): tile BM x BN of C = alpha A B, BK = 16, 4 waves in
+// 2 x 2, MFMA f64 16x16x4; A rows (K-contiguous) staged transposed into
+// LDS [k][m], B rows ([k][n], n-contiguous) staged as they are; double
+// buffered, one barrier per K step.  Out-of-range rows, columns and K are
+// read from clamped addresses and zeroed by a select.
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_nn_f64_kernel(const GemmDesc *__restrict__ descs,
+                                                          const Tile *__restrict__ tiles, Queues Q,
+                                                          int *__restrict__ cnt,
+                                                          const DensPtrs *__restrict__ dp,
+                                                          const double *__restrict__ xbuf) {
+  constexpr int BK = 16;
+  constexpr int LA = BM + 2, LB = BN + 2;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int RA = BM / 64;              // A rows per thread (4 consecutive k each)
+  constexpr int CB = BN * BK / 256;        // B columns per thread (one k row)
+  constexpr int TPK = BN / CB;             // threads per B k row
+  static_assert(CB >= 1 && 256 / TPK == BK, "B staging");
+  __shared__ double As[2][BK][LA];
+  __shared__ double Bs[2][BK][LB];
+  __shared__ int s_tile;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = tid >> 2, lk = (tid & 3) * 4;   // A staging
+  const int bk = tid / TPK, bc = (tid % TPK) * CB;  // B staging
+  unsigned dead = 0;
+
+  for (;;) {
+    const int t = next_tile(cnt, Q, dead, &s_tile);
+    if (t < 0) break;
+    const Tile tl = tiles[t];
+    const GemmDesc D = descs[tl.desc];
+    const DensPtrs P = dp[D.sys];
+    const int m0 = tl.tm * BM, n0 = tl.tn * BN;
+    const int K = D.K;
+    const CDCC_GLOBAL double *arow[RA];
+    double am[RA];
+#pragma unroll
+    for (int q = 0; q < RA; ++q) {
+      const int m = m0 + lr + 64 * q;
+      am[q] = m < D.M ? 1.0 : 0.0;
+      arow[q] = as_global(xbuf) + D.aoff + int64_t(m < D.M ? m : D.M - 1) * D.lda;
+    }
+    const CDCC_GLOBAL double *bmat = as_global(P.L) + D.boff;
+    int bcol[CB];
+    double bm[CB];
+#pragma unroll
+    for (int e = 0; e < CB; ++e) {
+      const int n = n0 + bc + e;
+      bm[e] = n < D.N ? 1.0 : 0.0;
+      bcol[e] = n < D.N ? n : D.N - 1;
+    }
+
+    d4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    double ra[RA][4], rb[CB];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = k0 + lk + e;
+        const bool kin = k < K;
+        const int kc = kin ? k : (K > 0 ? K - 1 : 0);
+        const double ka = kin ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < RA; ++q) ra[q][e] = arow[q][kc] * (am[q] * ka);
+      }
+      const int k = k0 + bk;
+      const bool kin = k < K;
+      const int64_t ko = int64_t(kin ? k : (K > 0 ? K - 1 : 0)) * D.ldb;
+      const double kb = kin ? 1.0 : 0.0;
+#pragma unroll
+      for (int e = 0; e < CB; ++e) rb[e] = bmat[ko + bcol[e]] * (bm[e] * kb);
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int q = 0; q < RA; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[buf][lk + e][lr + 64 * q] = ra[q][e];
+#pragma unroll
+      for (int e = 0; e < CB; ++e) Bs[buf][bk][bc + e] = rb[e];
+    };
+
+    const int nk = (K + BK - 1) / BK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kb = 0; kb < nk; ++kb) {
+      const int cur = kb & 1;
+      gload((kb + 1) * BK);
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        double fa[FM], fb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) fa[i] = As[cur][kr][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) fb[j] = Bs[cur][kr][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      }
+      lstore(cur ^ 1);
+      __syncthreads();
+    }
+
+    double *__restrict__ C = P.G + D.coff;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * r;
+          const int n = n0 + wn * WN + j * 16 + (lane & 15);
+          if (m >= D.M || n >= D.N) continue;
+          C[int64_t(m) * D.ldc + n] = D.alpha * acc[i][j][r];
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_density_pack(const DensPackJob *jobs, const int2 *tiles, int ntiles, const DensPtrs *dp,
+                               hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  density_pack_kernel<<<ntiles, 256, 0, s>>>(jobs, tiles, dp);
+  return hipGetLastError();
+}
+
+hipError_t launch_density_gemm(int grid, const GemmDesc *descs, const Tile *tiles, const Queues &Q, int *cnt,
+                               const DensPtrs *dp, const double *xbuf, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  gemm_nn_f64_kernel<128, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, dp, xbuf);
+  return hipGetLastError();
+}
+
+int occupancy_density_gemm() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_nn_f64_kernel<128, 64>, 256, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+}  // namespace cdcc

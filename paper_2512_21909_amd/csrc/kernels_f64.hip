@@ -130,7 +130,13 @@ __global__ __launch_bounds__(256) void dress_kernel(const DressJob *__restrict__
 // and K are read from a clamped address and zeroed by a select, so the loads
 // are straight-line code.
 // ---------------------------------------------------------------------------
-template <int BM, int BN>
+//
+// MODE 1 (vvvv two-body density, first stage) reuses the tile loop for
+// W_(ab),(cd) = sum_K T_(ab),K T'_(cd),K: both operand rows are consecutive
+// (rows a_first.. of the left table, rows 0.. of the right one), m = (a, b)
+// with b = m % vc, n = (c, d) with d = n % vd, and the element is stored at
+// row (a - ga0) * nb + c, column xrow0 + b * vd + d of the region (no 1/2).
+template <int BM, int BN, int MODE = 0>
 __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restrict__ descs,
                                                            const Tile *__restrict__ tiles, Queues Q,
                                                            int *__restrict__ cnt,
@@ -173,8 +179,12 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
       const int n = n0 + lr + 64 * q;
       bmk[q] = n < D.N ? 1.0 : 0.0;
       const int nn = n < D.N ? n : D.N - 1;
-      const int dd = nn / D.nb, b = nn - dd * D.nb;
-      brow[q] = as_global(op) + D.boff + (int64_t(b) * D.vd + dd) * K;
+      if constexpr (MODE == 1) {
+        brow[q] = as_global(op) + D.boff + int64_t(nn) * K;
+      } else {
+        const int dd = nn / D.nb, b = nn - dd * D.nb;
+        brow[q] = as_global(op) + D.boff + (int64_t(b) * D.vd + dd) * K;
+      }
     }
 
     d4 acc[FM][FN];
@@ -191,7 +201,7 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
       for (int e = 0; e < 4; ++e) {
         const int k = k0 + lk + e;
         const bool kin = k < K;
-        const int kc = kin ? k : K - 1;
+        const int kc = kin ? k : (K > 0 ? K - 1 : 0);
         const double ka = kin ? 1.0 : 0.0;
         const double kb = kin ? (k >= D.kneg ? -1.0 : 1.0) : 0.0;
 #pragma unroll
@@ -248,6 +258,13 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
           const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * r;
           const int n = n0 + wn * WN + j * 16 + (lane & 15);
           if (m >= D.M || n >= D.N) continue;
+          if constexpr (MODE == 1) {
+            const int am = m / D.vc, b = m - am * D.vc;
+            const int c = n / D.vd, d = n - c * D.vd;
+            const int64_t wrow = int64_t(D.a_first + am - D.ga0) * D.nb + c;
+            xbuf[D.xoff + wrow * D.ldx + D.xrow0 + int64_t(b) * D.vd + d] = acc[i][j][r];
+            continue;
+          }
           const int am = m / D.vc, c = m - am * D.vc;
           const int a = D.a_first + am;
           const int dd = n / D.nb, b = n - dd * D.nb;
@@ -626,6 +643,20 @@ hipError_t launch_assemble_f64(int cls, int grid, const P1Desc *descs, const Til
     default: assemble_f64_kernel<128, 128><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
   }
   return hipGetLastError();
+}
+
+// vvvv density, first stage (W = T T'^T with the density store): 128 x 64 tiles
+hipError_t launch_assemble_density(int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
+                                   const SysPtrs *sp, double *xbuf, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  assemble_f64_kernel<128, 64, 1><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf);
+  return hipGetLastError();
+}
+
+int occupancy_density_w() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_f64_kernel<128, 64, 1>, 256, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_contract_f64(int grid, const P2Group *groups, const Tile *tiles, const Queues &Q, int *cnt,

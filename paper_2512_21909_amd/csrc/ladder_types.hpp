@@ -124,4 +124,31 @@ struct SliceJob {
   int64_t t1_off;      // dress: t1 block Ge, [m][e]
 };
 
+// vvvv two-body density: per-system pointers.
+struct DensPtrs {
+  const double *X;     // tau~ amplitudes (amplitude layout)
+  const double *Y;     // lambda amplitudes (amplitude layout)
+  const double *L;     // transformed Cholesky vectors (Cholesky layout)
+  double *G;           // result G^P_ac (Cholesky layout)
+  double *T;           // workspace: per pair irrep, rows (ab) of [Y | X] then rows of [X | Y]
+};
+
+// Transposition of one pair-irrep amplitude block into the T tables.
+struct DensPackJob {
+  int32_t sys, nrow, ncol, pad0;   // nrow = n_oo(G) (K half), ncol = n_vv(G) (pair rows)
+  int64_t x_off;                   // amp_off[G]
+  int64_t tw_off;                  // element offset of row 0 of [Y | X] in T; [X | Y] follows
+};
+
+// One plain GEMM of the second stage: C = alpha A B, A rows K-contiguous
+// (lda), B row-major [K][N] (ldb), C row-major (ldc).
+struct GemmDesc {
+  int32_t sys, M, N, K;
+  int32_t lda, ldb, ldc, pad0;
+  int64_t aoff;        // into the batch buffer
+  int64_t boff;        // into DensPtrs::L
+  int64_t coff;        // into DensPtrs::G
+  double alpha;
+};
+
 }  // namespace cdcc

@@ -136,6 +136,38 @@ extern "C" int cdcc_ladder_flops(const cdcc_layout_t *lay, int32_t kind, double 
   return CDCC_OK;
 }
 
+extern "C" int cdcc_density_flops(const cdcc_layout_t *lay, double flops[2]) {
+  if (!lay || !flops) return CDCC_EINVAL;
+  const int h = lay->sym.nirrep;
+  if (!valid_h(h)) return CDCC_EUNSUPPORTED;
+  const int32_t *no = lay->sym.nocc, *nv = lay->sym.nvir, *nc = lay->sym.ncd;
+  auto n_oo = [&](int G) {
+    double n = 0;
+    for (int g = 0; g < h; ++g) n += double(no[g]) * no[g ^ G];
+    return n;
+  };
+  auto n_vv = [&](int G) {
+    double n = 0;
+    for (int g = 0; g < h; ++g) n += double(nv[g]) * nv[g ^ G];
+    return n;
+  };
+  double fv = 0, fl = 0;
+  for (int gP = 0; gP < h; ++gP) {
+    if (nc[gP] == 0) continue;
+    for (int ga = 0; ga < h; ++ga) {
+      const int gc = ga ^ gP;
+      for (int gb = 0; gb < h; ++gb) {
+        const int gd = gb ^ gP;
+        fv += 4.0 * double(nv[ga]) * nv[gb] * nv[gc] * nv[gd] * n_oo(ga ^ gb);
+      }
+      fl += 2.0 * double(nv[ga]) * nv[gc] * n_vv(gP) * nc[gP];
+    }
+  }
+  flops[0] = fv;
+  flops[1] = fl;
+  return CDCC_OK;
+}
+
 extern "C" const char *cdcc_status_string(int status) {
   switch (status) {
     case CDCC_OK: return "ok";

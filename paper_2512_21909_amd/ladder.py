@@ -99,6 +99,29 @@ def ladder_lambda(problems, precision="fp64", stream=None, tile_policy=0, batch_
     _lib.check(st, "cdcc_ladder_lambda")
 
 
+def vvvv_density(problems, stream=None, batch_bytes=0) -> None:
+    """vvvv two-body-density contraction G^P_ac = 1/2 sum_bd sum_mn
+    [Y_mn^ab X_mn^cd + Y_mn^cd X_mn^ab] L^P_bd (FP64) for one problem dict or
+    a list of them.  Keys: layout (Layout), L, X (tau~), Y (lambda), G (out;
+    Cholesky layout).  Asynchronous on ``stream``."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr = (_lib.DensityProblem * len(problems))()
+    keep = []
+    for k, p in enumerate(problems):
+        lay: Layout = p["layout"]
+        keep.append(lay)
+        q = arr[k]
+        q.lay = ctypes.pointer(lay.c)
+        q.L = _ptr(p["L"], lay.b_size, "L")
+        q.X = _ptr(p["X"], lay.amp_size, "X")
+        q.Y = _ptr(p["Y"], lay.amp_size, "Y")
+        q.G = _ptr(p["G"], lay.b_size, "G")
+    o = _opts("fp64", 0, batch_bytes)
+    st = _lib.load().cdcc_vvvv_density(len(problems), arr, ctypes.byref(o), _stream(stream))
+    _lib.check(st, "cdcc_vvvv_density")
+
+
 def workspace_bytes(problems, lambda_=False, precision="fp64", tile_policy=0, batch_bytes=0) -> int:
     if isinstance(problems, dict):
         problems = [problems]
@@ -114,7 +137,7 @@ def release() -> None:
     _lib.check(_lib.load().cdcc_release(), "cdcc_release")
 
 
-KERNEL_CLASSES = ("dress", "pack", "assemble", "contract", "energy", "slice", "unused6", "unused7")
+KERNEL_CLASSES = ("dress", "pack", "assemble", "contract", "energy", "slice", "density_w", "density_g")
 
 
 def timing_enable(on: bool = True) -> None:

@@ -92,6 +92,13 @@ class Layout:
         return np.concatenate([np.asarray(x, dtype=np.float64).ravel() for x in per_irrep]) \
             if per_irrep else np.zeros(0)
 
+    def density_flops(self):
+        """((ab|cd) products, contraction with L) algorithmic flops of the vvvv
+        density contraction (cdcc_density_flops)."""
+        out = (ctypes.c_double * 2)()
+        _lib.check(_lib.load().cdcc_density_flops(ctypes.byref(self.c), out), "cdcc_density_flops")
+        return float(out[0]), float(out[1])
+
     def flops(self, kind: int = 0):
         """(assembly, contraction, dressing) algorithmic flops (cdcc_ladder_flops)."""
         out = (ctypes.c_double * 3)()

@@ -156,3 +156,52 @@ def test_error_codes_before_device_work(lib):
     o.precision = 7
     assert L.cdcc_ladder_t2(1, arr, ctypes.byref(o), None) == lib.EINVAL
     assert L.cdcc_status_string(lib.ENOMEM).decode().startswith("device workspace")
+
+
+# ---------------------------------------------------------------- vvvv density
+def _brute_density_flops(sym):
+    h, no, nv, nc = sym["h"], sym["nocc"], sym["nvir"], sym["ncd"]
+    irr_v = [g for g in range(h) for _ in range(nv[g])]
+    irr_o = [g for g in range(h) for _ in range(no[g])]
+    irr_p = [g for g in range(h) for _ in range(nc[g])]
+    n_oo = [sum(1 for m in irr_o for n in irr_o if m ^ n == G) for G in range(h)]
+    fv = fl = 0
+    for a in irr_v:
+        for c in irr_v:
+            gP = a ^ c
+            if nc[gP] == 0:
+                continue
+            for b in irr_v:
+                for d in irr_v:
+                    if b ^ d != gP:
+                        continue
+                    fv += 4 * n_oo[a ^ b]
+                    fl += 2 * sum(1 for p in irr_p if p == gP)
+    return fv, fl
+
+
+@pytest.mark.parametrize("spec", [SPECS[1], SPECS[2], SPECS[4], ([1, 0], [3, 2], [2, 2])])
+def test_density_flops_match_enumeration(spec):
+    from paper_2512_21909_amd import Layout
+    sym = S.sym_custom(*spec)
+    got = Layout(sym).density_flops()
+    assert tuple(int(round(x)) for x in got) == _brute_density_flops(sym)
+
+
+def test_density_error_codes_before_device_work(lib):
+    L = lib.load()
+    s = lib.Sym()
+    out = lib.LayoutC()
+    s.nirrep = 2
+    s.nocc[0] = s.nvir[0] = s.ncd[0] = 1
+    assert L.cdcc_irrep_layout(ctypes.byref(s), ctypes.byref(out)) == lib.OK
+    arr = (lib.DensityProblem * 1)()
+    arr[0].lay = ctypes.pointer(out)
+    assert L.cdcc_vvvv_density(1, arr, None, None) == lib.EINVAL      # no pointers
+    assert L.cdcc_vvvv_density(-1, None, None, None) == lib.EINVAL
+    assert L.cdcc_vvvv_density(0, None, None, None) == lib.OK         # nothing to do
+    o = lib.Opts()
+    o.precision = lib.MIXED
+    arr[0].L = arr[0].X = arr[0].Y = arr[0].G = ctypes.c_void_p(0x1000)
+    assert L.cdcc_vvvv_density(1, arr, ctypes.byref(o), None) == lib.EUNSUPPORTED
+    assert L.cdcc_density_flops(None, None) == lib.EINVAL
