@@ -192,6 +192,97 @@ def cpu_baseline(entries, flops_step, budget_s=12.0):
                       f"NumPy + host BLAS) in {dt:.1f} s; rate = their algorithmic flops / time"}
 
 
+DENSITY_METRIC = "vvvv two-body-density contraction with Cholesky vectors, TFLOP/s (FP64)"
+
+
+def density_workload(name):
+    import synth as S
+    syms = {"vvvv_d2h_medium": ("vvvv density: 8 irreps, o=20, v=200, Ncd=1500 (all in the totally symmetric "
+                                "irrep)", S.sym_d2h_medium("A")),
+            "vvvv_d2h_medium_B": ("vvvv density: 8 irreps, o=20, v=200, Ncd=1500 (even split)",
+                                  S.sym_d2h_medium("B")),
+            "vvvv_c1_small": ("vvvv density: 1 irrep, o=8, v=40, Ncd=300", S.sym_c1_small())}
+    if name not in syms:
+        raise SystemExit(f"unknown workload {name}")
+    desc, sym = syms[name]
+    return desc, S.make_density_problem(sym, 0)
+
+
+def density_main(args, cdcc):
+    """One step = one vvvv density contraction; accuracy: every element
+    against the oracle (max error relative to max|G|)."""
+    import torch
+    import oracle as O
+    from oracle.layout import OracleLayout
+    from tests.gpu_support import to_dev
+    desc, prob = density_workload(args.workload)
+    sym = prob["sym"]
+    lay = cdcc.Layout(sym)
+    d = {"layout": lay, "L": to_dev(lay.pack_B(prob["L"])), "X": to_dev(lay.pack_amp(prob["X"])),
+         "Y": to_dev(lay.pack_amp(prob["Y"])), "G": torch.zeros(lay.b_size, dtype=torch.float64, device="cuda")}
+    fv, fl = lay.density_flops()
+    flops = fv + fl
+    print(f"[bench] {desc}; F_alg {flops:.4e} ((ab|cd) {fv:.4e}, contraction {fl:.4e})", file=sys.stderr, flush=True)
+    cdcc.vvvv_density([d])
+    torch.cuda.synchronize()
+    acc = None
+    if not args.no_check:
+        ref = OracleLayout(sym).pack_B(O.vvvv_density_blocks(sym, prob["X"], prob["Y"], prob["L"]))
+        err = float(np.max(np.abs(d["G"].cpu().numpy() - ref)))
+        acc = {"max_rel": err / float(np.max(np.abs(ref))), "checked": "every element"}
+    for _ in range(args.warmup):
+        cdcc.vvvv_density([d])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cdcc.vvvv_density([d])
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    cdcc.timing_read()
+    cdcc.timing_enable(True)
+    for _ in range(args.steps):
+        cdcc.vvvv_density([d])
+    torch.cuda.synchronize()
+    cdcc.timing_enable(False)
+    kt = cdcc.timing_read()
+    ok = acc is None or acc["max_rel"] <= 1e-12
+    print(f"[bench] density: {sec * 1e3:.3f} ms/step, {flops / sec / 1e12:.2f} TFLOP/s, gate ok={ok}, kernels={kt}",
+          file=sys.stderr, flush=True)
+    g_ms, g_n = kt.get("density_g", (0.0, 0))
+    w_ms, w_n = kt.get("density_w", (0.0, 0))
+    ach = fl * args.steps / (g_ms * 1e-3) / 1e12 if g_ms else 0.0
+    line = {
+        "metric": DENSITY_METRIC, "value": round(flops / sec / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "flops_per_step": flops, "path": "fp64"},
+        "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                     "frac": round(ach / PEAK["fp64"], 4), "traffic": None,
+                     "kernel": "contraction of the (ab|cd) batch with L", "launches": g_n,
+                     "avg_launch_ms": g_ms / max(g_n, 1), "flops_per_launch": fl * args.steps / max(g_n, 1)},
+        "stage_ab_cd": {"ms_per_step": w_ms / args.steps, "tflops": fv * args.steps / (w_ms * 1e-3) / 1e12 if w_ms else 0},
+        "accuracy": acc, "passes_gate": ok, "kernels_ms": kt,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max((x.get("num_threads", 1) for x in threadpool_info()), default=os.cpu_count())
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count()
+        reps = 0
+        t0 = time.perf_counter()
+        while reps < 20 and (reps == 0 or time.perf_counter() - t0 < 10.0):
+            O.vvvv_density_blocks(sym, prob["X"], prob["Y"], prob["L"])
+            reps += 1
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": flops * reps / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores),
+                                "kind": "oracle",
+                                "sample": f"the whole workload, {reps} oracle runs in {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +315,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload.startswith("vvvv_"):
+        density_main(args, cdcc)
+        return
     wdesc, entries = workload(args.workload)
     dev = build_inputs(cdcc, entries)
     flops_step = flops_assemble = 0.0
