@@ -261,6 +261,7 @@ def density_main(args, cdcc):
                      "kernel": "contraction of the (ab|cd) batch with L", "launches": g_n,
                      "avg_launch_ms": g_ms / max(g_n, 1), "flops_per_launch": fl * args.steps / max(g_n, 1)},
         "stage_ab_cd": {"ms_per_step": w_ms / args.steps, "tflops": fv * args.steps / (w_ms * 1e-3) / 1e12 if w_ms else 0},
+        "split_k_reduce_ms_per_step": kt.get("density_r", (0.0, 0))[0] / args.steps,
         "accuracy": acc, "passes_gate": ok, "kernels_ms": kt,
     }
     if not args.no_cpu_baseline:

@@ -212,12 +212,15 @@ int cdcc_workspace_bytes(int32_t nsys, const cdcc_problem_t *probs,
  * call records a HIP event pair on its own stream around each kernel class:
  * 0 = T1 dressing, 1 = amplitude packing, 2 = (ac|bd) batch assembly,
  * 3 = contraction + unpack, 4 = pair energies, 5 = operand slicing (mixed),
- * 6 = vvvv density (ab|cd) batch, 7 = vvvv density contraction with L.
+ * 6 = vvvv density (ab|cd) batch, 7 = vvvv density contraction with L,
+ * 8 = vvvv density split-K reduction.
  * cdcc_timing_read waits for the recorded events, returns the summed elapsed
- * milliseconds and launch counts per class (arrays of 8) and clears the record.
+ * milliseconds and launch counts per class (arrays of CDCC_TIMING_CLASSES)
+ * and clears the record.
  */
+#define CDCC_TIMING_CLASSES 9
 int cdcc_timing_enable(int32_t on);
-int cdcc_timing_read(double ms[8], int64_t launches[8]);
+int cdcc_timing_read(double ms[CDCC_TIMING_CLASSES], int64_t launches[CDCC_TIMING_CLASSES]);
 
 /* Static, human-readable text for a status code. */
 const char *cdcc_status_string(int status);

@@ -54,7 +54,9 @@ int occupancy_density_w();
 hipError_t launch_density_pack(const DensPackJob *jobs, const int2 *tiles, int ntiles, const DensPtrs *dp,
                                hipStream_t s);
 hipError_t launch_density_gemm(int grid, const GemmDesc *descs, const Tile *tiles, const Queues &Q, int *cnt,
-                               const DensPtrs *dp, const double *xbuf, hipStream_t s);
+                               const DensPtrs *dp, const double *xbuf, double *part, hipStream_t s);
+hipError_t launch_density_reduce(int njobs, const GemmDesc *descs, const Tile *jobs, const DensPtrs *dp,
+                                 const double *part, hipStream_t s);
 int occupancy_density_gemm();
 }  // namespace cdcc
 
@@ -1023,10 +1025,13 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
 // rows (a, c) (c in Ga^GP) times all (b, d) pairs of GP go to the batch
 // buffer (first stage: one T T'^T GEMM per Gb, K = 2 n_oo(Ga^Gb)); the second
 // stage multiplies the region by the GP block of L and writes the result rows
-// (a, c) of block (GP, Ga) directly.  Every result element is written once.
+// (a, c) of block (GP, Ga): directly when K = n_vv(GP) fits one segment, else
+// through partial tiles and the reduction.  Every result element is written
+// once.
 // ===========================================================================
 struct DensBatch {
   Launch w, g;
+  int rstart = 0, rcount = 0;  // reduction jobs
 };
 
 struct DensPlan {
@@ -1039,9 +1044,10 @@ struct DensPlan {
   Tile *wtiles = nullptr;
   GemmDesc *gdesc = nullptr;
   Tile *gtiles = nullptr;
+  Tile *rjobs = nullptr;
   std::vector<DensBatch> batches;
   int ncounters = 0;
-  int64_t xbuf_elems = 0;
+  int64_t xbuf_elems = 0, part_elems = 0;
   std::vector<int64_t> t_elems;
   ~DensPlan() {
     if (dtab) (void)hipFree(dtab);
@@ -1072,7 +1078,7 @@ Launch deal_tiles(std::vector<std::pair<int64_t, Tile>> &v, int chunk, int occ, 
 }
 
 int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t cap, DensPlan &P) {
-  constexpr int WBM = 128, WBN = 64, GBM = 128, GBN = 64;
+  constexpr int WBM = 128, WBN = 64, GBM = kGemmBM, GBN = kGemmBN;
   P.nsys = nsys;
   P.t_elems.assign(nsys, 0);
   const int64_t cap_elems = std::max<int64_t>(cap / 8, 1);
@@ -1114,10 +1120,11 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
     for (int gP = 0; gP < h; ++gP) {
       const int64_t kvv = L.n_vv[gP];
       if (nc[gP] == 0 || kvv == 0) continue;
+      const int64_t ldw = align_up(kvv, 4);  // W row stride: 32-byte aligned rows for the GEMM's A loads
       for (int ga = 0; ga < h; ++ga) {
         const int gc = ga ^ gP;
         if (nv[ga] == 0 || nv[gc] == 0) continue;
-        const int64_t per_a = int64_t(nv[gc]) * kvv;
+        const int64_t per_a = int64_t(nv[gc]) * ldw;
         const int step = int(std::max<int64_t>(1, std::min<int64_t>(nv[ga], cap_elems / std::max<int64_t>(per_a, 1))));
         for (int a0 = 0; a0 < nv[ga]; a0 += step) {
           const int a1 = std::min(nv[ga], a0 + step);
@@ -1141,7 +1148,7 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
             d.a_first = a0;
             d.ga0 = a0;
             d.tri = 0;
-            d.ldx = int(kvv);
+            d.ldx = int(ldw);
             d.xrow0 = int(L.vv_off[gP][gb]);
             d.aoff = K > 0 ? tw_off[G] + (L.vv_off[G][ga] + int64_t(a0) * nv[gb]) * K : 0;
             d.boff = K > 0 ? tv_off[G] + L.vv_off[G][gc] * K : 0;
@@ -1152,7 +1159,7 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
           g.M = (a1 - a0) * nv[gc];
           g.N = nc[gP];
           g.K = int(kvv);
-          g.lda = int(kvv);
+          g.lda = int(ldw);
           g.ldb = nc[gP];
           g.ldc = nc[gP];
           g.boff = L.b_off[gP][0];
@@ -1167,7 +1174,7 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
   // batches of regions under the cap
   std::vector<P1Desc> wd;
   std::vector<GemmDesc> gd;
-  std::vector<Tile> wt, gt;
+  std::vector<Tile> wt, gt, rjobs;
   const int occw = occupancy_density_w(), occg = occupancy_density_gemm();
   size_t ri = 0;
   int nl = 0;
@@ -1179,7 +1186,8 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
       ++rj;
     }
     std::vector<std::pair<int64_t, Tile>> tw, tg;
-    int64_t xo = 0;
+    int64_t xo = 0, po = 0;
+    const int rstart = int(rjobs.size());
     for (size_t k = ri; k < rj; ++k) {
       Region &R = regions[k];
       for (P1Desc d : R.w) {
@@ -1192,17 +1200,28 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
       }
       GemmDesc g = R.g;
       g.aoff = xo;
+      const int tm = (g.M + GBM - 1) / GBM, tn = (g.N + GBN - 1) / GBN;
+      g.nseg = (g.K + kGemmKSeg - 1) / kGemmKSeg;
+      g.tiles_n = tn;
+      g.poff = po;
+      if (g.nseg > 1) po += int64_t(tm) * tn * g.nseg * GBM * GBN;
       const int gid = int(gd.size());
       gd.push_back(g);
-      const int tm = (g.M + GBM - 1) / GBM, tn = (g.N + GBN - 1) / GBN;
       for (int a = 0; a < tm; ++a)
-        for (int b = 0; b < tn; ++b) tg.push_back({int64_t(g.K) + 1, Tile{gid, a, b, 0}});
+        for (int b = 0; b < tn; ++b) {
+          for (int sg = 0; sg < g.nseg; ++sg)
+            tg.push_back({int64_t(std::min(g.K - sg * kGemmKSeg, kGemmKSeg)) + 1, Tile{gid, a, b, sg}});
+          if (g.nseg > 1) rjobs.push_back(Tile{gid, a, b, 0});
+        }
       xo += align_up(R.elems, 32);
     }
     P.xbuf_elems = std::max(P.xbuf_elems, xo);
+    P.part_elems = std::max(P.part_elems, po);
     DensBatch B;
     B.w = deal_tiles(tw, 16, occw, wt);
     B.g = deal_tiles(tg, 16, occg, gt);
+    B.rstart = rstart;
+    B.rcount = int(rjobs.size()) - rstart;
     P.batches.push_back(B);
     nl += 2;
     ri = rj;
@@ -1210,7 +1229,7 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
   P.ncounters = 8 * std::max(nl, 1) * kQueueStride;
   TableBuilder T;
   const int64_t o_pj = T.add(packjobs), o_pt = T.add(packtiles), o_wd = T.add(wd), o_wt = T.add(wt);
-  const int64_t o_gd = T.add(gd), o_gt = T.add(gt);
+  const int64_t o_gd = T.add(gd), o_gt = T.add(gt), o_rj = T.add(rjobs);
   if (hipMalloc(&P.dtab, std::max<size_t>(T.bytes.size(), 256)) != hipSuccess) return CDCC_ENOMEM;
   if (hipMemcpy(P.dtab, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return CDCC_EDEVICE;
   char *b = static_cast<char *>(P.dtab);
@@ -1221,6 +1240,7 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
   P.wtiles = reinterpret_cast<Tile *>(b + o_wt);
   P.gdesc = reinterpret_cast<GemmDesc *>(b + o_gd);
   P.gtiles = reinterpret_cast<Tile *>(b + o_gt);
+  P.rjobs = reinterpret_cast<Tile *>(b + o_rj);
   return CDCC_OK;
 }
 
@@ -1237,7 +1257,7 @@ int validate_density(int32_t nsys, const cdcc_density_problem_t *probs) {
 }
 
 struct DensWs {
-  int64_t counters = 0, dptrs = 0, sptrs = 0, xbuf = 0, total = 0;
+  int64_t counters = 0, dptrs = 0, sptrs = 0, xbuf = 0, part = 0, total = 0;
   std::vector<int64_t> t;
 };
 DensWs dens_ws_layout(const DensPlan &P) {
@@ -1251,6 +1271,8 @@ DensWs dens_ws_layout(const DensPlan &P) {
   o = align_up(o + int64_t(P.nsys) * int64_t(sizeof(SysPtrs)));
   W.xbuf = o;
   o = align_up(o + P.xbuf_elems * 8);
+  W.part = o;
+  o = align_up(o + P.part_elems * 8);
   W.t.resize(P.nsys);
   for (int s = 0; s < P.nsys; ++s) {
     W.t[s] = o;
@@ -1323,6 +1345,7 @@ int run_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_op
 
   int *counters = reinterpret_cast<int *>(base + W.counters);
   double *xbuf = reinterpret_cast<double *>(base + W.xbuf);
+  double *part = reinterpret_cast<double *>(base + W.part);
   HIPCHK(launch_fill_int(counters, P->ncounters, 0, stream));
   {
     Span sp(1, P->npacktiles > 0, stream);
@@ -1338,7 +1361,11 @@ int run_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_op
     {
       Span sp(7, B.g.count > 0, stream);
       HIPCHK(launch_density_gemm(B.g.grid, P->gdesc, P->gtiles + B.g.start, B.g.q,
-                                 counters + 8 * kQueueStride * ci++, ddp, xbuf, stream));
+                                 counters + 8 * kQueueStride * ci++, ddp, xbuf, part, stream));
+    }
+    if (B.rcount > 0) {
+      Span sp(8, true, stream);
+      HIPCHK(launch_density_reduce(B.rcount, P->gdesc, P->rjobs + B.rstart, ddp, part, stream));
     }
   }
   return CDCC_OK;
@@ -1378,10 +1405,10 @@ extern "C" int cdcc_timing_enable(int32_t on) {
   return CDCC_OK;
 }
 
-extern "C" int cdcc_timing_read(double ms[8], int64_t launches[8]) {
+extern "C" int cdcc_timing_read(double ms[CDCC_TIMING_CLASSES], int64_t launches[CDCC_TIMING_CLASSES]) {
   if (!ms || !launches) return CDCC_EINVAL;
   std::lock_guard<std::mutex> lock(g_mu);
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < CDCC_TIMING_CLASSES; ++k) {
     ms[k] = 0.0;
     launches[k] = 0;
   }

@@ -15,13 +15,15 @@
 //          GEMM T T'^T with K = 2 n_oo (the assembly kernel, mode 1, writes
 //          W with rows (a, c) and columns (b, d) into a bounded batch buffer)
 //   gemm   G[(a,c)][P] = 1/2 W[(a,c)][(b,d)] L[(b,d)][P] over the (b, d) pairs
-//          of the Cholesky irrep (below)
+//          of the Cholesky irrep (below), K cut into fixed segments
+//   reduce partial tiles of the segments summed in segment order
 #include <hip/hip_runtime.h>
 
 #include "kernel_common.hpp"
 
 namespace cdcc {
 
+typedef double d2 __attribute__((ext_vector_type(2)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
@@ -68,18 +70,22 @@ __global__ __launch_bounds__(256) void density_pack_kernel(const DensPackJob *__
 }
 
 // ---------------------------------------------------------------------------
-// gemm (second stage): tile BM x BN of C = alpha A B, BK = 16, 4 waves in
-// 2 x 2, MFMA f64 16x16x4; A rows (K-contiguous) staged transposed into
-// LDS [k][m], B rows ([k][n], n-contiguous) staged as they are; double
-// buffered, one barrier per K step.  Out-of-range rows, columns and K are
-// read from clamped addresses and zeroed by a select.
+// gemm (second stage), persistent: one work unit = one BM x BN tile of one K
+// segment.  BK = 16, 4 waves in 2 x 2, MFMA f64 16x16x4.  A rows
+// (K-contiguous, lda a multiple of 4) are read 4 k at a time and staged
+// transposed into LDS [k][m]; B rows ([k][n], n-contiguous) are staged as
+// they are; double buffered, one barrier per K step.  Rows past M and columns
+// past N are read from clamped addresses and their results are not stored;
+// k past the segment end (last block only) reads a clamped address and is
+// zeroed by a select, so padding columns of A are never read.
 // ---------------------------------------------------------------------------
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_nn_f64_kernel(const GemmDesc *__restrict__ descs,
-                                                          const Tile *__restrict__ tiles, Queues Q,
-                                                          int *__restrict__ cnt,
-                                                          const DensPtrs *__restrict__ dp,
-                                                          const double *__restrict__ xbuf) {
+__global__ __launch_bounds__(256, 2) void gemm_nn_f64_kernel(const GemmDesc *__restrict__ descs,
+                                                             const Tile *__restrict__ tiles, Queues Q,
+                                                             int *__restrict__ cnt,
+                                                             const DensPtrs *__restrict__ dp,
+                                                             const double *__restrict__ xbuf,
+                                                             double *__restrict__ part) {
   constexpr int BK = 16;
   constexpr int LA = BM + 2, LB = BN + 2;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -105,24 +111,18 @@ __global__ __launch_bounds__(256) void gemm_nn_f64_kernel(const GemmDesc *__rest
     const GemmDesc D = descs[tl.desc];
     const DensPtrs P = dp[D.sys];
     const int m0 = tl.tm * BM, n0 = tl.tn * BN;
-    const int K = D.K;
+    const int kseg0 = tl.aux * kGemmKSeg;
+    const int K = min(D.K - kseg0, kGemmKSeg);
     const CDCC_GLOBAL double *arow[RA];
-    double am[RA];
 #pragma unroll
     for (int q = 0; q < RA; ++q) {
-      const int m = m0 + lr + 64 * q;
-      am[q] = m < D.M ? 1.0 : 0.0;
-      arow[q] = as_global(xbuf) + D.aoff + int64_t(m < D.M ? m : D.M - 1) * D.lda;
+      const int m = min(m0 + lr + 64 * q, D.M - 1);
+      arow[q] = as_global(xbuf) + D.aoff + int64_t(m) * D.lda + kseg0 + lk;
     }
-    const CDCC_GLOBAL double *bmat = as_global(P.L) + D.boff;
+    const CDCC_GLOBAL double *brow = as_global(P.L) + D.boff + int64_t(kseg0 + bk) * D.ldb;
     int bcol[CB];
-    double bm[CB];
 #pragma unroll
-    for (int e = 0; e < CB; ++e) {
-      const int n = n0 + bc + e;
-      bm[e] = n < D.N ? 1.0 : 0.0;
-      bcol[e] = n < D.N ? n : D.N - 1;
-    }
+    for (int e = 0; e < CB; ++e) bcol[e] = min(n0 + bc + e, D.N - 1);
 
     d4 acc[FM][FN];
 #pragma unroll
@@ -131,22 +131,38 @@ __global__ __launch_bounds__(256) void gemm_nn_f64_kernel(const GemmDesc *__rest
       for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
     double ra[RA][4], rb[CB];
-    auto gload = [&](int k0) {
+    auto gload = [&](int k0) {  // a whole block
+#pragma unroll
+      for (int q = 0; q < RA; ++q) {
+        const CDCC_GLOBAL d2 *pa = reinterpret_cast<const CDCC_GLOBAL d2 *>(arow[q] + k0);
+        const d2 u = pa[0], v = pa[1];
+        ra[q][0] = u.x;
+        ra[q][1] = u.y;
+        ra[q][2] = v.x;
+        ra[q][3] = v.y;
+      }
+      const CDCC_GLOBAL double *br = brow + int64_t(k0) * D.ldb;
+#pragma unroll
+      for (int e = 0; e < CB; ++e) rb[e] = br[bcol[e]];
+    };
+    auto gload_tail = [&](int k0) {  // the last, partial block
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = k0 + lk + e;
-        const bool kin = k < K;
-        const int kc = kin ? k : (K > 0 ? K - 1 : 0);
-        const double ka = kin ? 1.0 : 0.0;
+        const int kc = min(k, K - 1) - lk;
 #pragma unroll
-        for (int q = 0; q < RA; ++q) ra[q][e] = arow[q][kc] * (am[q] * ka);
+        for (int q = 0; q < RA; ++q) {
+          const double x = arow[q][kc];
+          ra[q][e] = k < K ? x : 0.0;
+        }
       }
       const int k = k0 + bk;
-      const bool kin = k < K;
-      const int64_t ko = int64_t(kin ? k : (K > 0 ? K - 1 : 0)) * D.ldb;
-      const double kb = kin ? 1.0 : 0.0;
+      const CDCC_GLOBAL double *br = brow + int64_t(min(k, K - 1) - bk) * D.ldb;
 #pragma unroll
-      for (int e = 0; e < CB; ++e) rb[e] = bmat[ko + bcol[e]] * (bm[e] * kb);
+      for (int e = 0; e < CB; ++e) {
+        const double x = br[bcol[e]];
+        rb[e] = k < K ? x : 0.0;
+      }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
@@ -157,13 +173,15 @@ __global__ __launch_bounds__(256) void gemm_nn_f64_kernel(const GemmDesc *__rest
       for (int e = 0; e < CB; ++e) Bs[buf][bk][bc + e] = rb[e];
     };
 
-    const int nk = (K + BK - 1) / BK;
-    gload(0);
+    const int nfull = K / BK, nk = (K + BK - 1) / BK;
+    if (nfull > 0) gload(0);
+    else gload_tail(0);
     lstore(0);
     __syncthreads();
     for (int kb = 0; kb < nk; ++kb) {
-      const int cur = kb & 1;
-      gload((kb + 1) * BK);
+      const int cur = kb & 1, kn = kb + 1;
+      if (kn < nfull) gload(kn * BK);
+      else if (kn < nk) gload_tail(kn * BK);
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
@@ -178,22 +196,61 @@ __global__ __launch_bounds__(256) void gemm_nn_f64_kernel(const GemmDesc *__rest
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
       }
-      lstore(cur ^ 1);
+      if (kn < nk) lstore(cur ^ 1);
       __syncthreads();
     }
 
-    double *__restrict__ C = P.G + D.coff;
+    if (D.nseg == 1) {
+      double *__restrict__ C = P.G + D.coff;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * r;
-          const int n = n0 + wn * WN + j * 16 + (lane & 15);
-          if (m >= D.M || n >= D.N) continue;
-          C[int64_t(m) * D.ldc + n] = D.alpha * acc[i][j][r];
-        }
+          for (int r = 0; r < 4; ++r) {
+            const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * r;
+            const int n = n0 + wn * WN + j * 16 + (lane & 15);
+            if (m >= D.M || n >= D.N) continue;
+            C[int64_t(m) * D.ldc + n] = D.alpha * acc[i][j][r];
+          }
+    } else {
+      double *__restrict__ pb =
+          part + D.poff + (int64_t(tl.tm * D.tiles_n + tl.tn) * D.nseg + tl.aux) * (BM * BN);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int lm = wm * WM + i * 16 + (lane >> 4) + 4 * r;
+            const int ln = wn * WN + j * 16 + (lane & 15);
+            pb[lm * BN + ln] = acc[i][j][r];
+          }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reduce (split K): one workgroup per output tile; the partial tiles are
+// summed in segment order, scaled by alpha and stored.
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(const GemmDesc *__restrict__ descs,
+                                                          const Tile *__restrict__ jobs,
+                                                          const DensPtrs *__restrict__ dp,
+                                                          const double *__restrict__ part) {
+  const Tile tl = jobs[blockIdx.x];
+  const GemmDesc D = descs[tl.desc];
+  double *__restrict__ C = dp[D.sys].G + D.coff;
+  const CDCC_GLOBAL double *pb =
+      as_global(part) + D.poff + int64_t(tl.tm * D.tiles_n + tl.tn) * D.nseg * (BM * BN);
+#pragma unroll 4
+  for (int e = threadIdx.x; e < BM * BN; e += 256) {
+    const int m = tl.tm * BM + e / BN, n = tl.tn * BN + e % BN;
+    if (m >= D.M || n >= D.N) continue;
+    double s = pb[e];
+    for (int k = 1; k < D.nseg; ++k) s += pb[int64_t(k) * (BM * BN) + e];
+    C[int64_t(m) * D.ldc + n] = D.alpha * s;
   }
 }
 
@@ -208,15 +265,23 @@ hipError_t launch_density_pack(const DensPackJob *jobs, const int2 *tiles, int n
 }
 
 hipError_t launch_density_gemm(int grid, const GemmDesc *descs, const Tile *tiles, const Queues &Q, int *cnt,
-                               const DensPtrs *dp, const double *xbuf, hipStream_t s) {
+                               const DensPtrs *dp, const double *xbuf, double *part, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  gemm_nn_f64_kernel<128, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, dp, xbuf);
+  gemm_nn_f64_kernel<kGemmBM, kGemmBN><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, dp, xbuf, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_density_reduce(int njobs, const GemmDesc *descs, const Tile *jobs, const DensPtrs *dp,
+                                 const double *part, hipStream_t s) {
+  if (njobs <= 0) return hipSuccess;
+  gemm_reduce_kernel<kGemmBM, kGemmBN><<<njobs, 256, 0, s>>>(descs, jobs, dp, part);
   return hipGetLastError();
 }
 
 int occupancy_density_gemm() {
   int n = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_nn_f64_kernel<128, 64>, 256, 0);
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_nn_f64_kernel<kGemmBM, kGemmBN>, 256, 0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 

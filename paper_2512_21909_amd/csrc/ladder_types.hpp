@@ -141,13 +141,21 @@ struct DensPackJob {
 };
 
 // One plain GEMM of the second stage: C = alpha A B, A rows K-contiguous
-// (lda), B row-major [K][N] (ldb), C row-major (ldc).
+// (lda, a multiple of 4), B row-major [K][N] (ldb), C row-major (ldc).
+// K is cut into segments of kGemmKSeg (the last one shorter); with more than
+// one segment every segment writes its BM x BN partial tile and a reduction
+// sums them in segment order, so the result depends on K only, not on the
+// batch the GEMM runs in.
+constexpr int kGemmKSeg = 2048;
+constexpr int kGemmBM = 128, kGemmBN = 64;
 struct GemmDesc {
   int32_t sys, M, N, K;
-  int32_t lda, ldb, ldc, pad0;
+  int32_t lda, ldb, ldc, nseg;
+  int32_t tiles_n, pad0;
   int64_t aoff;        // into the batch buffer
   int64_t boff;        // into DensPtrs::L
   int64_t coff;        // into DensPtrs::G
+  int64_t poff;        // into the partial-tile buffer (nseg > 1): [tm][tn][seg][BM * BN]
   double alpha;
 };
 

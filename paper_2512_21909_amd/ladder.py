@@ -137,7 +137,8 @@ def release() -> None:
     _lib.check(_lib.load().cdcc_release(), "cdcc_release")
 
 
-KERNEL_CLASSES = ("dress", "pack", "assemble", "contract", "energy", "slice", "density_w", "density_g")
+KERNEL_CLASSES = ("dress", "pack", "assemble", "contract", "energy", "slice", "density_w", "density_g",
+                  "density_r")
 
 
 def timing_enable(on: bool = True) -> None:
@@ -147,7 +148,8 @@ def timing_enable(on: bool = True) -> None:
 
 def timing_read() -> dict:
     """{class: (total_ms, launches)} since the last read (waits for the events)."""
-    ms = (ctypes.c_double * 8)()
-    n = (_lib._i64 * 8)()
+    nk = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * nk)()
+    n = (_lib._i64 * nk)()
     _lib.check(_lib.load().cdcc_timing_read(ms, n), "cdcc_timing_read")
-    return {KERNEL_CLASSES[k]: (float(ms[k]), int(n[k])) for k in range(8) if n[k]}
+    return {KERNEL_CLASSES[k]: (float(ms[k]), int(n[k])) for k in range(nk) if n[k]}

@@ -99,3 +99,42 @@ def test_repeatable(gpu_lib):
         d["G"].fill_(float("nan"))
         _run(cdcc, [d])
         assert np.array_equal(d["G"].cpu().numpy(), first)
+
+
+# K = n_vv(GP) above one GEMM K segment (2048): partial tiles and the
+# segment-order reduction; ragged last segments, K not a multiple of 4 (padded
+# W rows) or of the 16-wide K block, several segments per output tile.
+SPLIT_SYMS = [
+    ([2], [47], [9]),                  # K = 2209: segments 2048 + 161
+    ([1, 1], [40, 30], [5, 6]),        # K = 2500 (GP = 0), 2400 (GP = 1)
+    ([1], [68], [3]),                  # K = 4624: three segments, the last 528 = 33 blocks exactly
+]
+
+
+@pytest.mark.parametrize("spec", SPLIT_SYMS)
+def test_split_k_segments(gpu_lib, spec):
+    cdcc = gpu_lib
+    prob = S.make_density_problem(S.sym_custom(*spec), seed=21)
+    d = _dev(cdcc, prob)
+    _run(cdcc, [d])
+    got = d["G"].cpu().numpy()
+    assert np.all(np.isfinite(got))
+    assert _rel(got, _ref(prob)) <= TOL
+
+
+def test_split_k_batched_and_small_cap_bitwise(gpu_lib):
+    cdcc = gpu_lib
+    probs = [S.make_density_problem(S.sym_custom(*spec), seed=30 + k) for k, spec in enumerate(SPLIT_SYMS[:2])]
+    alone = []
+    for p in probs:
+        d = _dev(cdcc, p)
+        _run(cdcc, [d])
+        alone.append(d["G"].cpu().numpy())
+    ds = [_dev(cdcc, p) for p in probs]
+    _run(cdcc, ds)
+    for k, d in enumerate(ds):
+        assert np.array_equal(d["G"].cpu().numpy(), alone[k])
+    ds = [_dev(cdcc, p) for p in probs]
+    _run(cdcc, ds, batch_bytes=1 << 20)  # a few a per region, several batches
+    for k, d in enumerate(ds):
+        assert np.array_equal(d["G"].cpu().numpy(), alone[k])
