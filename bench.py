@@ -32,8 +32,10 @@ HBM_PEAK = 8000.0  # GB/s
 # Bytes one assembly launch moves between L2 and the memory fabric, from
 # rocprofv3 FETCH_SIZE + WRITE_SIZE per dispatch (scaled x2.0 and x1.0 by a
 # plain 256 MiB device copy), averaged over the T2 and Lambda launches of a
-# step; per (workload, path), for the kernels as committed (profiles/).
-TRAFFIC = {("d2h_medium", "mixed"): 2.8905e9, ("d2h_medium", "fp64"): 1.6339e9}
+# step; per (workload, path), for the kernels as committed (profiles/).  The
+# vvvv density entry is the density GEMM's launch, counted the same way.
+TRAFFIC = {("d2h_medium", "mixed"): 2.8905e9, ("d2h_medium", "fp64"): 1.6339e9,
+           ("vvvv_d2h_medium", "fp64"): 3.800e9}
 
 
 def workload(name):
@@ -257,7 +259,8 @@ def density_main(args, cdcc):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": desc, "flops_per_step": flops, "path": "fp64"},
         "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                     "frac": round(ach / PEAK["fp64"], 4), "traffic": None,
+                     "frac": round(ach / PEAK["fp64"], 4),
+                     "traffic": TRAFFIC.get((args.workload, "fp64")),
                      "kernel": "contraction of the (ab|cd) batch with L", "launches": g_n,
                      "avg_launch_ms": g_ms / max(g_n, 1), "flops_per_launch": fl * args.steps / max(g_n, 1)},
         "stage_ab_cd": {"ms_per_step": w_ms / args.steps, "tflops": fv * args.steps / (w_ms * 1e-3) / 1e12 if w_ms else 0},
