@@ -4,8 +4,11 @@ Follows the selection rule of the paper's symmetry section (a tensor element is
 stored only when the product of its index irreps is totally symmetric), for the
 flat layout the C ABI documents: amplitude blocks per pair irrep G, rows (i,j)
 ordered by irrep of i then i then j, columns (a,b) likewise; Cholesky blocks per
-(irrep of P, irrep of a) as [a][c][P]. Independent re-statement used to pin the
-library's layout function.
+(irrep of P, irrep of a) as [a][c][P]; tensors with one virtual and one
+occupied index in their first pair (lambda_bi^mn, M_bi^dc) as one block per
+pair irrep G with rows (b,i) ordered by irrep of b then b then i and the
+columns of the amplitude layout ((m,n) rows or (d,c) columns). Independent
+re-statement used to pin the library's layout function.
 """
 from __future__ import annotations
 
@@ -54,6 +57,22 @@ class OracleLayout:
         self.vir_off = list(np.concatenate([[0], np.cumsum(nv)[:-1]]).astype(int))
         self.cd_off = list(np.concatenate([[0], np.cumsum(nc)[:-1]]).astype(int))
         self.nocc_tot, self.nvir_tot, self.ncd_tot = sum(no), sum(nv), sum(nc)
+        # (b,i) rows: irrep of b, then b, then i
+        self.n_vo = [sum(nv[g] * no[g ^ G] for g in range(h)) for G in range(h)]
+        self.vo_off = [[0] * h for _ in range(h)]
+        for G in range(h):
+            r = 0
+            for g in range(h):
+                self.vo_off[G][g] = r
+                r += nv[g] * no[g ^ G]
+        self.lvo_off, self.mvo_off = [], []
+        ol = om = 0
+        for G in range(h):
+            self.lvo_off.append(ol)
+            self.mvo_off.append(om)
+            ol += self.n_vo[G] * self.n_oo[G]
+            om += self.n_vo[G] * self.n_vv[G]
+        self.lvo_size, self.mvo_size = ol, om
 
     # ---- flat <-> blocks -------------------------------------------------
     def pack_amp(self, blocks: dict) -> np.ndarray:
@@ -82,6 +101,55 @@ class OracleLayout:
                     gb = ga ^ G
                     c0, ncol = self.vv_off[G][ga], nv[ga] * nv[gb]
                     out[(G, gi, ga)] = mat[r0:r0 + nr, c0:c0 + ncol].reshape(no[gi], no[gj], nv[ga], nv[gb]).copy()
+        return out
+
+    def pack_vo(self, blocks: dict, right: str) -> np.ndarray:
+        """lambda_bi^mn (right = "oo") or M_bi^dc (right = "vv") blocks keyed
+        (G, gb, gm or gd) -> flat."""
+        h, no, nv = self.h, self.sym["nocc"], self.sym["nvir"]
+        ncols = self.n_oo if right == "oo" else self.n_vv
+        coff = self.oo_off if right == "oo" else self.vv_off
+        base = self.lvo_off if right == "oo" else self.mvo_off
+        cdim = no if right == "oo" else nv
+        flat = np.zeros(self.lvo_size if right == "oo" else self.mvo_size)
+        for G in range(h):
+            mat = flat[base[G]:base[G] + self.n_vo[G] * ncols[G]].reshape(self.n_vo[G], ncols[G])
+            for gb in range(h):
+                r0, nr = self.vo_off[G][gb], nv[gb] * no[gb ^ G]
+                for gx in range(h):
+                    c0, nc_ = coff[G][gx], cdim[gx] * cdim[gx ^ G]
+                    mat[r0:r0 + nr, c0:c0 + nc_] = blocks[(G, gb, gx)].reshape(nr, nc_)
+        return flat
+
+    def unpack_vo(self, flat: np.ndarray, right: str) -> dict:
+        h, no, nv = self.h, self.sym["nocc"], self.sym["nvir"]
+        ncols = self.n_oo if right == "oo" else self.n_vv
+        coff = self.oo_off if right == "oo" else self.vv_off
+        base = self.lvo_off if right == "oo" else self.mvo_off
+        cdim = no if right == "oo" else nv
+        out = {}
+        for G in range(h):
+            mat = np.asarray(flat[base[G]:base[G] + self.n_vo[G] * ncols[G]]).reshape(self.n_vo[G], ncols[G])
+            for gb in range(h):
+                gi = gb ^ G
+                r0, nr = self.vo_off[G][gb], nv[gb] * no[gi]
+                for gx in range(h):
+                    c0, nc_ = coff[G][gx], cdim[gx] * cdim[gx ^ G]
+                    out[(G, gb, gx)] = mat[r0:r0 + nr, c0:c0 + nc_].reshape(
+                        nv[gb], no[gi], cdim[gx], cdim[gx ^ G]).copy()
+        return out
+
+    def full_vo(self, blocks: dict, right: str) -> np.ndarray:
+        """Scatter vo blocks into a full (v, o, x, x) tensor (x = o or v)."""
+        h, no, nv = self.h, self.sym["nocc"], self.sym["nvir"]
+        xd = self.nocc_tot if right == "oo" else self.nvir_tot
+        xoff = self.occ_off if right == "oo" else self.vir_off
+        cdim = no if right == "oo" else nv
+        out = np.zeros((self.nvir_tot, self.nocc_tot, xd, xd))
+        for (G, gb, gx), blk in blocks.items():
+            gi, gy = gb ^ G, gx ^ G
+            b0, i0, x0, y0 = self.vir_off[gb], self.occ_off[gi], xoff[gx], xoff[gy]
+            out[b0:b0 + nv[gb], i0:i0 + no[gi], x0:x0 + cdim[gx], y0:y0 + cdim[gy]] = blk
         return out
 
     def pack_B(self, blocks: dict, vo: bool = False) -> np.ndarray:

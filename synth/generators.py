@@ -18,6 +18,10 @@ Conventions (Abelian groups D2h and subgroups, irreps 0..h-1, product = XOR):
 * amplitudes ``tau[(G, gi, ga)]`` / ``lam[...]``: array ``(o_gi, o_gj, v_ga, v_gb)``
   with ``gj = gi ^ G``, ``gb = ga ^ G`` (pair irrep ``G``).
 * ``eps_occ[g]``, ``eps_vir[g]``: orbital energies per irrep.
+* ``lam_vo[(G, gb, gm)]``: array ``(v_gb, o_gi, o_gm, o_gn)`` with
+  ``gi = gb ^ G``, ``gn = gm ^ G``, holding a tensor ``lambda_bi^mn`` with one
+  virtual and three occupied indices (pair irrep ``G`` of (b,i) and of (m,n)),
+  the left operand of the O(O^3 V^3) contraction ``M_bi^dc``.
 
 Value recipe (synthetic stand-ins for molecular data, none of which is
 available): ``eps_occ ~ U[-2,-0.5]``, ``eps_vir ~ U[0.2,3]``;
@@ -25,7 +29,8 @@ available): ``eps_occ ~ U[-2,-0.5]``, ``eps_vir ~ U[0.2,3]``;
 vector list, symmetrised ``(G + G^T)/sqrt(2)`` off the diagonal;
 ``t2 = N(0,1) * 0.01 / (e_a + e_b - e_i - e_j)`` averaged with its pair
 transpose so that ``t2_ij^ab = t2_ji^ba``; ``t1 ~ N(0, (1e-3)^2)``;
-``tau = t2 + t1 t1``; ``lambda`` drawn like ``t2``; ``Bvo`` like ``B``.
+``tau = t2 + t1 t1``; ``lambda`` drawn like ``t2``; ``Bvo`` like ``B``;
+``lam_vo ~ N(0, (1e-3)^2)`` (no permutational symmetry).
 Every block draws from ``numpy.random.default_rng([seed, tensor_id, ...])`` so
 the values do not depend on generation order.
 """
@@ -39,7 +44,8 @@ __all__ = [
     "SPLIT_D2H", "largest_remainder_split", "sym_c1_small", "sym_d2h_medium",
     "sym_d2h_large", "sym_serving_large", "sym_custom", "dirichlet_sym",
     "batch_syms", "make_eps", "make_B", "make_Bvo", "make_t1", "make_t2",
-    "make_tau", "make_lambda", "make_problem", "make_density_problem", "irrep_pairs",
+    "make_tau", "make_lambda", "make_problem", "make_density_problem", "make_lam_vo",
+    "make_partial_problem", "irrep_pairs",
     "serving_stream", "TENSOR_IDS",
 ]
 
@@ -48,7 +54,7 @@ SPLIT_D2H = (Fraction(20, 100), Fraction(11, 100), Fraction(15, 100), Fraction(1
              Fraction(16, 100), Fraction(9, 100), Fraction(11, 100), Fraction(8, 100))
 
 TENSOR_IDS = {"eps_occ": 1, "eps_vir": 2, "B": 3, "Bvo": 4, "t1": 5, "t2": 6,
-              "lam": 7, "Bsym": 8}
+              "lam": 7, "Bsym": 8, "lam_vo": 9}
 
 
 def largest_remainder_split(total: int, weights) -> list[int]:
@@ -276,6 +282,30 @@ def make_density_problem(sym: dict, seed: int = 0) -> dict:
     t1 = make_t1(sym, seed)
     return {"sym": sym, "kind": "density", "L": make_B(sym, seed + 7919, True),
             "X": make_tau(sym, make_t2(sym, seed, eps), t1), "Y": make_lambda(sym, seed, eps)}
+
+
+def make_lam_vo(sym: dict, seed: int = 0) -> dict:
+    """lambda_bi^mn blocks ``(v_gb, o_gi, o_gm, o_gn)``, N(0, (1e-3)^2)."""
+    h, no, nv = sym["h"], sym["nocc"], sym["nvir"]
+    out = {}
+    for G in range(h):
+        for gb in range(h):
+            gi = gb ^ G
+            for gm in range(h):
+                gn = gm ^ G
+                rng = np.random.default_rng([seed, TENSOR_IDS["lam_vo"], G, gb, gm])
+                out[(G, gb, gm)] = 1e-3 * rng.standard_normal((nv[gb], no[gi], no[gm], no[gn]))
+    return out
+
+
+def make_partial_problem(sym: dict, seed: int = 0) -> dict:
+    """Inputs of one O(O^3 V^3) contraction M_bi^dc = sum_mn lambda_bi^mn
+    tau~_mn^dc: ``lam`` (lam_vo blocks) and ``tau`` (the tau recipe, pair
+    symmetric)."""
+    eps = make_eps(sym, seed)
+    t1 = make_t1(sym, seed)
+    return {"sym": sym, "kind": "partial", "lam": make_lam_vo(sym, seed),
+            "tau": make_tau(sym, make_t2(sym, seed, eps), t1)}
 
 
 def serving_stream(n_requests: int, rate_hz: float, seed: int = 5, p_large: float = 0.1):
