@@ -192,6 +192,66 @@ int cdcc_vvvv_density(int32_t nsys, const cdcc_density_problem_t *probs,
 int cdcc_density_flops(const cdcc_layout_t *lay, double flops[2]);
 
 /*
+ * Layout of tensors whose first index pair is (virtual b, occupied i), filled
+ * by cdcc_vo_layout from a layout of cdcc_irrep_layout.  One block per pair
+ * irrep G (Gb^Gi = G), row-major with rows (b,i): row
+ * vo_off[G][Gb] + b*nocc[Gi] + i (b, i local to their irrep), n_vo[G] rows.
+ *   lambda_bi^mn: block at lam_off[G], n_vo[G] x n_oo[G], columns (m,n) as
+ *     the rows of the amplitude layout (oo_off[G][Gm] + m*nocc[Gn] + n);
+ *   M_bi^dc:      block at m_off[G],   n_vo[G] x n_vv[G], columns (d,c) as
+ *     the columns of the amplitude layout (vv_off[G][Gd] + d*nvir[Gc] + c).
+ * Host only; CDCC_EINVAL for a NULL pointer.
+ */
+typedef struct {
+  int64_t n_vo[CDCC_MAX_IRREP];
+  int64_t vo_off[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
+  int64_t lam_off[CDCC_MAX_IRREP];
+  int64_t m_off[CDCC_MAX_IRREP];
+  int64_t lam_size, m_size;
+} cdcc_vo_layout_t;
+
+int cdcc_vo_layout(const cdcc_layout_t *lay, cdcc_vo_layout_t *out);
+
+/*
+ * O(O^3 V^3) contraction with the partial symmetric-antisymmetric algorithm
+ * (paper: the paragraph closing the section on the I_pq multipliers, example
+ * M_bi^dc = sum_mn lambda_Bi^Mn tau~_mn^dc, half the flops of the plain
+ * contraction):
+ *
+ *   M_bi^dc = sum_mn lambda_bi^mn tau_mn^dc
+ *
+ * lam = lambda_bi^mn (vo layout, lam_off; any values, no symmetry assumed),
+ * tau = tau~_mn^dc in the amplitude layout, which must be pair symmetric
+ * (tau_mn^dc = tau_nm^cd; only its rows with m >= n are read), M = the
+ * result in the vo layout (m_off); every element of M is written.
+ */
+typedef struct {
+  const cdcc_layout_t *lay;  /* host pointer, read during the call only        */
+  const double *lam;         /* device, cdcc_vo_layout lam_size                 */
+  const double *tau;         /* device, lay->amp_size                           */
+  double *M;                 /* device out, cdcc_vo_layout m_size               */
+} cdcc_partial_problem_t;
+
+/*
+ * The contraction above for nsys >= 0 independent systems, FP64 MFMA,
+ * asynchronous on `stream`.  opts may be NULL; precision must be CDCC_FP64
+ * (CDCC_MIXED returns CDCC_EUNSUPPORTED); the other options are ignored.
+ * CDCC_EINVAL for nsys < 0, NULL probs with nsys > 0 or a NULL required
+ * pointer; CDCC_ENOMEM, CDCC_EDEVICE as for cdcc_ladder_t2.  Inputs must not
+ * overlap M.
+ */
+int cdcc_partial_contract(int32_t nsys, const cdcc_partial_problem_t *probs,
+                          const cdcc_opts_t *opts, void *stream);
+
+/*
+ * Algorithmic flop count of one partial contraction (host only): flops[0] =
+ * the symmetric half S (2 flops per (b,i), m>=n, d>=c term), flops[1] = the
+ * antisymmetric half A (2 flops per (b,i), m>n, d>c term); symmetry-allowed
+ * blocks only.  The plain contraction costs 2 n_vo n_oo n_vv per irrep.
+ */
+int cdcc_partial_flops(const cdcc_layout_t *lay, double flops[2]);
+
+/*
  * Algorithmic flop count of one evaluation (host only): flops[0] = (ac|bd)
  * assembly, flops[1] = contraction, flops[2] = T1 dressing (Lambda with t1).
  * kind: 0 = T2, 1 = Lambda, 2 = Lambda with dressing.  Counts the stored
@@ -213,12 +273,13 @@ int cdcc_workspace_bytes(int32_t nsys, const cdcc_problem_t *probs,
  * 0 = T1 dressing, 1 = amplitude packing, 2 = (ac|bd) batch assembly,
  * 3 = contraction + unpack, 4 = pair energies, 5 = operand slicing (mixed),
  * 6 = vvvv density (ab|cd) batch, 7 = vvvv density contraction with L,
- * 8 = vvvv density split-K reduction.
+ * 8 = vvvv density split-K reduction, 9 = partial contraction +/- packing,
+ * 10 = partial contraction GEMM.
  * cdcc_timing_read waits for the recorded events, returns the summed elapsed
  * milliseconds and launch counts per class (arrays of CDCC_TIMING_CLASSES)
  * and clears the record.
  */
-#define CDCC_TIMING_CLASSES 9
+#define CDCC_TIMING_CLASSES 11
 int cdcc_timing_enable(int32_t on);
 int cdcc_timing_read(double ms[CDCC_TIMING_CLASSES], int64_t launches[CDCC_TIMING_CLASSES]);
 

@@ -50,13 +50,26 @@ class DensityProblem(ctypes.Structure):
     ]
 
 
+class VoLayoutC(ctypes.Structure):
+    _fields_ = [("n_vo", _L8), ("vo_off", _L88), ("lam_off", _L8), ("m_off", _L8),
+                ("lam_size", _i64), ("m_size", _i64)]
+
+
+class PartialProblem(ctypes.Structure):
+    _fields_ = [
+        ("lay", ctypes.POINTER(LayoutC)),
+        ("lam", ctypes.c_void_p), ("tau", ctypes.c_void_p), ("M", ctypes.c_void_p),
+    ]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("precision", _i32), ("tile_policy", _i32), ("batch_bytes", _i64)]
 
 
 EXPORTS = ["cdcc_irrep_layout", "cdcc_ladder_t2", "cdcc_ladder_lambda", "cdcc_ladder_flops",
            "cdcc_workspace_bytes", "cdcc_timing_enable", "cdcc_timing_read", "cdcc_status_string",
-           "cdcc_release", "cdcc_vvvv_density", "cdcc_density_flops"]
+           "cdcc_release", "cdcc_vvvv_density", "cdcc_density_flops", "cdcc_vo_layout",
+           "cdcc_partial_contract", "cdcc_partial_flops"]
 
 _lib = None
 
@@ -90,6 +103,13 @@ def load() -> ctypes.CDLL:
     lib.cdcc_vvvv_density.restype = ctypes.c_int
     lib.cdcc_density_flops.argtypes = [ctypes.POINTER(LayoutC), ctypes.POINTER(ctypes.c_double)]
     lib.cdcc_density_flops.restype = ctypes.c_int
+    lib.cdcc_vo_layout.argtypes = [ctypes.POINTER(LayoutC), ctypes.POINTER(VoLayoutC)]
+    lib.cdcc_vo_layout.restype = ctypes.c_int
+    lib.cdcc_partial_contract.argtypes = [_i32, ctypes.POINTER(PartialProblem), ctypes.POINTER(Opts),
+                                          ctypes.c_void_p]
+    lib.cdcc_partial_contract.restype = ctypes.c_int
+    lib.cdcc_partial_flops.argtypes = [ctypes.POINTER(LayoutC), ctypes.POINTER(ctypes.c_double)]
+    lib.cdcc_partial_flops.restype = ctypes.c_int
     lib.cdcc_release.argtypes = []
     lib.cdcc_release.restype = ctypes.c_int
     _lib = lib

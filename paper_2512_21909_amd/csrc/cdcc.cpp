@@ -57,6 +57,11 @@ hipError_t launch_density_gemm(int grid, const GemmDesc *descs, const Tile *tile
                                const DensPtrs *dp, const double *xbuf, double *part, hipStream_t s);
 hipError_t launch_density_reduce(int njobs, const GemmDesc *descs, const Tile *jobs, const DensPtrs *dp,
                                  const double *part, hipStream_t s);
+// partial symmetric-antisymmetric contraction (kernels_partial.hip)
+hipError_t launch_pm_pack(const PmDesc *descs, const PmChunk *lch, int nl, const PmChunk *tch, int nt,
+                          const int2 *kp, const PmSquare *sqs, const PmPtrs *pp, hipStream_t s);
+hipError_t launch_pm_gemm(const PmDesc *descs, const int4 *tiles, int ntiles, const PmSquare *sqs,
+                          const PmPtrs *pp, hipStream_t s);
 int occupancy_density_gemm();
 }  // namespace cdcc
 
@@ -1371,7 +1376,202 @@ int run_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_op
   return CDCC_OK;
 }
 
+// ===========================================================================
+// O(O^3 V^3) contraction, partial symmetric-antisymmetric algorithm (the
+// paragraph closing the I_pq section): M_bi^dc = sum_mn lam_bi^mn tau_mn^dc.
+// One block per (system, pair irrep G) with rows (b,i); K = the m >= n pairs
+// of G; columns = squares of 8 d x 8 c over the d >= c pairs.  Each launch
+// covers every block of every system; every element of M is written once.
+// ===========================================================================
+struct PmPlan {
+  int nsys = 0;
+  void *dtab = nullptr;
+  PmDesc *descs = nullptr;
+  int4 *tiles = nullptr;
+  int ntiles = 0;
+  PmSquare *sqs = nullptr;
+  int2 *kp = nullptr;
+  PmChunk *lchunks = nullptr, *tchunks = nullptr;
+  int nlchunks = 0, ntchunks = 0;
+  std::vector<int64_t> ws_elems;
+  ~PmPlan() {
+    if (dtab) (void)hipFree(dtab);
+  }
+};
+std::map<std::string, std::shared_ptr<PmPlan>> g_pmplans;
+
+int build_pm_plan(int nsys, const cdcc_partial_problem_t *probs, PmPlan &P) {
+  constexpr int BM = 64;
+  P.nsys = nsys;
+  P.ws_elems.assign(nsys, 0);
+  std::vector<PmDesc> descs;
+  std::vector<int4> tiles;
+  std::vector<PmSquare> sqs;
+  std::vector<int2> kp;
+  std::vector<PmChunk> lch, tch;
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_layout_t &L = *probs[s].lay;
+    cdcc_vo_layout_t V;
+    if (cdcc_vo_layout(&L, &V) != CDCC_OK) return CDCC_EINVAL;
+    const int h = L.sym.nirrep;
+    const int32_t *no = L.sym.nocc, *nv = L.sym.nvir;
+    int64_t wo = 0;
+    for (int G = 0; G < h; ++G) {
+      if (V.n_vo[G] == 0 || L.n_vv[G] == 0) continue;
+      PmDesc D{};
+      D.sys = s;
+      D.nrow = int(V.n_vo[G]);
+      D.kp_off = int(kp.size());
+      for (int gm = 0; gm < h; ++gm) {
+        const int gn = gm ^ G;
+        if (gm < gn) continue;
+        for (int m = 0; m < no[gm]; ++m)
+          for (int n = 0; n < (gm == gn ? m + 1 : no[gn]); ++n)
+            kp.push_back(int2{int(L.oo_off[G][gm] + int64_t(m) * no[gn] + n),
+                              int(L.oo_off[G][gn] + int64_t(n) * no[gm] + m)});
+      }
+      D.nk = int(kp.size()) - D.kp_off;
+      D.ldk = int(align_up(int64_t(D.nk), 16));
+      D.sq_off = int(sqs.size());
+      for (int gd = 0; gd < h; ++gd) {
+        const int gc = gd ^ G;
+        if (gd < gc || nv[gd] == 0 || nv[gc] == 0) continue;
+        const int nbd = (nv[gd] + 7) / 8, nbc = (nv[gc] + 7) / 8;
+        for (int dB = 0; dB < nbd; ++dB)
+          for (int cB = 0; cB < nbc; ++cB) {
+            if (gd == gc && cB > dB) continue;
+            PmSquare Q{};
+            Q.base_dc = int(L.vv_off[G][gd] + int64_t(dB) * 8 * nv[gc] + cB * 8);
+            Q.base_cd = int(L.vv_off[G][gc] + int64_t(cB) * 8 * nv[gd] + dB * 8);
+            Q.ld_dc = nv[gc];
+            Q.ld_cd = nv[gd];
+            Q.nd = std::min(8, nv[gd] - dB * 8);
+            Q.nc = std::min(8, nv[gc] - cB * 8);
+            Q.diag = (gd == gc && dB == cB) ? 1 : 0;
+            sqs.push_back(Q);
+          }
+      }
+      D.nsq = int(sqs.size()) - D.sq_off;
+      D.lam_off = V.lam_off[G];
+      D.tau_off = L.amp_off[G];
+      D.m_off = V.m_off[G];
+      D.n_oo = L.n_oo[G];
+      D.n_vv = L.n_vv[G];
+      D.lp_off = wo;
+      wo += align_up(2 * int64_t(D.nrow) * D.ldk, 32);
+      D.tp_off = wo;
+      wo += align_up(2 * int64_t(D.ldk) * D.nsq * 64, 32);
+      const int did = int(descs.size());
+      descs.push_back(D);
+      const int tm = (D.nrow + BM - 1) / BM;
+      for (int a = 0; a < tm; ++a)
+        for (int q = 0; q < D.nsq; ++q) tiles.push_back(int4{did, a, q, 0});
+      const int64_t nl = (int64_t(D.nrow) * D.ldk + 255) / 256, nt = (int64_t(D.ldk) * D.nsq * 64 + 255) / 256;
+      for (int64_t c = 0; c < nl; ++c) lch.push_back(PmChunk{did, int(c)});
+      for (int64_t c = 0; c < nt; ++c) tch.push_back(PmChunk{did, int(c)});
+    }
+    P.ws_elems[s] = wo;
+  }
+  TableBuilder T;
+  const int64_t o_d = T.add(descs), o_t = T.add(tiles), o_s = T.add(sqs), o_k = T.add(kp);
+  const int64_t o_l = T.add(lch), o_c = T.add(tch);
+  if (hipMalloc(&P.dtab, std::max<size_t>(T.bytes.size(), 256)) != hipSuccess) return CDCC_ENOMEM;
+  if (hipMemcpy(P.dtab, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return CDCC_EDEVICE;
+  char *b = static_cast<char *>(P.dtab);
+  P.descs = reinterpret_cast<PmDesc *>(b + o_d);
+  P.tiles = reinterpret_cast<int4 *>(b + o_t);
+  P.ntiles = int(tiles.size());
+  P.sqs = reinterpret_cast<PmSquare *>(b + o_s);
+  P.kp = reinterpret_cast<int2 *>(b + o_k);
+  P.lchunks = reinterpret_cast<PmChunk *>(b + o_l);
+  P.nlchunks = int(lch.size());
+  P.tchunks = reinterpret_cast<PmChunk *>(b + o_c);
+  P.ntchunks = int(tch.size());
+  return CDCC_OK;
+}
+
+int validate_partial(int32_t nsys, const cdcc_partial_problem_t *probs) {
+  if (nsys < 0 || (nsys > 0 && !probs)) return CDCC_EINVAL;
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_partial_problem_t &p = probs[s];
+    if (!p.lay) return CDCC_EINVAL;
+    if (!valid_sym(p.lay->sym)) return p.lay->sym.nirrep > 0 ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+    cdcc_vo_layout_t V;
+    if (cdcc_vo_layout(p.lay, &V) != CDCC_OK) return CDCC_EINVAL;
+    if (V.m_size > 0 && (!p.lam || !p.tau || !p.M)) return CDCC_EINVAL;
+  }
+  return CDCC_OK;
+}
+
+int run_partial(int32_t nsys, const cdcc_partial_problem_t *probs, const cdcc_opts_t *popts, void *vstream) {
+  cdcc_opts_t opts{};
+  if (popts) opts = *popts;
+  if (opts.precision != CDCC_FP64) return opts.precision == CDCC_MIXED ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+  int rc = validate_partial(nsys, probs);
+  if (rc != CDCC_OK) return rc;
+  if (nsys == 0) return CDCC_OK;
+  hipStream_t stream = static_cast<hipStream_t>(vstream);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_mu);
+  std::string key = "partial|" + std::to_string(dev) + "|" + std::to_string(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_sym_t &y = probs[s].lay->sym;
+    key += "|" + std::to_string(y.nirrep);
+    for (int g = 0; g < y.nirrep; ++g) key += "," + std::to_string(y.nocc[g]) + "," + std::to_string(y.nvir[g]);
+  }
+  std::shared_ptr<PmPlan> P;
+  auto it = g_pmplans.find(key);
+  if (it != g_pmplans.end()) {
+    P = it->second;
+  } else {
+    P = std::make_shared<PmPlan>();
+    rc = build_pm_plan(nsys, probs, *P);
+    if (rc != CDCC_OK) return rc;
+    if (g_pmplans.size() > 64) g_pmplans.clear();
+    g_pmplans[key] = P;
+  }
+  int64_t total = align_up(int64_t(nsys) * int64_t(sizeof(PmPtrs)));
+  std::vector<int64_t> wofs(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    wofs[s] = total;
+    total = align_up(total + P->ws_elems[s] * 8);
+  }
+  Workspace *ws = nullptr;
+  rc = get_workspace(dev, stream, std::max<int64_t>(total, 256), int64_t(nsys) * int64_t(sizeof(PmPtrs)), ws);
+  if (rc != CDCC_OK) return rc;
+  char *base = static_cast<char *>(ws->dev);
+  if (ws->ev_recorded) HIPCHK(hipEventSynchronize(ws->ev));
+  PmPtrs *hp = static_cast<PmPtrs *>(ws->staging);
+  for (int s = 0; s < nsys; ++s) {
+    PmPtrs q{};
+    q.lam = probs[s].lam;
+    q.tau = probs[s].tau;
+    q.M = probs[s].M;
+    q.ws = reinterpret_cast<double *>(base + wofs[s]);
+    hp[s] = q;
+  }
+  PmPtrs *dpp = reinterpret_cast<PmPtrs *>(base);
+  HIPCHK(hipMemcpyAsync(dpp, hp, size_t(nsys) * sizeof(PmPtrs), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(ws->ev, stream));
+  ws->ev_recorded = true;
+  {
+    Span sp(9, P->nlchunks + P->ntchunks > 0, stream);
+    HIPCHK(launch_pm_pack(P->descs, P->lchunks, P->nlchunks, P->tchunks, P->ntchunks, P->kp, P->sqs, dpp, stream));
+  }
+  {
+    Span sp(10, P->ntiles > 0, stream);
+    HIPCHK(launch_pm_gemm(P->descs, P->tiles, P->ntiles, P->sqs, dpp, stream));
+  }
+  return CDCC_OK;
+}
+
 }  // namespace
+
+extern "C" int cdcc_partial_contract(int32_t nsys, const cdcc_partial_problem_t *probs, const cdcc_opts_t *opts,
+                                     void *stream) {
+  return run_partial(nsys, probs, opts, stream);
+}
 
 extern "C" int cdcc_ladder_t2(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *opts, void *stream) {
   return run_ladder(nsys, probs, opts, stream, 0);
@@ -1433,6 +1633,7 @@ extern "C" int cdcc_vvvv_density(int32_t nsys, const cdcc_density_problem_t *pro
 extern "C" int cdcc_release(void) {
   std::lock_guard<std::mutex> lock(g_mu);
   g_dplans.clear();
+  g_pmplans.clear();
   delete g_tile_table;  // re-read on the next plan
   g_tile_table = nullptr;
   if (hipDeviceSynchronize() != hipSuccess) return CDCC_EDEVICE;

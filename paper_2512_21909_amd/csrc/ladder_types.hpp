@@ -159,4 +159,44 @@ struct GemmDesc {
   double alpha;
 };
 
+// Partial symmetric-antisymmetric contraction M_bi^dc = sum_mn lam_bi^mn
+// tau_mn^dc: per-system pointers.
+struct PmPtrs {
+  const double *lam;   // lambda_bi^mn (vo layout)
+  const double *tau;   // tau~_mn^dc (amplitude layout, pair symmetric)
+  double *M;           // result (vo layout)
+  double *ws;          // workspace: packed lam+/lam- and tau+/tau- of this system
+};
+
+// One (system, pair irrep G) block.  K = the m >= n pairs of G (kp table
+// entries [kp_off, kp_off + nk): oo-column indices of (m,n) and (n,m)),
+// padded with zeros to ldk (a multiple of 16).  Columns = squares of 8 d x 8
+// c (square table entries [sq_off, sq_off + nsq)), 64 columns each.
+struct PmDesc {
+  int32_t sys, nrow, nk, ldk;     // nrow = n_vo(G)
+  int32_t nsq, kp_off, sq_off, pad0;
+  int64_t lam_off;                // block of lambda (n_vo x n_oo)
+  int64_t tau_off;                // block of tau (n_oo x n_vv)
+  int64_t m_off;                  // block of M (n_vo x n_vv)
+  int64_t n_oo, n_vv;             // row strides of lambda and of tau / M
+  int64_t lp_off;                 // ws: lam+ [nrow][ldk], lam- follows
+  int64_t tp_off;                 // ws: tau+ [ldk][nsq * 64], tau- follows
+};
+
+// A square of the d >= c column pairs: d in [d0, d0 + nd) of irrep Gd, c in
+// [c0, c0 + nc) of irrep Gc (Gd > Gc, or Gd == Gc and the d block at or
+// after the c block).  Column of (d,c) in the amplitude layout:
+// base_dc + dd * ld_dc + cc; column of (c,d): base_cd + cc * ld_cd + dd
+// (dd, cc local to the square).  diag: the square sits on the d = c block
+// diagonal and holds both orders, so only (d,c) is written.
+struct PmSquare {
+  int32_t base_dc, base_cd, ld_dc, ld_cd;
+  int32_t nd, nc, diag, pad0;
+};
+
+// Work of the +/- packing kernels: one chunk of 256 elements of one block.
+struct PmChunk {
+  int32_t desc, chunk;
+};
+
 }  // namespace cdcc

@@ -168,6 +168,61 @@ extern "C" int cdcc_density_flops(const cdcc_layout_t *lay, double flops[2]) {
   return CDCC_OK;
 }
 
+extern "C" int cdcc_vo_layout(const cdcc_layout_t *lay, cdcc_vo_layout_t *out) {
+  if (!lay || !out) return CDCC_EINVAL;
+  const int h = lay->sym.nirrep;
+  if (!valid_h(h)) return CDCC_EUNSUPPORTED;
+  const int32_t *no = lay->sym.nocc, *nv = lay->sym.nvir;
+  *out = cdcc_vo_layout_t{};
+  int64_t ol = 0, om = 0;
+  for (int G = 0; G < h; ++G) {
+    int64_t r = 0;
+    for (int gb = 0; gb < h; ++gb) {
+      out->vo_off[G][gb] = r;
+      r += int64_t(nv[gb]) * no[gb ^ G];
+    }
+    out->n_vo[G] = r;
+    out->lam_off[G] = ol;
+    out->m_off[G] = om;
+    ol += r * lay->n_oo[G];
+    om += r * lay->n_vv[G];
+  }
+  out->lam_size = ol;
+  out->m_size = om;
+  return CDCC_OK;
+}
+
+extern "C" int cdcc_partial_flops(const cdcc_layout_t *lay, double flops[2]) {
+  if (!lay || !flops) return CDCC_EINVAL;
+  const int h = lay->sym.nirrep;
+  if (!valid_h(h)) return CDCC_EUNSUPPORTED;
+  const int32_t *no = lay->sym.nocc, *nv = lay->sym.nvir;
+  double fs = 0, fa = 0;
+  for (int G = 0; G < h; ++G) {
+    double nvo = 0, kp = 0, km = 0, cp = 0, cm = 0;
+    for (int g = 0; g < h; ++g) {
+      nvo += double(nv[g]) * no[g ^ G];
+      const int g2 = g ^ G;
+      if (g > g2) {
+        kp += double(no[g]) * no[g2];
+        km += double(no[g]) * no[g2];
+        cp += double(nv[g]) * nv[g2];
+        cm += double(nv[g]) * nv[g2];
+      } else if (g == g2) {
+        kp += double(no[g]) * (no[g] + 1) / 2;
+        km += double(no[g]) * (no[g] - 1) / 2;
+        cp += double(nv[g]) * (nv[g] + 1) / 2;
+        cm += double(nv[g]) * (nv[g] - 1) / 2;
+      }
+    }
+    fs += 2.0 * nvo * kp * cp;
+    fa += 2.0 * nvo * km * cm;
+  }
+  flops[0] = fs;
+  flops[1] = fa;
+  return CDCC_OK;
+}
+
 extern "C" const char *cdcc_status_string(int status) {
   switch (status) {
     case CDCC_OK: return "ok";

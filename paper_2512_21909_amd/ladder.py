@@ -122,6 +122,28 @@ def vvvv_density(problems, stream=None, batch_bytes=0) -> None:
     _lib.check(st, "cdcc_vvvv_density")
 
 
+def partial_contract(problems, stream=None) -> None:
+    """M_bi^dc = sum_mn lambda_bi^mn tau_mn^dc (FP64, partial
+    symmetric-antisymmetric algorithm) for one problem dict or a list.  Keys:
+    layout (Layout), lam (vo layout), tau (amplitude layout, pair symmetric),
+    M (out, vo layout).  Asynchronous on ``stream``."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr = (_lib.PartialProblem * len(problems))()
+    keep = []
+    for k, p in enumerate(problems):
+        lay: Layout = p["layout"]
+        keep.append(lay)
+        q = arr[k]
+        q.lay = ctypes.pointer(lay.c)
+        q.lam = _ptr(p["lam"], lay.lvo_size, "lam")
+        q.tau = _ptr(p["tau"], lay.amp_size, "tau")
+        q.M = _ptr(p["M"], lay.mvo_size, "M")
+    o = _opts("fp64", 0, 0)
+    st = _lib.load().cdcc_partial_contract(len(problems), arr, ctypes.byref(o), _stream(stream))
+    _lib.check(st, "cdcc_partial_contract")
+
+
 def workspace_bytes(problems, lambda_=False, precision="fp64", tile_policy=0, batch_bytes=0) -> int:
     if isinstance(problems, dict):
         problems = [problems]
@@ -138,7 +160,7 @@ def release() -> None:
 
 
 KERNEL_CLASSES = ("dress", "pack", "assemble", "contract", "energy", "slice", "density_w", "density_g",
-                  "density_r")
+                  "density_r", "partial_pack", "partial_gemm")
 
 
 def timing_enable(on: bool = True) -> None:

@@ -34,6 +34,11 @@ class Layout:
         self.t1_off, self.occ_off, self.vir_off, self.cd_off = r8(c.t1_off), r8(c.occ_off), r8(c.vir_off), r8(c.cd_off)
         self.amp_size, self.b_size, self.bvo_size, self.t1_size = c.amp_size, c.b_size, c.bvo_size, c.t1_size
         self.nocc_tot, self.nvir_tot, self.ncd_tot = c.nocc_tot, c.nvir_tot, c.ncd_tot
+        v = self.vo = _lib.VoLayoutC()
+        _lib.check(lib.cdcc_vo_layout(ctypes.byref(self.c), ctypes.byref(v)), "cdcc_vo_layout")
+        self.n_vo, self.vo_off = r8(v.n_vo), r88(v.vo_off)
+        self.lvo_off, self.mvo_off = r8(v.lam_off), r8(v.m_off)
+        self.lvo_size, self.mvo_size = int(v.lam_size), int(v.m_size)
 
     # -- marshalling of inputs --------------------------------------------------
     def pack_amp(self, blocks: dict, out: np.ndarray | None = None) -> np.ndarray:
@@ -65,6 +70,51 @@ class Layout:
                     c0, cc = self.vv_off[G][ga], nv[ga] * nv[gb]
                     out[(G, gi, ga)] = mat[r0:r0 + rr, c0:c0 + cc].reshape(no[gi], no[gj], nv[ga], nv[gb]).copy()
         return out
+
+    def _vo_geom(self, right: str):
+        no, nv = self.sym["nocc"], self.sym["nvir"]
+        if right == "oo":
+            return self.n_oo, self.oo_off, self.lvo_off, self.lvo_size, no
+        return self.n_vv, self.vv_off, self.mvo_off, self.mvo_size, nv
+
+    def pack_vo(self, blocks: dict, right: str) -> np.ndarray:
+        """lambda_bi^mn (right = "oo") or M_bi^dc (right = "vv") blocks keyed
+        (G, gb, gx) with shape (v_gb, o_gi, x_gx, x_gy) -> flat vo layout."""
+        no, nv, h = self.sym["nocc"], self.sym["nvir"], self.h
+        ncols, coff, base, size, cdim = self._vo_geom(right)
+        flat = np.zeros(size)
+        for G in range(h):
+            mat = flat[base[G]:base[G] + self.n_vo[G] * ncols[G]].reshape(self.n_vo[G], ncols[G])
+            for gb in range(h):
+                r0, rr = self.vo_off[G][gb], nv[gb] * no[gb ^ G]
+                for gx in range(h):
+                    c0, cc = coff[G][gx], cdim[gx] * cdim[gx ^ G]
+                    if rr and cc:
+                        mat[r0:r0 + rr, c0:c0 + cc] = blocks[(G, gb, gx)].reshape(rr, cc)
+        return flat
+
+    def unpack_vo(self, flat, right: str) -> dict:
+        flat = np.asarray(flat)
+        no, nv, h = self.sym["nocc"], self.sym["nvir"], self.h
+        ncols, coff, base, size, cdim = self._vo_geom(right)
+        out = {}
+        for G in range(h):
+            mat = flat[base[G]:base[G] + self.n_vo[G] * ncols[G]].reshape(self.n_vo[G], ncols[G])
+            for gb in range(h):
+                gi = gb ^ G
+                r0, rr = self.vo_off[G][gb], nv[gb] * no[gi]
+                for gx in range(h):
+                    c0, cc = coff[G][gx], cdim[gx] * cdim[gx ^ G]
+                    out[(G, gb, gx)] = mat[r0:r0 + rr, c0:c0 + cc].reshape(nv[gb], no[gi], cdim[gx],
+                                                                           cdim[gx ^ G]).copy()
+        return out
+
+    def partial_flops(self):
+        """(S, A) algorithmic flops of the partial symmetric-antisymmetric
+        contraction (cdcc_partial_flops)."""
+        out = (ctypes.c_double * 2)()
+        _lib.check(_lib.load().cdcc_partial_flops(ctypes.byref(self.c), out), "cdcc_partial_flops")
+        return float(out[0]), float(out[1])
 
     def pack_B(self, blocks: dict) -> np.ndarray:
         flat = np.zeros(self.b_size)

@@ -205,3 +205,71 @@ def test_density_error_codes_before_device_work(lib):
     arr[0].L = arr[0].X = arr[0].Y = arr[0].G = ctypes.c_void_p(0x1000)
     assert L.cdcc_vvvv_density(1, arr, ctypes.byref(o), None) == lib.EUNSUPPORTED
     assert L.cdcc_density_flops(None, None) == lib.EINVAL
+
+
+# ------------------------------------------- partial symmetric-antisymmetric
+@pytest.mark.parametrize("spec", SPECS)
+def test_vo_layout_matches_oracle_layout(spec):
+    from paper_2512_21909_amd import Layout
+    sym = S.sym_custom(*spec)
+    L, O = Layout(sym), OracleLayout(sym)
+    assert L.n_vo == O.n_vo and L.vo_off == O.vo_off
+    assert L.lvo_off == O.lvo_off and L.mvo_off == O.mvo_off
+    assert (L.lvo_size, L.mvo_size) == (O.lvo_size, O.mvo_size)
+    p = S.make_partial_problem(sym, seed=4)
+    assert np.array_equal(L.pack_vo(p["lam"], "oo"), O.pack_vo(p["lam"], "oo"))
+
+
+def _brute_partial_flops(sym):
+    h, no, nv = sym["h"], sym["nocc"], sym["nvir"]
+    io = [g for g in range(h) for _ in range(no[g])]
+    iv = [g for g in range(h) for _ in range(nv[g])]
+    fs = fa = 0
+    for G in range(h):
+        nvo = sum(1 for b in iv for i in io if b ^ i == G)
+        kp = sum(1 for m in range(len(io)) for n in range(m + 1) if io[m] ^ io[n] == G)
+        km = sum(1 for m in range(len(io)) for n in range(m) if io[m] ^ io[n] == G)
+        cp = sum(1 for d in range(len(iv)) for c in range(d + 1) if iv[d] ^ iv[c] == G)
+        cm = sum(1 for d in range(len(iv)) for c in range(d) if iv[d] ^ iv[c] == G)
+        fs += 2 * nvo * kp * cp
+        fa += 2 * nvo * km * cm
+    return fs, fa
+
+
+@pytest.mark.parametrize("spec", SPECS[:3] + SPECS[4:])
+def test_partial_flops_match_enumeration(spec):
+    from paper_2512_21909_amd import Layout
+    sym = S.sym_custom(*spec)
+    got = Layout(sym).partial_flops()
+    assert tuple(int(round(x)) for x in got) == _brute_partial_flops(sym)
+
+
+def test_partial_flops_halve_the_plain_contraction():
+    """S + A is about half of the plain 2 n_vo n_oo n_vv (exactly half up to
+    the diagonal m = n and d = c terms)."""
+    from paper_2512_21909_amd import Layout
+    sym = S.sym_d2h_medium()
+    L = Layout(sym)
+    plain = sum(2.0 * L.n_vo[G] * L.n_oo[G] * L.n_vv[G] for G in range(L.h))
+    fs, fa = L.partial_flops()
+    assert 0.45 < (fs + fa) / plain < 0.56
+
+
+def test_partial_error_codes_before_device_work(lib):
+    L = lib.load()
+    s = lib.Sym()
+    out = lib.LayoutC()
+    s.nirrep = 2
+    s.nocc[0] = s.nvir[0] = s.ncd[0] = 1
+    assert L.cdcc_irrep_layout(ctypes.byref(s), ctypes.byref(out)) == lib.OK
+    arr = (lib.PartialProblem * 1)()
+    arr[0].lay = ctypes.pointer(out)
+    assert L.cdcc_partial_contract(1, arr, None, None) == lib.EINVAL      # no pointers
+    assert L.cdcc_partial_contract(-1, None, None, None) == lib.EINVAL
+    assert L.cdcc_partial_contract(0, None, None, None) == lib.OK         # nothing to do
+    o = lib.Opts()
+    o.precision = lib.MIXED
+    arr[0].lam = arr[0].tau = arr[0].M = ctypes.c_void_p(0x1000)
+    assert L.cdcc_partial_contract(1, arr, ctypes.byref(o), None) == lib.EUNSUPPORTED
+    assert L.cdcc_partial_flops(None, None) == lib.EINVAL
+    assert L.cdcc_vo_layout(None, None) == lib.EINVAL
