@@ -287,6 +287,113 @@ def density_main(args, cdcc):
         sys.exit(1)
 
 
+PARTIAL_METRIC = ("O(O^3 V^3) contraction M_bi^dc = sum_mn lambda_bi^mn tau_mn^dc, partial "
+                  "symmetric-antisymmetric algorithm, TFLOP/s (FP64)")
+
+
+def partial_workload(name):
+    import synth as S
+    syms = {"pm_d2h_medium": ("M_bi^dc contraction: 8 irreps, o=20, v=200", S.sym_d2h_medium("A")),
+            "pm_d2h_large": ("M_bi^dc contraction: 8 irreps, o=40, v=400", S.sym_d2h_large()),
+            "pm_c1_small": ("M_bi^dc contraction: 1 irrep, o=8, v=40", S.sym_c1_small())}
+    if name not in syms:
+        raise SystemExit(f"unknown workload {name}")
+    desc, sym = syms[name]
+    return desc, S.make_partial_problem(sym, 0)
+
+
+def partial_main(args, cdcc):
+    """One step = one M_bi^dc contraction (packing + GEMM); accuracy: every
+    element against the oracle's plain definition."""
+    import torch
+    import oracle as O
+    from oracle.layout import OracleLayout
+    from tests.gpu_support import to_dev
+    desc, prob = partial_workload(args.workload)
+    sym = prob["sym"]
+    lay = cdcc.Layout(sym)
+    d = {"layout": lay, "lam": to_dev(lay.pack_vo(prob["lam"], "oo")), "tau": to_dev(lay.pack_amp(prob["tau"])),
+         "M": torch.zeros(lay.mvo_size, dtype=torch.float64, device="cuda")}
+    fs, fa = lay.partial_flops()
+    flops = fs + fa
+    plain = sum(2.0 * lay.n_vo[G] * lay.n_oo[G] * lay.n_vv[G] for G in range(lay.h))
+    # algorithmic bytes: lambda and tau read once, M written once
+    nbytes = 8.0 * (lay.lvo_size + lay.amp_size + lay.mvo_size)
+    print(f"[bench] {desc}; F_alg {flops:.4e} (S {fs:.4e}, A {fa:.4e}; plain {plain:.4e}); "
+          f"bytes {nbytes:.4e}", file=sys.stderr, flush=True)
+    cdcc.partial_contract([d])
+    torch.cuda.synchronize()
+    acc = None
+    if not args.no_check:
+        ref = OracleLayout(sym).pack_vo(O.partial_blocks(sym, prob["lam"], prob["tau"]), "vv")
+        err = float(np.max(np.abs(d["M"].cpu().numpy() - ref)))
+        acc = {"max_rel": err / float(np.max(np.abs(ref))), "checked": "every element"}
+        del ref
+    for _ in range(args.warmup):
+        cdcc.partial_contract([d])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cdcc.partial_contract([d])
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    cdcc.timing_read()
+    cdcc.timing_enable(True)
+    for _ in range(args.steps):
+        cdcc.partial_contract([d])
+    torch.cuda.synchronize()
+    cdcc.timing_enable(False)
+    kt = cdcc.timing_read()
+    ok = acc is None or acc["max_rel"] <= 1e-12
+    print(f"[bench] partial: {sec * 1e3:.4f} ms/step, {flops / sec / 1e12:.2f} TFLOP/s, gate ok={ok}, kernels={kt}",
+          file=sys.stderr, flush=True)
+    g_ms, g_n = kt.get("partial_gemm", (0.0, 0))
+    p_ms, _ = kt.get("partial_pack", (0.0, 0))
+    g_s = g_ms * 1e-3 / max(g_n, 1)
+    # the GEMM kernel reads the packed operands and writes M; its algorithmic
+    # bytes are M written once plus lambda+/- and tau+/- read once
+    gemm_bytes = 8.0 * lay.mvo_size + 8.0 * (lay.lvo_size + lay.amp_size)
+    intensity = flops / gemm_bytes
+    if intensity >= PEAK["fp64"] / (HBM_PEAK / 1e3):
+        roof = {"bound": "mfma", "achieved": round(flops / g_s / 1e12, 3) if g_ms else 0.0, "peak": PEAK["fp64"],
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gemm_bytes / g_s / 1e9, 1) if g_ms else 0.0, "peak": HBM_PEAK,
+                "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof.update({"traffic": TRAFFIC.get((args.workload, "fp64")), "kernel": "pm_gemm (S and A, both orders of M)",
+                 "launches": g_n, "avg_launch_ms": g_ms / max(g_n, 1), "flops_per_launch": flops,
+                 "algorithmic_bytes_per_launch": gemm_bytes, "intensity_flop_per_byte": round(intensity, 2)})
+    line = {
+        "metric": PARTIAL_METRIC, "value": round(flops / sec / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "flops_per_step": flops, "plain_flops": plain, "path": "fp64"},
+        "roofline": roof, "pack_ms_per_step": p_ms / args.steps,
+        "accuracy": acc, "passes_gate": ok, "kernels_ms": kt,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max((x.get("num_threads", 1) for x in threadpool_info()), default=os.cpu_count())
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count()
+        reps = 0
+        t0 = time.perf_counter()
+        while reps < 20 and (reps == 0 or time.perf_counter() - t0 < 10.0):
+            O.partial_blocks(sym, prob["lam"], prob["tau"])
+            reps += 1
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": flops * reps / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores),
+                                "kind": "oracle",
+                                "sample": f"the whole workload, {reps} oracle runs (plain definition, "
+                                          f"{plain:.3e} flops each) in {dt:.1f} s; rate in the partial "
+                                          f"algorithm's flops"}
+    print(json.dumps(line), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +428,9 @@ def main():
         del src, dst
     if args.workload.startswith("vvvv_"):
         density_main(args, cdcc)
+        return
+    if args.workload.startswith("pm_"):
+        partial_main(args, cdcc)
         return
     wdesc, entries = workload(args.workload)
     dev = build_inputs(cdcc, entries)

@@ -17,7 +17,7 @@
 //   pack_lam  lam+/- rows (b,i), K = the m >= n pairs, zero-padded to 16
 //   pack_tau  tau+/- rows m >= n, columns grouped in squares of 8 d x 8 c
 //   gemm      one 64-row x one-square tile of S and A per workgroup (MFMA
-//             f64), then both orders of M written from LDS
+//             f64), then M_bi^dc from registers and M_bi^cd through LDS
 #include <hip/hip_runtime.h>
 
 #include "kernel_common.hpp"
@@ -95,19 +95,20 @@ __global__ __launch_bounds__(256) void pm_pack_tau_kernel(const PmDesc *__restri
 
 // ---------------------------------------------------------------------------
 // gemm: one workgroup per (block, 64-row tile, square); 4 waves in 2 x 2,
-// each 32 x 32 of both S and A (MFMA f64 16x16x4); BK = 16 double-buffered
+// each 32 x 32 of both S and A (MFMA f64 16x16x4); BK = 8 double-buffered
 // LDS stages of lam+, lam- (transposed to [k][m]) and tau+, tau- ([k][n]).
 // K is zero-padded to a multiple of 16, rows past nrow read a clamped row
-// (not stored).  Epilogue: S and A through LDS, then M_bi^dc (cc fastest,
-// 64-byte runs) and, off the block diagonal, M_bi^cd (dd fastest).
+// (not stored).  Epilogue: M_bi^dc straight from the accumulators (the 16
+// lanes of a row hold two 8-wide (d, c) runs), and off the block diagonal
+// M_bi^cd through a transposing pass in LDS (dd fastest).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void pm_gemm_kernel(const PmDesc *__restrict__ descs,
+__global__ __launch_bounds__(256, 3) void pm_gemm_kernel(const PmDesc *__restrict__ descs,
                                                          const int4 *__restrict__ tiles,
                                                          const PmSquare *__restrict__ sqs,
                                                          const PmPtrs *__restrict__ pp) {
-  constexpr int BM = 64, BK = 16, LD = BM + 2, LE = 65;
+  constexpr int BM = 64, BK = 8, LD = BM + 2, LE = 65;
   __shared__ double lds[2][4][BK][LD];  // [buffer][lam+, lam-, tau+, tau-][k][m or n]
-  static_assert(sizeof(lds) >= 2 * BM * LE * sizeof(double), "epilogue reuses the staging buffer");
+  static_assert(sizeof(lds) >= BM * LE * sizeof(double), "epilogue reuses the staging buffer");
 
   const int4 tl = tiles[blockIdx.x];
   const PmDesc D = descs[tl.x];
@@ -118,8 +119,8 @@ __global__ __launch_bounds__(256, 2) void pm_gemm_kernel(const PmDesc *__restric
   const int wm = wave >> 1, wn = wave & 1;
   const int ncol = D.nsq * 64;
 
-  const int ar = tid >> 2, ak = (tid & 3) * 4;     // A staging: row, 4 k
-  const int bk = tid >> 4, bn = (tid & 15) * 4;    // B staging: k, 4 columns
+  const int ar = tid >> 2, ak = (tid & 3) * 2;     // A staging: row, 2 k
+  const int bk = tid >> 5, bn = (tid & 31) * 2;    // B staging: k, 2 columns
   const CDCC_GLOBAL double *lp =
       as_global(P.ws) + D.lp_off + int64_t(min(m0 + ar, D.nrow - 1)) * D.ldk + ak;
   const CDCC_GLOBAL double *lm = lp + int64_t(D.nrow) * D.ldk;
@@ -135,32 +136,20 @@ __global__ __launch_bounds__(256, 2) void pm_gemm_kernel(const PmDesc *__restric
       accA[i][j] = pd4{0.0, 0.0, 0.0, 0.0};
     }
 
-  pd2 ra[4], rb[4];
+  pd2 ra[2], rb[2];
   auto gload = [&](int k0) {
-    const CDCC_GLOBAL pd2 *a0 = reinterpret_cast<const CDCC_GLOBAL pd2 *>(lp + k0);
-    const CDCC_GLOBAL pd2 *a1 = reinterpret_cast<const CDCC_GLOBAL pd2 *>(lm + k0);
-    const CDCC_GLOBAL pd2 *b0 = reinterpret_cast<const CDCC_GLOBAL pd2 *>(tp + int64_t(k0) * ncol);
-    const CDCC_GLOBAL pd2 *b1 = reinterpret_cast<const CDCC_GLOBAL pd2 *>(tm + int64_t(k0) * ncol);
-    ra[0] = a0[0];
-    ra[1] = a0[1];
-    ra[2] = a1[0];
-    ra[3] = a1[1];
-    rb[0] = b0[0];
-    rb[1] = b0[1];
-    rb[2] = b1[0];
-    rb[3] = b1[1];
+    ra[0] = *reinterpret_cast<const CDCC_GLOBAL pd2 *>(lp + k0);
+    ra[1] = *reinterpret_cast<const CDCC_GLOBAL pd2 *>(lm + k0);
+    rb[0] = *reinterpret_cast<const CDCC_GLOBAL pd2 *>(tp + int64_t(k0) * ncol);
+    rb[1] = *reinterpret_cast<const CDCC_GLOBAL pd2 *>(tm + int64_t(k0) * ncol);
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      lds[buf][s][ak + 0][ar] = ra[2 * s].x;
-      lds[buf][s][ak + 1][ar] = ra[2 * s].y;
-      lds[buf][s][ak + 2][ar] = ra[2 * s + 1].x;
-      lds[buf][s][ak + 3][ar] = ra[2 * s + 1].y;
-      lds[buf][2 + s][bk][bn + 0] = rb[2 * s].x;
-      lds[buf][2 + s][bk][bn + 1] = rb[2 * s].y;
-      lds[buf][2 + s][bk][bn + 2] = rb[2 * s + 1].x;
-      lds[buf][2 + s][bk][bn + 3] = rb[2 * s + 1].y;
+      lds[buf][s][ak + 0][ar] = ra[s].x;
+      lds[buf][s][ak + 1][ar] = ra[s].y;
+      lds[buf][2 + s][bk][bn + 0] = rb[s].x;
+      lds[buf][2 + s][bk][bn + 1] = rb[s].y;
     }
   };
 
@@ -197,38 +186,39 @@ __global__ __launch_bounds__(256, 2) void pm_gemm_kernel(const PmDesc *__restric
     __syncthreads();
   }
 
-  // S and A tiles to LDS (the staging buffer is free after the last barrier)
-  double(*sS)[LE] = reinterpret_cast<double(*)[LE]>(&lds[0][0][0][0]);
-  double(*sA)[LE] = sS + BM;
+  double *__restrict__ Mb = P.M + D.m_off;
+  // M_bi^dc from the accumulators: tile column w = dd * 8 + cc
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int w = wn * 32 + j * 16 + (lane & 15);
+      const int dd = w >> 3, cc = w & 7;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
+        if (row < D.nrow && dd < Q.nd && cc < Q.nc)
+          Mb[int64_t(row) * D.n_vv + Q.base_dc + dd * Q.ld_dc + cc] = 0.5 * (accS[i][j][r] + accA[i][j][r]);
+      }
+    }
+  if (Q.diag) return;  // uniform: the square holds both orders
+  // M_bi^cd: (S - A) / 2 through LDS (the staging buffer is free after the
+  // last barrier of the K loop), then dd-fastest runs
+  double(*sD)[LE] = reinterpret_cast<double(*)[LE]>(&lds[0][0][0][0]);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int lm_ = wm * 32 + i * 16 + (lane >> 4) + 4 * r;
-        const int ln = wn * 32 + j * 16 + (lane & 15);
-        sS[lm_][ln] = accS[i][j][r];
-        sA[lm_][ln] = accA[i][j][r];
-      }
+      for (int r = 0; r < 4; ++r)
+        sD[wm * 32 + i * 16 + (lane >> 4) + 4 * r][wn * 32 + j * 16 + (lane & 15)] =
+            0.5 * (accS[i][j][r] - accA[i][j][r]);
   __syncthreads();
-
-  double *__restrict__ Mb = P.M + D.m_off;
-  for (int e = tid; e < BM * 64; e += 256) {  // (d,c): cc fastest
-    const int cc = e & 7, dd = (e >> 3) & 7, r = e >> 6;
+  for (int e = tid; e < BM * 64; e += 256) {
+    const int dd = e & 7, cc = (e >> 3) & 7, r = e >> 6;
     const int row = m0 + r;
     if (row >= D.nrow || dd >= Q.nd || cc >= Q.nc) continue;
-    const int w = dd * 8 + cc;
-    Mb[int64_t(row) * D.n_vv + Q.base_dc + dd * Q.ld_dc + cc] = 0.5 * (sS[r][w] + sA[r][w]);
-  }
-  if (!Q.diag) {
-    for (int e = tid; e < BM * 64; e += 256) {  // (c,d): dd fastest
-      const int dd = e & 7, cc = (e >> 3) & 7, r = e >> 6;
-      const int row = m0 + r;
-      if (row >= D.nrow || dd >= Q.nd || cc >= Q.nc) continue;
-      const int w = dd * 8 + cc;
-      Mb[int64_t(row) * D.n_vv + Q.base_cd + cc * Q.ld_cd + dd] = 0.5 * (sS[r][w] - sA[r][w]);
-    }
+    Mb[int64_t(row) * D.n_vv + Q.base_cd + cc * Q.ld_cd + dd] = sD[r][dd * 8 + cc];
   }
 }
 
