@@ -33,9 +33,11 @@ HBM_PEAK = 8000.0  # GB/s
 # rocprofv3 FETCH_SIZE + WRITE_SIZE per dispatch (scaled x2.0 and x1.0 by a
 # plain 256 MiB device copy), averaged over the T2 and Lambda launches of a
 # step; per (workload, path), for the kernels as committed (profiles/).  The
-# vvvv density entry is the density GEMM's launch, counted the same way.
+# vvvv density and partial-contraction entries are the launch of their GEMM
+# kernel, counted the same way.
 TRAFFIC = {("d2h_medium", "mixed"): 2.8905e9, ("d2h_medium", "fp64"): 1.6339e9,
-           ("vvvv_d2h_medium", "fp64"): 3.800e9}
+           ("vvvv_d2h_medium", "fp64"): 3.800e9,
+           ("pm_d2h_medium", "fp64"): 0.277e9, ("pm_d2h_large", "fp64"): 7.494e9}
 
 
 def workload(name):
