@@ -31,6 +31,14 @@ vector list, symmetrised ``(G + G^T)/sqrt(2)`` off the diagonal;
 transpose so that ``t2_ij^ab = t2_ji^ba``; ``t1 ~ N(0, (1e-3)^2)``;
 ``tau = t2 + t1 t1``; ``lambda`` drawn like ``t2``; ``Bvo`` like ``B``;
 ``lam_vo ~ N(0, (1e-3)^2)`` (no permutational symmetry).
+
+Synthetic "two-electron integral" matrices for the Cholesky decomposition
+(``make_cd_matrices``): per irrep g a dense symmetric positive semidefinite
+``V = W Z S S Z^T W`` over n_g basis-function pairs, ``Z ~ N(0,1)``
+(n_g x n_g), ``S = diag(exp(-k / kappa))`` (an exponentially decaying
+spectrum, as for Coulomb integrals) and ``W = diag(exp(-u_r))``,
+``u_r ~ U[0, 9]`` (pair magnitudes spanning several orders, as Schwarz
+bounds do).
 Every block draws from ``numpy.random.default_rng([seed, tensor_id, ...])`` so
 the values do not depend on generation order.
 """
@@ -45,7 +53,7 @@ __all__ = [
     "sym_d2h_large", "sym_serving_large", "sym_custom", "dirichlet_sym",
     "batch_syms", "make_eps", "make_B", "make_Bvo", "make_t1", "make_t2",
     "make_tau", "make_lambda", "make_problem", "make_density_problem", "make_lam_vo",
-    "make_partial_problem", "irrep_pairs",
+    "make_partial_problem", "make_cd_matrices", "irrep_pairs",
     "serving_stream", "TENSOR_IDS",
 ]
 
@@ -54,7 +62,7 @@ SPLIT_D2H = (Fraction(20, 100), Fraction(11, 100), Fraction(15, 100), Fraction(1
              Fraction(16, 100), Fraction(9, 100), Fraction(11, 100), Fraction(8, 100))
 
 TENSOR_IDS = {"eps_occ": 1, "eps_vir": 2, "B": 3, "Bvo": 4, "t1": 5, "t2": 6,
-              "lam": 7, "Bsym": 8, "lam_vo": 9}
+              "lam": 7, "Bsym": 8, "lam_vo": 9, "cd": 10}
 
 
 def largest_remainder_split(total: int, weights) -> list[int]:
@@ -306,6 +314,20 @@ def make_partial_problem(sym: dict, seed: int = 0) -> dict:
     t1 = make_t1(sym, seed)
     return {"sym": sym, "kind": "partial", "lam": make_lam_vo(sym, seed),
             "tau": make_tau(sym, make_t2(sym, seed, eps), t1)}
+
+
+def make_cd_matrices(npairs, seed: int = 0, kappa: float = 60.0) -> list:
+    """Dense symmetric PSD matrices, one per irrep (see the module docstring)."""
+    out = []
+    for g, n in enumerate(npairs):
+        rng = np.random.default_rng([seed, TENSOR_IDS["cd"], g])
+        z = rng.standard_normal((n, n))
+        w = np.exp(-rng.uniform(0.0, 9.0, n))
+        s_ = np.exp(-np.arange(n) / kappa)
+        gm = (w[:, None] * z) * s_[None, :]
+        v = gm @ gm.T
+        out.append(0.5 * (v + v.T))
+    return out
 
 
 def serving_stream(n_requests: int, rate_hz: float, seed: int = 5, p_large: float = 0.1):
