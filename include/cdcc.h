@@ -252,6 +252,58 @@ int cdcc_partial_contract(int32_t nsys, const cdcc_partial_problem_t *probs,
 int cdcc_partial_flops(const cdcc_layout_t *lay, double flops[2]);
 
 /*
+ * Symmetry-adapted two-step Cholesky decomposition (paper: section
+ * "Symmetry-adapted two-step CD algorithm", Algorithm 1, and the equation
+ * L^P_rs = sum_R K^-1_PR (R|rs) of the CD/DF section) of a symmetric
+ * positive semidefinite integral matrix given per irrep: V[g] is the dense
+ * row-major n[g] x n[g] block of the basis-function pairs of irrep g (device,
+ * read only; pairs of different irreps do not couple).
+ */
+typedef struct {
+  int32_t nirrep;                  /* 1, 2, 4 or 8                              */
+  int32_t pad0;
+  int64_t n[CDCC_MAX_IRREP];       /* pairs per irrep                           */
+  const double *V[CDCC_MAX_IRREP]; /* device, n[g] * n[g], or NULL if n[g] = 0  */
+} cdcc_cd_matrix_t;
+
+typedef struct {
+  double tau;    /* decomposition threshold (> 0): every residual diagonal ends below it */
+  double sigma;  /* span factor (0 < sigma <= 1), the paper uses 1e-2                   */
+  int32_t qmax;  /* qualified pairs per macro iteration (1 .. 2048), the paper uses 1000 */
+  int32_t pad0;
+} cdcc_cd_params_t;
+
+/*
+ * First step: the Cholesky basis.  Pairs with Diag >= tau form P; each macro
+ * iteration qualifies the (at most qmax) largest diagonals of P that are
+ * >= sigma * D_max, forms their residual columns, and decomposes them in
+ * micro iterations (pivot = the largest qualified diagonal) while that
+ * diagonal is >= max(tau, sigma * D_max); pairs whose diagonal falls below
+ * tau leave P.  On return piv[g][0 .. npiv[g]) holds the pivots of irrep g
+ * (pair indices, in the order chosen); piv[g] is a host array of capacity
+ * n[g].  Synchronous: waits for `stream`.  Device workspace is allocated and
+ * freed inside the call.  CDCC_EINVAL for a bad argument (NULL pointer,
+ * negative n, tau <= 0, sigma outside (0, 1], qmax outside 1 .. 2048),
+ * CDCC_EUNSUPPORTED for an irrep count other than 1, 2, 4, 8.
+ */
+int cdcc_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *params,
+                  int64_t *const piv[CDCC_MAX_IRREP], int64_t npiv[CDCC_MAX_IRREP],
+                  void *stream);
+
+/*
+ * Second step: for each irrep, K = the lower Cholesky factor of the metric
+ * V[g][piv][piv] and the vectors L^P_r = (K^-1 V[g][piv][:])_Pr, written to
+ * L[g] (device, row-major n[g] x npiv[g]: element [r][P], vector index
+ * fastest).  piv as returned by cdcc_cd_basis (host arrays).  Asynchronous on
+ * `stream` except for the final check of the factorisation, which waits.
+ * CDCC_EINVAL for a bad argument, a pivot out of range, or a metric that is
+ * not numerically positive definite.
+ */
+int cdcc_cd_vectors(const cdcc_cd_matrix_t *mat, const int64_t *const piv[CDCC_MAX_IRREP],
+                    const int64_t npiv[CDCC_MAX_IRREP], double *const L[CDCC_MAX_IRREP],
+                    void *stream);
+
+/*
  * Algorithmic flop count of one evaluation (host only): flops[0] = (ac|bd)
  * assembly, flops[1] = contraction, flops[2] = T1 dressing (Lambda with t1).
  * kind: 0 = T2, 1 = Lambda, 2 = Lambda with dressing.  Counts the stored
@@ -274,12 +326,13 @@ int cdcc_workspace_bytes(int32_t nsys, const cdcc_problem_t *probs,
  * 3 = contraction + unpack, 4 = pair energies, 5 = operand slicing (mixed),
  * 6 = vvvv density (ab|cd) batch, 7 = vvvv density contraction with L,
  * 8 = vvvv density split-K reduction, 9 = partial contraction +/- packing,
- * 10 = partial contraction GEMM.
+ * 10 = partial contraction GEMM, 11 = Cholesky basis (first step), 12 =
+ * Cholesky vectors (second step).
  * cdcc_timing_read waits for the recorded events, returns the summed elapsed
  * milliseconds and launch counts per class (arrays of CDCC_TIMING_CLASSES)
  * and clears the record.
  */
-#define CDCC_TIMING_CLASSES 11
+#define CDCC_TIMING_CLASSES 13
 int cdcc_timing_enable(int32_t on);
 int cdcc_timing_read(double ms[CDCC_TIMING_CLASSES], int64_t launches[CDCC_TIMING_CLASSES]);
 

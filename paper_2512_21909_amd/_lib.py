@@ -62,6 +62,14 @@ class PartialProblem(ctypes.Structure):
     ]
 
 
+class CdMatrix(ctypes.Structure):
+    _fields_ = [("nirrep", _i32), ("pad0", _i32), ("n", _L8), ("V", ctypes.c_void_p * MAX_IRREP)]
+
+
+class CdParams(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("sigma", ctypes.c_double), ("qmax", _i32), ("pad0", _i32)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("precision", _i32), ("tile_policy", _i32), ("batch_bytes", _i64)]
 
@@ -69,7 +77,7 @@ class Opts(ctypes.Structure):
 EXPORTS = ["cdcc_irrep_layout", "cdcc_ladder_t2", "cdcc_ladder_lambda", "cdcc_ladder_flops",
            "cdcc_workspace_bytes", "cdcc_timing_enable", "cdcc_timing_read", "cdcc_status_string",
            "cdcc_release", "cdcc_vvvv_density", "cdcc_density_flops", "cdcc_vo_layout",
-           "cdcc_partial_contract", "cdcc_partial_flops"]
+           "cdcc_partial_contract", "cdcc_partial_flops", "cdcc_cd_basis", "cdcc_cd_vectors"]
 
 _lib = None
 
@@ -110,6 +118,12 @@ def load() -> ctypes.CDLL:
     lib.cdcc_partial_contract.restype = ctypes.c_int
     lib.cdcc_partial_flops.argtypes = [ctypes.POINTER(LayoutC), ctypes.POINTER(ctypes.c_double)]
     lib.cdcc_partial_flops.restype = ctypes.c_int
+    lib.cdcc_cd_basis.argtypes = [ctypes.POINTER(CdMatrix), ctypes.POINTER(CdParams),
+                                  ctypes.POINTER(ctypes.POINTER(_i64)), ctypes.POINTER(_i64), ctypes.c_void_p]
+    lib.cdcc_cd_basis.restype = ctypes.c_int
+    lib.cdcc_cd_vectors.argtypes = [ctypes.POINTER(CdMatrix), ctypes.POINTER(ctypes.POINTER(_i64)),
+                                    ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]
+    lib.cdcc_cd_vectors.restype = ctypes.c_int
     lib.cdcc_release.argtypes = []
     lib.cdcc_release.restype = ctypes.c_int
     _lib = lib

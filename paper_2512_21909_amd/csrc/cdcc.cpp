@@ -22,6 +22,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/cdcc.h"
@@ -62,6 +63,18 @@ hipError_t launch_pm_pack(const PmDesc *descs, const PmChunk *lch, int nl, const
                           const int2 *kp, const PmSquare *sqs, const PmPtrs *pp, hipStream_t s);
 hipError_t launch_pm_gemm(const PmDesc *descs, const int4 *tiles, int ntiles, const PmSquare *sqs,
                           const PmPtrs *pp, hipStream_t s);
+// two-step Cholesky decomposition (kernels_cd.hip)
+hipError_t launch_cd_diag(const double *V, int64_t n, double *D, hipStream_t s);
+hipError_t launch_cd_gather_cols(const double *V, int64_t n, const int32_t *qrows, int nq, double *M, int ldm,
+                                 hipStream_t s);
+hipError_t launch_cd_micro(const CdQ *q, int nq, const CdPtrs &P, int64_t nmax, CdState *st, int steps,
+                           hipStream_t s);
+hipError_t launch_cd_gemm_nt(const CdGemm &G, hipStream_t s);
+hipError_t launch_cd_gather_metric(const double *V, int64_t n, const int32_t *piv, int np, double *K, double *Y,
+                                   hipStream_t s);
+hipError_t launch_cd_potrf_diag(double *K, int ld, int j0, int w, int *bad, hipStream_t s);
+hipError_t launch_cd_rowsolve(double *X, int64_t ldx, int64_t r0, int64_t nr, int c0, int w, const double *K,
+                              int ldk, int kb, hipStream_t s);
 int occupancy_density_gemm();
 }  // namespace cdcc
 
@@ -1566,7 +1579,328 @@ int run_partial(int32_t nsys, const cdcc_partial_problem_t *probs, const cdcc_op
   return CDCC_OK;
 }
 
+// ===========================================================================
+// Two-step Cholesky decomposition (section on the symmetry-adapted two-step
+// CD algorithm, Algorithm 1; the second-step equation of the CD/DF section).
+// The host drives the macro iterations (qualification from a copy of the
+// diagonals, pruning); the device runs the residual columns, the micro
+// iterations and the second-step factorisation and solves.
+// ===========================================================================
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(size_t bytes) {
+    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return CDCC_ENOMEM;
+    }
+    return CDCC_OK;
+  }
+};
+struct HostBuf {
+  void *p = nullptr;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  int alloc(size_t bytes) {
+    if (hipHostMalloc(&p, std::max<size_t>(bytes, 256), hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      return CDCC_ENOMEM;
+    }
+    return CDCC_OK;
+  }
+};
+
+int validate_cd_matrix(const cdcc_cd_matrix_t *m) {
+  if (!m) return CDCC_EINVAL;
+  if (!(m->nirrep == 1 || m->nirrep == 2 || m->nirrep == 4 || m->nirrep == 8))
+    return m->nirrep > 0 ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+  for (int g = 0; g < m->nirrep; ++g) {
+    if (m->n[g] < 0 || m->n[g] > (int64_t(1) << 30)) return CDCC_EINVAL;
+    if (m->n[g] > 0 && !m->V[g]) return CDCC_EINVAL;
+  }
+  return CDCC_OK;
+}
+
+constexpr int kCdChunk = 32;  // micro iterations launched between host checks
+
+int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64_t *const piv_out[CDCC_MAX_IRREP],
+                 int64_t npiv[CDCC_MAX_IRREP], hipStream_t stream) {
+  int rc = validate_cd_matrix(mat);
+  if (rc != CDCC_OK) return rc;
+  if (!prm || !npiv || !piv_out) return CDCC_EINVAL;
+  const double tau = prm->tau, sigma = prm->sigma;
+  const int qmax = prm->qmax;
+  if (!(tau > 0.0) || !(sigma > 0.0 && sigma <= 1.0) || qmax < 1 || qmax > kCdQmaxCap) return CDCC_EINVAL;
+  const int h = mat->nirrep;
+  for (int g = 0; g < h; ++g)
+    if (mat->n[g] > 0 && !piv_out[g]) return CDCC_EINVAL;
+  // device buffers: per irrep D, inP, L1 (n x n), M (n x qcap), piv; shared Q list, qrows, state
+  int64_t off[8][5], tot = 0, ntot = 0, nmax = 0;
+  CdPtrs P{};
+  for (int g = 0; g < h; ++g) {
+    const int64_t n = mat->n[g];
+    P.n[g] = n;
+    P.qcap[g] = int(std::min<int64_t>(qmax, std::max<int64_t>(n, 1)));
+    ntot += n;
+    nmax = std::max(nmax, n);
+    off[g][0] = tot;
+    tot = align_up(tot + n * 8);
+    off[g][1] = tot;
+    tot = align_up(tot + n);
+    off[g][2] = tot;
+    tot = align_up(tot + n * n * 8);
+    off[g][3] = tot;
+    tot = align_up(tot + n * P.qcap[g] * 8);
+    off[g][4] = tot;
+    tot = align_up(tot + n * 4);
+  }
+  const int64_t o_q = tot;
+  tot = align_up(tot + int64_t(qmax) * sizeof(CdQ));
+  const int64_t o_qr = tot;
+  tot = align_up(tot + int64_t(qmax) * 4);
+  const int64_t o_st = tot;
+  tot = align_up(tot + int64_t(sizeof(CdState)));
+  DevBuf dev;
+  if ((rc = dev.alloc(size_t(tot))) != CDCC_OK) return rc;
+  char *base = static_cast<char *>(dev.p);
+  for (int g = 0; g < h; ++g) {
+    P.D[g] = reinterpret_cast<double *>(base + off[g][0]);
+    P.inP[g] = reinterpret_cast<uint8_t *>(base + off[g][1]);
+    P.L1[g] = reinterpret_cast<double *>(base + off[g][2]);
+    P.M[g] = reinterpret_cast<double *>(base + off[g][3]);
+    P.piv[g] = reinterpret_cast<int32_t *>(base + off[g][4]);
+  }
+  CdQ *dq = reinterpret_cast<CdQ *>(base + o_q);
+  int32_t *dqr = reinterpret_cast<int32_t *>(base + o_qr);
+  CdState *dst = reinterpret_cast<CdState *>(base + o_st);
+  // pinned host mirrors
+  HostBuf hD, hP, hQ, hQr, hSt;
+  if ((rc = hD.alloc(size_t(ntot) * 8)) != CDCC_OK) return rc;
+  if ((rc = hP.alloc(size_t(ntot))) != CDCC_OK) return rc;
+  if ((rc = hQ.alloc(size_t(qmax) * sizeof(CdQ))) != CDCC_OK) return rc;
+  if ((rc = hQr.alloc(size_t(qmax) * 4)) != CDCC_OK) return rc;
+  if ((rc = hSt.alloc(sizeof(CdState))) != CDCC_OK) return rc;
+  double *Dh = static_cast<double *>(hD.p);
+  uint8_t *Ph = static_cast<uint8_t *>(hP.p);
+  CdQ *Qh = static_cast<CdQ *>(hQ.p);
+  int32_t *Qrh = static_cast<int32_t *>(hQr.p);
+  CdState *Sh = static_cast<CdState *>(hSt.p);
+  int64_t goff[9] = {0};
+  for (int g = 0; g < h; ++g) goff[g + 1] = goff[g] + mat->n[g];
+
+  auto pull_D = [&]() -> int {
+    for (int g = 0; g < h; ++g)
+      if (mat->n[g] > 0)
+        HIPCHK(hipMemcpyAsync(Dh + goff[g], P.D[g], size_t(mat->n[g]) * 8, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return CDCC_OK;
+  };
+  auto push_P = [&]() -> int {
+    for (int g = 0; g < h; ++g)
+      if (mat->n[g] > 0)
+        HIPCHK(hipMemcpyAsync(P.inP[g], Ph + goff[g], size_t(mat->n[g]), hipMemcpyHostToDevice, stream));
+    return CDCC_OK;
+  };
+
+  int k[8] = {0};
+  {
+    Span sp(11, ntot > 0, stream);
+    for (int g = 0; g < h; ++g) HIPCHK(launch_cd_diag(mat->V[g], mat->n[g], P.D[g], stream));
+  }
+  if ((rc = pull_D()) != CDCC_OK) return rc;
+  for (int64_t i = 0; i < ntot; ++i) Ph[i] = Dh[i] >= tau ? 1 : 0;
+  if ((rc = push_P()) != CDCC_OK) return rc;
+
+  std::vector<std::tuple<double, int, int>> cand;
+  for (;;) {
+    double dmax = -1.0;
+    bool any = false;
+    for (int g = 0; g < h; ++g)
+      for (int64_t r = 0; r < mat->n[g]; ++r)
+        if (Ph[goff[g] + r]) {
+          any = true;
+          dmax = std::max(dmax, Dh[goff[g] + r]);
+        }
+    if (!any) break;
+    // qualified list: the qmax largest diagonals of P that are >= sigma * D_max
+    cand.clear();
+    for (int g = 0; g < h; ++g)
+      for (int64_t r = 0; r < mat->n[g]; ++r)
+        if (Ph[goff[g] + r] && Dh[goff[g] + r] >= sigma * dmax) cand.emplace_back(-Dh[goff[g] + r], g, int(r));
+    std::sort(cand.begin(), cand.end());
+    const int nq = int(std::min<size_t>(cand.size(), size_t(qmax)));
+    int nqg[8] = {0}, qbeg[8] = {0};
+    for (int e = 0; e < nq; ++e) ++nqg[std::get<1>(cand[e])];
+    for (int g = 1; g < h; ++g) qbeg[g] = qbeg[g - 1] + nqg[g - 1];
+    int fill[8] = {0};
+    for (int e = 0; e < nq; ++e) {
+      const int g = std::get<1>(cand[e]), r = std::get<2>(cand[e]);
+      const int slot = fill[g]++;
+      Qh[e] = CdQ{g, r, slot, 0};
+      Qrh[qbeg[g] + slot] = r;
+    }
+    *Sh = CdState{};
+    for (int g = 0; g < h; ++g) {
+      Sh->k[g] = k[g];
+      Sh->k0[g] = k[g];
+    }
+    Sh->tau_mic = std::max(tau, sigma * dmax);
+    HIPCHK(hipMemcpyAsync(dq, Qh, size_t(nq) * sizeof(CdQ), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dqr, Qrh, size_t(nq) * 4, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dst, Sh, sizeof(CdState), hipMemcpyHostToDevice, stream));
+    {
+      Span sp(11, 1, stream);
+      for (int g = 0; g < h; ++g) {
+        if (nqg[g] == 0) continue;
+        HIPCHK(launch_cd_gather_cols(mat->V[g], mat->n[g], dqr + qbeg[g], nqg[g], P.M[g], P.qcap[g], stream));
+        if (k[g] > 0) {
+          CdGemm G{};
+          G.A = P.L1[g];
+          G.B = P.L1[g];
+          G.C = P.M[g];
+          G.brows = dqr + qbeg[g];
+          G.M = int(mat->n[g]);
+          G.N = nqg[g];
+          G.K = k[g];
+          G.lda = G.ldb = int(mat->n[g]);
+          G.ldc = P.qcap[g];
+          G.alpha = -1.0;
+          HIPCHK(launch_cd_gemm_nt(G, stream));
+        }
+      }
+      // micro iterations, in chunks; the device ends them (done flag)
+      for (int launched = 0; launched < nq;) {
+        const int c = std::min(kCdChunk, nq - launched);
+        HIPCHK(launch_cd_micro(dq, nq, P, nmax, dst, c, stream));
+        launched += c;
+        HIPCHK(hipMemcpyAsync(Sh, dst, sizeof(CdState), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (Sh->done) break;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(Sh, dst, sizeof(CdState), hipMemcpyDeviceToHost, stream));
+    if ((rc = pull_D()) != CDCC_OK) return rc;
+    for (int g = 0; g < h; ++g) k[g] = Sh->k[g];
+    if (Sh->steps == 0) return CDCC_EDEVICE;  // cannot happen: the largest qualified diagonal always pivots
+    for (int64_t i = 0; i < ntot; ++i)
+      if (Ph[i] && !(Dh[i] >= tau)) Ph[i] = 0;
+    if ((rc = push_P()) != CDCC_OK) return rc;
+  }
+  // pivots back to the caller
+  std::vector<int32_t> tmp;
+  for (int g = 0; g < h; ++g) {
+    npiv[g] = k[g];
+    if (k[g] == 0) continue;
+    tmp.resize(size_t(k[g]));
+    HIPCHK(hipMemcpyAsync(tmp.data(), P.piv[g], size_t(k[g]) * 4, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int i = 0; i < k[g]; ++i) piv_out[g][i] = tmp[size_t(i)];
+  }
+  for (int g = h; g < CDCC_MAX_IRREP; ++g) npiv[g] = 0;
+  return CDCC_OK;
+}
+
+int run_cd_vectors(const cdcc_cd_matrix_t *mat, const int64_t *const piv[CDCC_MAX_IRREP],
+                   const int64_t npiv[CDCC_MAX_IRREP], double *const L[CDCC_MAX_IRREP], hipStream_t stream) {
+  int rc = validate_cd_matrix(mat);
+  if (rc != CDCC_OK) return rc;
+  if (!piv || !npiv || !L) return CDCC_EINVAL;
+  const int h = mat->nirrep;
+  int64_t tot = 256;
+  for (int g = 0; g < h; ++g) {
+    const int64_t n = mat->n[g], np = npiv[g];
+    if (np < 0 || np > n || (np > 0 && (!piv[g] || !L[g]))) return CDCC_EINVAL;
+    for (int64_t i = 0; i < np; ++i)
+      if (piv[g][i] < 0 || piv[g][i] >= n) return CDCC_EINVAL;
+    tot += align_up(np * np * 8) + align_up(np * 4);
+  }
+  DevBuf dev;
+  if ((rc = dev.alloc(size_t(tot))) != CDCC_OK) return rc;
+  char *base = static_cast<char *>(dev.p);
+  int *bad = reinterpret_cast<int *>(base);
+  int64_t o = 256;
+  HostBuf hp;
+  int64_t maxnp = 0;
+  for (int g = 0; g < h; ++g) maxnp = std::max(maxnp, npiv[g]);
+  if ((rc = hp.alloc(size_t(std::max<int64_t>(maxnp, 1)) * 4 * h + 16)) != CDCC_OK) return rc;
+  int32_t *ph = static_cast<int32_t *>(hp.p);
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), stream));
+  {
+    Span sp(12, 1, stream);
+    for (int g = 0; g < h; ++g) {
+      const int64_t n = mat->n[g];
+      const int np = int(npiv[g]);
+      if (np == 0) continue;
+      double *K = reinterpret_cast<double *>(base + o);
+      o += align_up(int64_t(np) * np * 8);
+      int32_t *dp = reinterpret_cast<int32_t *>(base + o);
+      o += align_up(int64_t(np) * 4);
+      int32_t *hpg = ph + int64_t(g) * maxnp;
+      for (int i = 0; i < np; ++i) hpg[i] = int32_t(piv[g][i]);
+      HIPCHK(hipMemcpyAsync(dp, hpg, size_t(np) * 4, hipMemcpyHostToDevice, stream));
+      double *Y = L[g];
+      HIPCHK(launch_cd_gather_metric(mat->V[g], n, dp, np, K, Y, stream));
+      // blocked right-looking Cholesky of the metric
+      for (int j0 = 0; j0 < np; j0 += 64) {
+        const int w = std::min(64, np - j0);
+        HIPCHK(launch_cd_potrf_diag(K, np, j0, w, bad, stream));
+        if (j0 + w < np) {
+          HIPCHK(launch_cd_rowsolve(K, np, j0 + w, np - j0 - w, j0, w, K, np, j0, stream));
+          CdGemm G{};
+          G.A = K + int64_t(j0 + w) * np + j0;
+          G.B = G.A;
+          G.C = K + int64_t(j0 + w) * np + j0 + w;
+          G.M = G.N = np - j0 - w;
+          G.K = w;
+          G.lda = G.ldb = G.ldc = np;
+          G.alpha = -1.0;
+          HIPCHK(launch_cd_gemm_nt(G, stream));
+        }
+      }
+      // Y K^-T by 64-column blocks
+      for (int c0 = 0; c0 < np; c0 += 64) {
+        const int w = std::min(64, np - c0);
+        if (c0 > 0) {
+          CdGemm G{};
+          G.A = Y;
+          G.B = K + int64_t(c0) * np;
+          G.C = Y + c0;
+          G.M = int(n);
+          G.N = w;
+          G.K = c0;
+          G.lda = np;
+          G.ldb = np;
+          G.ldc = np;
+          G.alpha = -1.0;
+          HIPCHK(launch_cd_gemm_nt(G, stream));
+        }
+        HIPCHK(launch_cd_rowsolve(Y, np, 0, n, c0, w, K, np, c0, stream));
+      }
+    }
+  }
+  int hbad = 0;
+  HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return hbad ? CDCC_EINVAL : CDCC_OK;
+}
+
 }  // namespace
+
+extern "C" int cdcc_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *params,
+                             int64_t *const piv[CDCC_MAX_IRREP], int64_t npiv[CDCC_MAX_IRREP], void *stream) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  return run_cd_basis(mat, params, piv, npiv, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int cdcc_cd_vectors(const cdcc_cd_matrix_t *mat, const int64_t *const piv[CDCC_MAX_IRREP],
+                               const int64_t npiv[CDCC_MAX_IRREP], double *const L[CDCC_MAX_IRREP], void *stream) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  return run_cd_vectors(mat, piv, npiv, L, static_cast<hipStream_t>(stream));
+}
 
 extern "C" int cdcc_partial_contract(int32_t nsys, const cdcc_partial_problem_t *probs, const cdcc_opts_t *opts,
                                      void *stream) {

@@ -199,4 +199,41 @@ struct PmChunk {
   int32_t desc, chunk;
 };
 
+// Two-step Cholesky decomposition.  Qualified pairs of one macro iteration:
+// irrep, row (pair index in the irrep) and column slot in the irrep's
+// residual block.
+constexpr int kCdQmaxCap = 2048;
+struct CdQ {
+  int32_t g, r, slot, pad0;
+};
+
+// Per-irrep device buffers of the first step.
+struct CdPtrs {
+  double *D[8];          // diagonals (n)
+  uint8_t *inP[8];       // membership of P (n)
+  double *L1[8];         // vectors so far, [r][p], ld n (capacity n vectors)
+  double *M[8];          // residual columns of the qualified pairs, [r][slot], ld qcap
+  int32_t *piv[8];       // pivots in the order chosen (capacity n)
+  int64_t n[8];
+  int32_t qcap[8];
+};
+
+// Device-side state of the micro iterations.
+struct CdState {
+  int32_t k[8];          // vectors per irrep
+  int32_t k0[8];         // first vector of the current macro iteration
+  int32_t done, step_valid, steps, pad0;
+  int32_t cur_g, cur_r, cur_slot, cur_col;
+  double cur_d, tau_mic;
+};
+
+// C[m][n] += alpha sum_k A[arow(m)][k] B[brow(n)][k].
+struct CdGemm {
+  const double *A, *B;
+  double *C;
+  const int32_t *arows, *brows;  // NULL: identity
+  int32_t M, N, K, lda, ldb, ldc;
+  double alpha;
+};
+
 }  // namespace cdcc

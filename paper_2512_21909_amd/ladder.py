@@ -5,6 +5,8 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
+
 from . import _lib
 from .layout import Layout
 
@@ -144,6 +146,54 @@ def partial_contract(problems, stream=None) -> None:
     _lib.check(st, "cdcc_partial_contract")
 
 
+def _cd_matrix(V):
+    m = _lib.CdMatrix()
+    if len(V) not in (1, 2, 4, 8):
+        raise ValueError("one matrix per irrep: 1, 2, 4 or 8 of them")
+    m.nirrep = len(V)
+    for g, v in enumerate(V):
+        n = int(v.shape[0]) if v is not None else 0
+        m.n[g] = n
+        m.V[g] = _ptr(v, n * n, f"V[{g}]").value if n else None
+    return m
+
+
+def cd_basis(V, tau: float, sigma: float = 1e-2, qmax: int = 1000, stream=None):
+    """First step of the two-step Cholesky decomposition (Algorithm 1):
+    V = list of dense symmetric (n_g, n_g) float64 device tensors, one per
+    irrep.  Returns the pivots of each irrep (int64 numpy arrays, in the
+    order chosen).  Synchronous."""
+    m = _cd_matrix(V)
+    prm = _lib.CdParams()
+    prm.tau, prm.sigma, prm.qmax = float(tau), float(sigma), int(qmax)
+    bufs = [np.zeros(max(int(m.n[g]), 1), dtype=np.int64) for g in range(_lib.MAX_IRREP)]
+    ptrs = (ctypes.POINTER(_lib._i64) * _lib.MAX_IRREP)(
+        *[b.ctypes.data_as(ctypes.POINTER(_lib._i64)) for b in bufs])
+    npiv = (_lib._i64 * _lib.MAX_IRREP)()
+    st = _lib.load().cdcc_cd_basis(ctypes.byref(m), ctypes.byref(prm), ptrs, npiv, _stream(stream))
+    _lib.check(st, "cdcc_cd_basis")
+    return [bufs[g][:int(npiv[g])].copy() for g in range(len(V))]
+
+
+def cd_vectors(V, piv, L, stream=None) -> None:
+    """Second step: L[g] (device, float64, n_g x npiv_g, [r][P]) receives the
+    Cholesky vectors K^-1 V[piv, :] of irrep g.  Waits for the stream."""
+    m = _cd_matrix(V)
+    pv = [np.ascontiguousarray(np.asarray(p, dtype=np.int64)) for p in piv]
+    if len(pv) != len(V) or len(L) != len(V):
+        raise ValueError("one pivot list and one output per irrep")
+    keep = [x if x.size else np.zeros(1, dtype=np.int64) for x in pv]
+    ptrs = (ctypes.POINTER(_lib._i64) * _lib.MAX_IRREP)(
+        *[k.ctypes.data_as(ctypes.POINTER(_lib._i64)) for k in keep])
+    npiv = (_lib._i64 * _lib.MAX_IRREP)(*[int(x.size) for x in pv])
+    outs = (ctypes.c_void_p * _lib.MAX_IRREP)()
+    for g, x in enumerate(pv):
+        n = int(m.n[g])
+        outs[g] = _ptr(L[g], n * x.size, f"L[{g}]").value if x.size else None
+    st = _lib.load().cdcc_cd_vectors(ctypes.byref(m), ptrs, npiv, outs, _stream(stream))
+    _lib.check(st, "cdcc_cd_vectors")
+
+
 def workspace_bytes(problems, lambda_=False, precision="fp64", tile_policy=0, batch_bytes=0) -> int:
     if isinstance(problems, dict):
         problems = [problems]
@@ -160,7 +210,7 @@ def release() -> None:
 
 
 KERNEL_CLASSES = ("dress", "pack", "assemble", "contract", "energy", "slice", "density_w", "density_g",
-                  "density_r", "partial_pack", "partial_gemm")
+                  "density_r", "partial_pack", "partial_gemm", "cd_basis", "cd_vectors")
 
 
 def timing_enable(on: bool = True) -> None:

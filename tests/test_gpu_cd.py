@@ -1,0 +1,97 @@
+"""GPU parity of the two-step Cholesky decomposition (through the C ABI)
+against the oracle: the pivots (integers, decided in FP64 on both sides)
+bit-exact; the vectors within a tolerance derived from the conditioning of
+the metric factor; the decomposition error below tau; ragged and empty
+irreps, many macro iterations (small Q_max), Q_max = 1 (greedy), full rank,
+exact low rank, repeatability, a singular metric rejected."""
+import numpy as np
+import pytest
+
+import synth as S
+
+pytestmark = pytest.mark.gpu
+
+U = np.finfo(np.float64).eps
+
+
+def _dev(V):
+    from gpu_support import to_dev
+    return [to_dev(v) for v in V]
+
+
+def _vectors(cdcc, dV, piv):
+    import torch
+    L = [torch.full((int(v.shape[0]), len(p)), float("nan"), dtype=torch.float64, device="cuda")
+         for v, p in zip(dV, piv)]
+    cdcc.cd_vectors(dV, piv, L)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in L]
+
+
+def _check(cdcc, V, tau, sigma, qmax):
+    import oracle as O
+    dV = _dev(V)
+    piv = cdcc.cd_basis(dV, tau, sigma, qmax)
+    rpiv, _ = O.cd_basis(V, tau, sigma, qmax)
+    for g, (p, rp) in enumerate(zip(piv, rpiv)):
+        assert p.tolist() == rp.tolist(), f"irrep {g}"
+    L = _vectors(cdcc, dV, piv)
+    R = O.cd_vectors(V, rpiv)
+    for v, p, l, r in zip(V, piv, L, R):
+        assert l.shape == r.shape
+        if p.size == 0:
+            continue
+        K = np.linalg.cholesky(v[np.ix_(p, p)])
+        tol = 64 * np.linalg.cond(K) * U * max(np.abs(r).max(), 1e-300)
+        assert np.abs(l - r).max() <= tol
+        assert np.abs(v - l @ l.T).max() < tau
+    return piv
+
+
+@pytest.mark.parametrize("tau", [1e-4, 1e-7])
+@pytest.mark.parametrize("qmax", [1, 16, 1000])
+def test_ragged_irreps(gpu_lib, tau, qmax):
+    V = S.make_cd_matrices([150, 90, 0, 61], seed=1, kappa=20.0)
+    _check(gpu_lib, V, tau, 1e-2, qmax)
+
+
+def test_c1_and_eight_irreps(gpu_lib):
+    _check(gpu_lib, S.make_cd_matrices([300], seed=2, kappa=30.0), 1e-6, 1e-2, 1000)
+    _check(gpu_lib, S.make_cd_matrices([120, 80, 95, 70, 110, 60, 85, 50], seed=3, kappa=25.0), 1e-6, 1e-2, 100)
+
+
+def test_span_factor_one(gpu_lib):
+    _check(gpu_lib, S.make_cd_matrices([100, 40], seed=4, kappa=15.0), 1e-6, 1.0, 50)
+
+
+def test_full_rank_and_low_rank(gpu_lib):
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((70, 70))
+    full = a @ a.T + 70 * np.eye(70)
+    piv = _check(gpu_lib, [full], 1e-12, 1e-2, 9)
+    assert sorted(piv[0].tolist()) == list(range(70))
+    g = rng.standard_normal((90, 13))
+    piv = _check(gpu_lib, [g @ g.T], 1e-8, 1e-2, 1000)
+    assert piv[0].size == 13
+
+
+def test_repeatable(gpu_lib):
+    cdcc = gpu_lib
+    V = S.make_cd_matrices([130, 70], seed=6, kappa=20.0)
+    dV = _dev(V)
+    p1 = cdcc.cd_basis(dV, 1e-6, 1e-2, 32)
+    L1 = _vectors(cdcc, dV, p1)
+    for _ in range(2):
+        p2 = cdcc.cd_basis(dV, 1e-6, 1e-2, 32)
+        assert all(np.array_equal(a, b) for a, b in zip(p1, p2))
+        L2 = _vectors(cdcc, dV, p2)
+        assert all(np.array_equal(a, b) for a, b in zip(L1, L2))
+
+
+def test_indefinite_metric_is_rejected(gpu_lib):
+    """A metric that is not positive definite (here from an indefinite
+    matrix, whose second pivot has diagonal 1 - 4 = -3) is an error."""
+    from paper_2512_21909_amd._lib import CdccError
+    dV = _dev([np.array([[1.0, 2.0], [2.0, 1.0]])])
+    with pytest.raises(CdccError):
+        _vectors(gpu_lib, dV, [np.array([0, 1], dtype=np.int64)])

@@ -273,3 +273,33 @@ def test_partial_error_codes_before_device_work(lib):
     assert L.cdcc_partial_contract(1, arr, ctypes.byref(o), None) == lib.EUNSUPPORTED
     assert L.cdcc_partial_flops(None, None) == lib.EINVAL
     assert L.cdcc_vo_layout(None, None) == lib.EINVAL
+
+
+# ------------------------------------------------------ two-step Cholesky
+def test_cd_argument_errors_before_device_work(lib):
+    L = lib.load()
+    m = lib.CdMatrix()
+    prm = lib.CdParams()
+    prm.tau, prm.sigma, prm.qmax = 1e-6, 1e-2, 100
+    piv = (ctypes.POINTER(lib._i64) * 8)()
+    npiv = (lib._i64 * 8)()
+    assert L.cdcc_cd_basis(None, ctypes.byref(prm), piv, npiv, None) == lib.EINVAL
+    m.nirrep = 3
+    assert L.cdcc_cd_basis(ctypes.byref(m), ctypes.byref(prm), piv, npiv, None) == lib.EUNSUPPORTED
+    m.nirrep = 1
+    m.n[0] = 4
+    assert L.cdcc_cd_basis(ctypes.byref(m), ctypes.byref(prm), piv, npiv, None) == lib.EINVAL  # V NULL
+    m.V[0] = 0x1000
+    for tau, sigma, qmax in [(0.0, 1e-2, 10), (1e-6, 0.0, 10), (1e-6, 1.5, 10), (1e-6, 1e-2, 0), (1e-6, 1e-2, 4096)]:
+        prm.tau, prm.sigma, prm.qmax = tau, sigma, qmax
+        assert L.cdcc_cd_basis(ctypes.byref(m), ctypes.byref(prm), piv, npiv, None) == lib.EINVAL
+    prm.tau, prm.sigma, prm.qmax = 1e-6, 1e-2, 10
+    assert L.cdcc_cd_basis(ctypes.byref(m), ctypes.byref(prm), piv, npiv, None) == lib.EINVAL  # piv[0] NULL
+    # second step: pivot out of range, more pivots than pairs
+    p0 = (lib._i64 * 2)(0, 7)
+    pp = (ctypes.POINTER(lib._i64) * 8)(ctypes.cast(p0, ctypes.POINTER(lib._i64)))
+    npv = (lib._i64 * 8)(2)
+    outs = (ctypes.c_void_p * 8)(0x2000)
+    assert L.cdcc_cd_vectors(ctypes.byref(m), pp, npv, outs, None) == lib.EINVAL
+    npv[0] = 5
+    assert L.cdcc_cd_vectors(ctypes.byref(m), pp, npv, outs, None) == lib.EINVAL
