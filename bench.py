@@ -396,6 +396,108 @@ def partial_main(args, cdcc):
         sys.exit(1)
 
 
+CD_METRIC = ("symmetry-adapted two-step Cholesky decomposition (basis + vectors) of a synthetic PSD "
+             "integral matrix, wall time")
+
+
+def cd_workload(name):
+    import synth as S
+    cfgs = {"cd_d2h": ("two-step CD: 8 irreps x 2000 pairs, tau=1e-6, sigma=1e-2, Q_max=1000",
+                       [2000] * 8, 60.0, 1e-6),
+            "cd_c1": ("two-step CD: 1 irrep x 4000 pairs, tau=1e-6, sigma=1e-2, Q_max=1000", [4000], 120.0, 1e-6)}
+    if name not in cfgs:
+        raise SystemExit(f"unknown workload {name}")
+    desc, npairs, kappa, tau = cfgs[name]
+    return desc, S.make_cd_matrices(npairs, 0, kappa), tau
+
+
+def cd_main(args, cdcc):
+    """One step = cdcc_cd_basis + cdcc_cd_vectors on device-resident
+    matrices; the pivots must equal the oracle's and the vectors agree within
+    the conditioning-derived tolerance; decomposition error < tau."""
+    import torch
+    import oracle as O
+    from tests.gpu_support import to_dev
+    desc, V, tau = cd_workload(args.workload)
+    sigma, qmax = 1e-2, 1000
+    dV = [to_dev(v) for v in V]
+    piv = cdcc.cd_basis(dV, tau, sigma, qmax)
+    L = [torch.zeros((v.shape[0], len(p)), dtype=torch.float64, device="cuda") for v, p in zip(V, piv)]
+    cdcc.cd_vectors(dV, piv, L)
+    torch.cuda.synchronize()
+    npiv = int(sum(len(p) for p in piv))
+    print(f"[bench] {desc}; {npiv} vectors", file=sys.stderr, flush=True)
+    acc = None
+    if not args.no_check:
+        rpiv, _ = O.cd_basis(V, tau, sigma, qmax)
+        same = all(a.tolist() == b.tolist() for a, b in zip(piv, rpiv))
+        R = O.cd_vectors(V, rpiv)
+        err = rec = 0.0
+        ok_v = True
+        u = np.finfo(np.float64).eps
+        for v, p, l, r in zip(V, piv, L, R):
+            if len(p) == 0:
+                continue
+            ln = l.cpu().numpy()
+            kf = np.linalg.cholesky(v[np.ix_(p, p)])
+            tol = 64 * np.linalg.cond(kf) * u * np.abs(r).max()
+            d = float(np.abs(ln - r).max()) if same else float("inf")
+            ok_v &= d <= tol
+            err = max(err, d / np.abs(r).max())
+            rec = max(rec, float(np.abs(v - ln @ ln.T).max()))
+        acc = {"pivots_equal_oracle": same, "vectors_max_rel": err, "vectors_within_tol": bool(ok_v),
+               "max_abs_residual": rec, "tau": tau}
+    for _ in range(args.warmup):
+        p2 = cdcc.cd_basis(dV, tau, sigma, qmax)
+        cdcc.cd_vectors(dV, p2, L)
+    torch.cuda.synchronize()
+    cdcc.timing_read()
+    cdcc.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        p2 = cdcc.cd_basis(dV, tau, sigma, qmax)
+        cdcc.cd_vectors(dV, p2, L)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    cdcc.timing_enable(False)
+    kt = cdcc.timing_read()
+    ok = acc is None or (acc["pivots_equal_oracle"] and acc["vectors_within_tol"] and acc["max_abs_residual"] < tau)
+    ms = {k: v[0] / args.steps for k, v in kt.items() if k.startswith("cd_")}
+    print(f"[bench] cd: {sec * 1e3:.3f} ms/step, per class {ms}, gate ok={ok}", file=sys.stderr, flush=True)
+    # dominant phase: the micro iterations, one argmax launch and one column
+    # launch per vector (dependent, so latency-bound)
+    micro_ms = ms.get("cd_micro", 0.0)
+    line = {
+        "metric": CD_METRIC, "value": round(sec * 1e3, 4), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "vectors": npiv, "path": "fp64"},
+        "phases_ms_per_step": ms, "micro_us_per_vector": round(micro_ms * 1e3 / max(npiv, 1), 3),
+        "roofline": {"bound": "latency", "achieved": round(micro_ms * 1e3 / max(npiv, 1), 3), "peak": None,
+                     "unit": "us per vector (two dependent launches)", "frac": None, "traffic": None,
+                     "kernel": "cd_argmax + cd_column (micro iterations)"},
+        "accuracy": acc, "passes_gate": ok, "kernels_ms": kt,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max((x.get("num_threads", 1) for x in threadpool_info()), default=os.cpu_count())
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count()
+        reps = 0
+        t0 = time.perf_counter()
+        while reps < 20 and (reps == 0 or time.perf_counter() - t0 < 10.0):
+            rp, _ = O.cd_basis(V, tau, sigma, qmax)
+            O.cd_vectors(V, rp)
+            reps += 1
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": dt / reps * 1e3, "unit": "ms", "cores": int(cores), "kind": "oracle",
+                                "sample": f"the whole workload, {reps} oracle runs in {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -433,6 +535,9 @@ def main():
         return
     if args.workload.startswith("pm_"):
         partial_main(args, cdcc)
+        return
+    if args.workload.startswith("cd_"):
+        cd_main(args, cdcc)
         return
     wdesc, entries = workload(args.workload)
     dev = build_inputs(cdcc, entries)

@@ -326,13 +326,14 @@ int cdcc_workspace_bytes(int32_t nsys, const cdcc_problem_t *probs,
  * 3 = contraction + unpack, 4 = pair energies, 5 = operand slicing (mixed),
  * 6 = vvvv density (ab|cd) batch, 7 = vvvv density contraction with L,
  * 8 = vvvv density split-K reduction, 9 = partial contraction +/- packing,
- * 10 = partial contraction GEMM, 11 = Cholesky basis (first step), 12 =
- * Cholesky vectors (second step).
+ * 10 = partial contraction GEMM, 11 = Cholesky basis: diagonals and
+ * residual columns, 12 = Cholesky basis: micro iterations, 13 = Cholesky
+ * vectors (second step).
  * cdcc_timing_read waits for the recorded events, returns the summed elapsed
  * milliseconds and launch counts per class (arrays of CDCC_TIMING_CLASSES)
  * and clears the record.
  */
-#define CDCC_TIMING_CLASSES 13
+#define CDCC_TIMING_CLASSES 14
 int cdcc_timing_enable(int32_t on);
 int cdcc_timing_read(double ms[CDCC_TIMING_CLASSES], int64_t launches[CDCC_TIMING_CLASSES]);
 

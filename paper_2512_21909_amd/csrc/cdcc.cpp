@@ -1772,7 +1772,10 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
           HIPCHK(launch_cd_gemm_nt(G, stream));
         }
       }
+    }
+    {
       // micro iterations, in chunks; the device ends them (done flag)
+      Span sp(12, 1, stream);
       for (int launched = 0; launched < nq;) {
         const int c = std::min(kCdChunk, nq - launched);
         HIPCHK(launch_cd_micro(dq, nq, P, nmax, dst, c, stream));
@@ -1830,7 +1833,7 @@ int run_cd_vectors(const cdcc_cd_matrix_t *mat, const int64_t *const piv[CDCC_MA
   int32_t *ph = static_cast<int32_t *>(hp.p);
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), stream));
   {
-    Span sp(12, 1, stream);
+    Span sp(13, 1, stream);
     for (int g = 0; g < h; ++g) {
       const int64_t n = mat->n[g];
       const int np = int(npiv[g]);

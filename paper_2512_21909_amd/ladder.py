@@ -210,7 +210,7 @@ def release() -> None:
 
 
 KERNEL_CLASSES = ("dress", "pack", "assemble", "contract", "energy", "slice", "density_w", "density_g",
-                  "density_r", "partial_pack", "partial_gemm", "cd_basis", "cd_vectors")
+                  "density_r", "partial_pack", "partial_gemm", "cd_residual", "cd_micro", "cd_vectors")
 
 
 def timing_enable(on: bool = True) -> None:
