@@ -67,14 +67,13 @@ hipError_t launch_pm_gemm(const PmDesc *descs, const int4 *tiles, int ntiles, co
 hipError_t launch_cd_diag(const double *V, int64_t n, double *D, hipStream_t s);
 hipError_t launch_cd_gather_cols(const double *V, int64_t n, const int32_t *qrows, int nq, double *M, int ldm,
                                  hipStream_t s);
-hipError_t launch_cd_micro(const CdQ *q, int nq, const CdPtrs &P, int64_t nmax, CdState *st, int steps,
-                           hipStream_t s);
-hipError_t launch_cd_gemm_nt(const CdGemm &G, hipStream_t s);
+hipError_t launch_cd_micro(const CdQ *q, int nq, const CdPtrs &P, int64_t nmax, CdState *st, double *dq,
+                           int qcap, int t0, int steps, hipStream_t s);
+hipError_t launch_cd_gemm_nt(const CdGemmBatch &B, hipStream_t s);
 hipError_t launch_cd_gather_metric(const double *V, int64_t n, const int32_t *piv, int np, double *K, double *Y,
                                    hipStream_t s);
-hipError_t launch_cd_potrf_diag(double *K, int ld, int j0, int w, int *bad, hipStream_t s);
-hipError_t launch_cd_rowsolve(double *X, int64_t ldx, int64_t r0, int64_t nr, int c0, int w, const double *K,
-                              int ldk, int kb, hipStream_t s);
+hipError_t launch_cd_potrf_diag(const CdDiagBatch &D, int *bad, hipStream_t s);
+
 int occupancy_density_gemm();
 }  // namespace cdcc
 
@@ -1639,7 +1638,7 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
   for (int g = 0; g < h; ++g)
     if (mat->n[g] > 0 && !piv_out[g]) return CDCC_EINVAL;
   // device buffers: per irrep D, inP, L1 (n x n), M (n x qcap), piv; shared Q list, qrows, state
-  int64_t off[8][5], tot = 0, ntot = 0, nmax = 0;
+  int64_t off[8][6], tot = 0, ntot = 0, nmax = 0;
   CdPtrs P{};
   for (int g = 0; g < h; ++g) {
     const int64_t n = mat->n[g];
@@ -1657,13 +1656,17 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
     tot = align_up(tot + n * P.qcap[g] * 8);
     off[g][4] = tot;
     tot = align_up(tot + n * 4);
+    off[g][5] = tot;
+    tot = align_up(tot + n * 4);
   }
   const int64_t o_q = tot;
   tot = align_up(tot + int64_t(qmax) * sizeof(CdQ));
   const int64_t o_qr = tot;
   tot = align_up(tot + int64_t(qmax) * 4);
   const int64_t o_st = tot;
-  tot = align_up(tot + int64_t(sizeof(CdState)));
+  tot = align_up(tot + 2 * int64_t(sizeof(CdState)));
+  const int64_t o_dq = tot;
+  tot = align_up(tot + 2 * int64_t(qmax) * 8);
   DevBuf dev;
   if ((rc = dev.alloc(size_t(tot))) != CDCC_OK) return rc;
   char *base = static_cast<char *>(dev.p);
@@ -1673,22 +1676,29 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
     P.L1[g] = reinterpret_cast<double *>(base + off[g][2]);
     P.M[g] = reinterpret_cast<double *>(base + off[g][3]);
     P.piv[g] = reinterpret_cast<int32_t *>(base + off[g][4]);
+    P.qpos[g] = reinterpret_cast<int32_t *>(base + off[g][5]);
   }
   CdQ *dq = reinterpret_cast<CdQ *>(base + o_q);
   int32_t *dqr = reinterpret_cast<int32_t *>(base + o_qr);
-  CdState *dst = reinterpret_cast<CdState *>(base + o_st);
+  CdState *dst = reinterpret_cast<CdState *>(base + o_st);  // two states, alternating per step
+  double *ddq = reinterpret_cast<double *>(base + o_dq);     // two copies of the qualified diagonals
   // pinned host mirrors
-  HostBuf hD, hP, hQ, hQr, hSt;
+  HostBuf hD, hP, hQ, hQr, hSt, hPos, hDq;
   if ((rc = hD.alloc(size_t(ntot) * 8)) != CDCC_OK) return rc;
   if ((rc = hP.alloc(size_t(ntot))) != CDCC_OK) return rc;
   if ((rc = hQ.alloc(size_t(qmax) * sizeof(CdQ))) != CDCC_OK) return rc;
   if ((rc = hQr.alloc(size_t(qmax) * 4)) != CDCC_OK) return rc;
   if ((rc = hSt.alloc(sizeof(CdState))) != CDCC_OK) return rc;
+  if ((rc = hPos.alloc(size_t(ntot) * 4)) != CDCC_OK) return rc;
+  if ((rc = hDq.alloc(size_t(qmax) * 8)) != CDCC_OK) return rc;
   double *Dh = static_cast<double *>(hD.p);
   uint8_t *Ph = static_cast<uint8_t *>(hP.p);
   CdQ *Qh = static_cast<CdQ *>(hQ.p);
   int32_t *Qrh = static_cast<int32_t *>(hQr.p);
   CdState *Sh = static_cast<CdState *>(hSt.p);
+  int32_t *Posh = static_cast<int32_t *>(hPos.p);
+  double *Dqh = static_cast<double *>(hDq.p);
+  for (int64_t i = 0; i < ntot; ++i) Posh[i] = -1;
   int64_t goff[9] = {0};
   for (int g = 0; g < h; ++g) goff[g + 1] = goff[g] + mat->n[g];
 
@@ -1742,6 +1752,8 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
       const int slot = fill[g]++;
       Qh[e] = CdQ{g, r, slot, 0};
       Qrh[qbeg[g] + slot] = r;
+      Posh[goff[g] + r] = e;
+      Dqh[e] = Dh[goff[g] + r];
     }
     *Sh = CdState{};
     for (int g = 0; g < h; ++g) {
@@ -1752,13 +1764,18 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
     HIPCHK(hipMemcpyAsync(dq, Qh, size_t(nq) * sizeof(CdQ), hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dqr, Qrh, size_t(nq) * 4, hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(dst, Sh, sizeof(CdState), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ddq, Dqh, size_t(nq) * 8, hipMemcpyHostToDevice, stream));
+    for (int g = 0; g < h; ++g)
+      if (mat->n[g] > 0)
+        HIPCHK(hipMemcpyAsync(P.qpos[g], Posh + goff[g], size_t(mat->n[g]) * 4, hipMemcpyHostToDevice, stream));
     {
       Span sp(11, 1, stream);
+      CdGemmBatch GB{};
       for (int g = 0; g < h; ++g) {
         if (nqg[g] == 0) continue;
         HIPCHK(launch_cd_gather_cols(mat->V[g], mat->n[g], dqr + qbeg[g], nqg[g], P.M[g], P.qcap[g], stream));
         if (k[g] > 0) {
-          CdGemm G{};
+          CdGemm &G = GB.g[GB.n++];
           G.A = P.L1[g];
           G.B = P.L1[g];
           G.C = P.M[g];
@@ -1769,24 +1786,26 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
           G.lda = G.ldb = int(mat->n[g]);
           G.ldc = P.qcap[g];
           G.alpha = -1.0;
-          HIPCHK(launch_cd_gemm_nt(G, stream));
+          G.beta = 1.0;
         }
       }
+      HIPCHK(launch_cd_gemm_nt(GB, stream));
     }
     {
       // micro iterations, in chunks; the device ends them (done flag)
       Span sp(12, 1, stream);
-      for (int launched = 0; launched < nq;) {
-        const int c = std::min(kCdChunk, nq - launched);
-        HIPCHK(launch_cd_micro(dq, nq, P, nmax, dst, c, stream));
+      // one more step than qualified pairs: the last one marks the state done
+      for (int launched = 0; launched <= nq;) {
+        const int c = std::min(kCdChunk, nq + 1 - launched);
+        HIPCHK(launch_cd_micro(dq, nq, P, nmax, dst, ddq, qmax, launched, c, stream));
         launched += c;
-        HIPCHK(hipMemcpyAsync(Sh, dst, sizeof(CdState), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(Sh, dst + (launched & 1), sizeof(CdState), hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         if (Sh->done) break;
       }
     }
-    HIPCHK(hipMemcpyAsync(Sh, dst, sizeof(CdState), hipMemcpyDeviceToHost, stream));
     if ((rc = pull_D()) != CDCC_OK) return rc;
+    for (int e = 0; e < nq; ++e) Posh[goff[Qh[e].g] + Qh[e].r] = -1;
     for (int g = 0; g < h; ++g) k[g] = Sh->k[g];
     if (Sh->steps == 0) return CDCC_EDEVICE;  // cannot happen: the largest qualified diagonal always pivots
     for (int64_t i = 0; i < ntot; ++i)
@@ -1819,7 +1838,7 @@ int run_cd_vectors(const cdcc_cd_matrix_t *mat, const int64_t *const piv[CDCC_MA
     if (np < 0 || np > n || (np > 0 && (!piv[g] || !L[g]))) return CDCC_EINVAL;
     for (int64_t i = 0; i < np; ++i)
       if (piv[g][i] < 0 || piv[g][i] >= n) return CDCC_EINVAL;
-    tot += align_up(np * np * 8) + align_up(np * 4);
+    tot += align_up(np * np * 8) + align_up(np * 4) + align_up((np + 63) / 64 * 64 * 64 * 8);
   }
   DevBuf dev;
   if ((rc = dev.alloc(size_t(tot))) != CDCC_OK) return rc;
@@ -1834,44 +1853,87 @@ int run_cd_vectors(const cdcc_cd_matrix_t *mat, const int64_t *const piv[CDCC_MA
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), stream));
   {
     Span sp(13, 1, stream);
+    // per irrep: metric K (np x np), pivot list, inverses of the diagonal blocks
+    double *Km[8] = {nullptr}, *Kinv[8] = {nullptr};
+    int nps[8] = {0}, nbmax = 0;
     for (int g = 0; g < h; ++g) {
       const int64_t n = mat->n[g];
       const int np = int(npiv[g]);
+      nps[g] = np;
       if (np == 0) continue;
-      double *K = reinterpret_cast<double *>(base + o);
+      Km[g] = reinterpret_cast<double *>(base + o);
       o += align_up(int64_t(np) * np * 8);
       int32_t *dp = reinterpret_cast<int32_t *>(base + o);
       o += align_up(int64_t(np) * 4);
+      Kinv[g] = reinterpret_cast<double *>(base + o);
+      o += align_up(int64_t(np + 63) / 64 * 64 * 64 * 8);
       int32_t *hpg = ph + int64_t(g) * maxnp;
       for (int i = 0; i < np; ++i) hpg[i] = int32_t(piv[g][i]);
       HIPCHK(hipMemcpyAsync(dp, hpg, size_t(np) * 4, hipMemcpyHostToDevice, stream));
-      double *Y = L[g];
-      HIPCHK(launch_cd_gather_metric(mat->V[g], n, dp, np, K, Y, stream));
-      // blocked right-looking Cholesky of the metric
-      for (int j0 = 0; j0 < np; j0 += 64) {
+      HIPCHK(launch_cd_gather_metric(mat->V[g], n, dp, np, Km[g], L[g], stream));
+      nbmax = std::max(nbmax, (np + 63) / 64);
+    }
+    // X K_bb^-T in place for the w <= 64 columns at c0 of X (one tile column,
+    // so each workgroup reads its rows before it overwrites them)
+    auto block_solve = [](CdGemm &G, double *X, int64_t ldx, int64_t rows, int c0, int w, const double *kinv) {
+      G = CdGemm{};
+      G.A = X + c0;
+      G.B = kinv;
+      G.C = X + c0;
+      G.M = int(rows);
+      G.N = w;
+      G.K = w;
+      G.lda = int(ldx);
+      G.ldb = 64;
+      G.ldc = int(ldx);
+      G.alpha = 1.0;
+      G.beta = 0.0;
+    };
+    // blocked right-looking Cholesky of every metric, the irreps side by side
+    for (int jb = 0; jb < nbmax; ++jb) {
+      CdDiagBatch DB{};
+      CdGemmBatch PB{}, TB{};
+      for (int g = 0; g < h; ++g) {
+        const int np = nps[g], j0 = jb * 64;
+        if (j0 >= np) continue;
         const int w = std::min(64, np - j0);
-        HIPCHK(launch_cd_potrf_diag(K, np, j0, w, bad, stream));
+        double *kinv = Kinv[g] + int64_t(jb) * 64 * 64;
+        DB.K[DB.n] = Km[g];
+        DB.Kinv[DB.n] = kinv;
+        DB.ld[DB.n] = np;
+        DB.j0[DB.n] = j0;
+        DB.w[DB.n] = w;
+        ++DB.n;
         if (j0 + w < np) {
-          HIPCHK(launch_cd_rowsolve(K, np, j0 + w, np - j0 - w, j0, w, K, np, j0, stream));
-          CdGemm G{};
-          G.A = K + int64_t(j0 + w) * np + j0;
+          block_solve(PB.g[PB.n++], Km[g] + int64_t(j0 + w) * np, np, np - j0 - w, j0, w, kinv);
+          CdGemm &G = TB.g[TB.n++];
+          G.A = Km[g] + int64_t(j0 + w) * np + j0;
           G.B = G.A;
-          G.C = K + int64_t(j0 + w) * np + j0 + w;
+          G.C = Km[g] + int64_t(j0 + w) * np + j0 + w;
           G.M = G.N = np - j0 - w;
           G.K = w;
           G.lda = G.ldb = G.ldc = np;
           G.alpha = -1.0;
-          HIPCHK(launch_cd_gemm_nt(G, stream));
+          G.beta = 1.0;
         }
       }
-      // Y K^-T by 64-column blocks
-      for (int c0 = 0; c0 < np; c0 += 64) {
+      HIPCHK(launch_cd_potrf_diag(DB, bad, stream));
+      HIPCHK(launch_cd_gemm_nt(PB, stream));
+      HIPCHK(launch_cd_gemm_nt(TB, stream));
+    }
+    // Y K^-T by 64-column blocks (Y = V[:, piv] already in L), irreps side by side
+    for (int cb = 0; cb < nbmax; ++cb) {
+      CdGemmBatch UB{}, SB{};
+      for (int g = 0; g < h; ++g) {
+        const int np = nps[g], c0 = cb * 64;
+        if (c0 >= np) continue;
         const int w = std::min(64, np - c0);
+        const int64_t n = mat->n[g];
         if (c0 > 0) {
-          CdGemm G{};
-          G.A = Y;
-          G.B = K + int64_t(c0) * np;
-          G.C = Y + c0;
+          CdGemm &G = UB.g[UB.n++];
+          G.A = L[g];
+          G.B = Km[g] + int64_t(c0) * np;
+          G.C = L[g] + c0;
           G.M = int(n);
           G.N = w;
           G.K = c0;
@@ -1879,10 +1941,12 @@ int run_cd_vectors(const cdcc_cd_matrix_t *mat, const int64_t *const piv[CDCC_MA
           G.ldb = np;
           G.ldc = np;
           G.alpha = -1.0;
-          HIPCHK(launch_cd_gemm_nt(G, stream));
+          G.beta = 1.0;
         }
-        HIPCHK(launch_cd_rowsolve(Y, np, 0, n, c0, w, K, np, c0, stream));
+        block_solve(SB.g[SB.n++], L[g], np, n, c0, w, Kinv[g] + int64_t(cb) * 64 * 64);
       }
+      HIPCHK(launch_cd_gemm_nt(UB, stream));
+      HIPCHK(launch_cd_gemm_nt(SB, stream));
     }
   }
   int hbad = 0;

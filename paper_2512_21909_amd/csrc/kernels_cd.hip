@@ -11,15 +11,18 @@
 // First step, per macro iteration (host loop in cd.cpp):
 //   gather     M[r][slot] = V[r][q_slot] for the qualified pairs q of an irrep
 //   gemm_nt    M -= L1 L1[Q]^T (the vectors of earlier macro iterations)
-//   argmax     pivot = the first largest Diag over Q (one workgroup)
-//   column     the new vector over P: (M[r][q] - sum_mic L1[r] L1[q]) / sqrt(d)
-//              and Diag(r) -= L^2; argmax and column alternate, launched in
-//              chunks without host synchronisation (a device flag ends them)
+//   micro      one launch per micro iteration: pivot = the first largest
+//              Diag over Q, then the new vector over P, (M[r][q] - sum_mic
+//              L1[r] L1[q]) / sqrt(d), and Diag(r) -= L^2; launched in chunks
+//              without host synchronisation (a device flag ends them)
 // Second step, per irrep: gather the metric V[piv][piv] and Y = V[:, piv];
-// blocked right-looking Cholesky of the metric (diagonal block in LDS, row
-// solves of the panel, gemm_nt trailing update); then Y K^-T by 64-column
-// blocks (gemm_nt update with the solved columns, row solves): L[r][P].
+// blocked right-looking Cholesky of the metric (64 x 64 diagonal block and its
+// inverse in one wave; panel = panel Kinv^T and the trailing update as
+// gemm_nt); then Y K^-T by 64-column blocks (gemm_nt update with the solved
+// columns, then the block times Kinv^T): L[r][P].
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "kernel_common.hpp"
 
@@ -47,103 +50,146 @@ __global__ __launch_bounds__(256) void cd_gather_cols_kernel(const double *__res
   M[r * ldm + s] = V[r * n + qrows[s]];
 }
 
-// One micro-iteration pivot choice over the qualified list (all irreps):
-// the first maximum of Diag in Q order; below tau_mic (or Q used up) ends the
-// macro iteration.
-__global__ __launch_bounds__(1024) void cd_argmax_kernel(const CdQ *__restrict__ q, int nq, CdPtrs P,
-                                                         CdState *__restrict__ st) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  const int tid = threadIdx.x;
-  if (st->done) {
-    if (tid == 0) st->step_valid = 0;
-    return;
-  }
-  double best = -1.0 / 0.0;
+// One micro iteration, fused: every workgroup finds the pivot (the first
+// largest diagonal over the qualified list, from this step's copy dq_in of
+// the qualified diagonals, which no workgroup writes during the step), and
+// the workgroups together compute the new vector over the rows of the
+// pivot's irrep, 32 lanes per row (partial dot products over the vectors of
+// this macro iteration, combined by shuffles): L_r = (M[r][slot] -
+// sum_mic L1[r] L1[q]) / sqrt(d), Diag(r) -= L_r^2 (the pivot's own diagonal
+// set to 0).  The next step's qualified diagonals go to dq_out and the next
+// state to st[par ^ 1]; workgroup 0 writes the state and the pivot.  A value
+// below tau_mic (or Q used up) marks the state done; later steps then only
+// carry the state forward.  The loads of a step form two dependent rounds:
+// state, diagonals and the qualified list; then the rows.
+__global__ __launch_bounds__(256) void cd_micro_kernel(const CdQ *__restrict__ q, int nq, CdPtrs P,
+                                                       CdState *__restrict__ st, int par,
+                                                       const double *__restrict__ dq_in,
+                                                       double *__restrict__ dq_out) {
+  __shared__ double wv[4];
+  __shared__ int wi[4];
+  __shared__ CdQ wq[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const CdState S = st[par];
+  CdState *__restrict__ nx = st + (par ^ 1);
+  // pivot: first maximum in Q order (the entry travels with its value)
+  double best = -__builtin_huge_val();
   int bi = nq;
-  for (int e = tid; e < nq; e += 1024) {
+  CdQ bx{0, 0, 0, 0};
+  for (int e = tid; e < nq; e += 256) {
+    const double v = dq_in[e];
     const CdQ x = q[e];
-    const double v = P.D[x.g][x.r];
-    if (v > best) {  // e increases within a thread: the first maximum is kept
+    if (v > best) {
       best = v;
       bi = e;
+      bx = x;
     }
   }
-  sv[tid] = best;
-  si[tid] = bi;
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v2 = __shfl_xor(best, o);
+    const int i2 = __shfl_xor(bi, o);
+    const int g2 = __shfl_xor(bx.g, o), r2 = __shfl_xor(bx.r, o), s2 = __shfl_xor(bx.slot, o);
+    if (v2 > best || (v2 == best && i2 < bi)) {
+      best = v2;
+      bi = i2;
+      bx = CdQ{g2, r2, s2, 0};
+    }
+  }
+  if (lane == 0) {
+    wv[wave] = best;
+    wi[wave] = bi;
+    wq[wave] = bx;
+  }
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (tid < w) {
-      const double v2 = sv[tid + w];
-      const int i2 = si[tid + w];
-      if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) {
-        sv[tid] = v2;
-        si[tid] = i2;
-      }
+  best = wv[0];
+  bi = wi[0];
+  bx = wq[0];
+  for (int w = 1; w < 4; ++w)
+    if (wv[w] > best || (wv[w] == best && wi[w] < bi)) {
+      best = wv[w];
+      bi = wi[w];
+      bx = wq[w];
     }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double v = sv[0];
-    const int e = si[0];
-    if (e >= nq || !(v >= st->tau_mic) || st->steps >= nq) {
-      st->done = 1;
-      st->step_valid = 0;
-    } else {
-      const CdQ x = q[e];
-      const int col = st->k[x.g];
-      st->k[x.g] = col + 1;
-      P.piv[x.g][col] = x.r;
-      st->cur_g = x.g;
-      st->cur_r = x.r;
-      st->cur_slot = x.slot;
-      st->cur_col = col;
-      st->cur_d = v;
-      st->steps += 1;
-      st->step_valid = 1;
+  if (S.done || bi >= nq || !(best >= S.tau_mic) || S.steps >= nq) {
+    if (blockIdx.x == 0 && tid == 0) {
+      CdState T = S;
+      T.done = 1;
+      T.step_valid = 0;
+      *nx = T;
     }
+    return;
   }
-}
-
-// The new vector of the chosen pivot over the rows of its irrep.
-__global__ __launch_bounds__(256) void cd_column_kernel(CdPtrs P, CdState *__restrict__ st) {
-  __shared__ double lq[kCdQmaxCap];
-  if (!st->step_valid) return;
-  const int g = st->cur_g, col = st->cur_col, q = st->cur_r, slot = st->cur_slot;
-  const int k0 = st->k0[g];
-  const double d = st->cur_d;
+  const int g = bx.g, col = S.k[g], k0 = S.k0[g];
   const int64_t n = P.n[g];
   const int nm = col - k0;
   double *__restrict__ L1 = P.L1[g];
-  for (int i = threadIdx.x; i < nm; i += 256) lq[i] = L1[int64_t(q) * n + k0 + i];
-  __syncthreads();
-  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (r >= n) return;
+  if (blockIdx.x == 0) {
+    if (tid == 0) {
+      CdState T = S;
+      T.k[g] = col + 1;
+      T.steps = S.steps + 1;
+      T.cur_g = g;
+      T.cur_r = bx.r;
+      T.cur_slot = bx.slot;
+      T.cur_col = col;
+      T.cur_d = best;
+      T.step_valid = 1;
+      *nx = T;
+      P.piv[g][col] = bx.r;
+    }
+    for (int e = tid; e < nq; e += 256)  // entries of the other irreps carry over
+      if (q[e].g != g) dq_out[e] = dq_in[e];
+  }
+  const int64_t r = (int64_t(blockIdx.x) * 256 + tid) >> 5;
+  const int sub = tid & 31;
+  if (r >= n) return;  // whole 32-lane groups leave together
   if (!P.inP[g][r]) {
-    L1[r * n + col] = 0.0;
+    if (sub == 0) L1[r * n + col] = 0.0;
     return;
   }
-  double s = P.M[g][r * P.qcap[g] + slot];
-  const double *__restrict__ lr = L1 + r * n + k0;
-  for (int i = 0; i < nm; ++i) s -= lr[i] * lq[i];
-  const double x = s / sqrt(d);
-  L1[r * n + col] = x;
-  P.D[g][r] = (r == q) ? 0.0 : P.D[g][r] - x * x;
+  const double m = P.M[g][r * P.qcap[g] + bx.slot];
+  const double dr = P.D[g][r];
+  const int e2 = P.qpos[g][r];
+  const CDCC_GLOBAL double *lr = as_global(L1) + r * n + k0;
+  const CDCC_GLOBAL double *lq = as_global(L1) + int64_t(bx.r) * n + k0;
+  double a = 0.0, b = 0.0;
+  int i = sub;
+  for (; i + 32 < nm; i += 64) {
+    a += lr[i] * lq[i];
+    b += lr[i + 32] * lq[i + 32];
+  }
+  if (i < nm) a += lr[i] * lq[i];
+  a += b;
+  a += __shfl_xor(a, 16);
+  a += __shfl_xor(a, 8);
+  a += __shfl_xor(a, 4);
+  a += __shfl_xor(a, 2);
+  a += __shfl_xor(a, 1);
+  if (sub == 0) {
+    const double v = (m - a) / sqrt(best);
+    L1[r * n + col] = v;
+    const double dn = (r == bx.r) ? 0.0 : dr - v * v;
+    P.D[g][r] = dn;
+    if (e2 >= 0) dq_out[e2] = dn;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// generic C[m][n] += alpha sum_k A[arow(m)][k] B[brow(n)][k]  (both operands
+// generic C[m][n] = beta C[m][n] + alpha sum_k A[arow(m)][k] B[brow(n)][k]
+// (C not read when beta = 0; both operands
 // K-contiguous rows; optional row-index tables), 64 x 64 tiles, 4 waves in
 // 2 x 2 of MFMA f64 16x16x4, BK = 16 double-buffered LDS ([k][m], [k][n]).
 // Rows past M / N read a clamped row and are not stored; k past K is zeroed
 // by a select.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void cd_gemm_nt_kernel(CdGemm G) {
+__global__ __launch_bounds__(256) void cd_gemm_nt_kernel(CdGemmBatch GB) {
   constexpr int BM = 64, BK = 16, LD = BM + 2;
   __shared__ double As[2][BK][LD], Bs[2][BK][LD];
+  const CdGemm &G = GB.g[blockIdx.z];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BM;
+  if (m0 >= G.M || n0 >= G.N) return;  // the grid covers the largest GEMM of the batch
   const int lr = tid >> 2, lk = (tid & 3) * 4;
   const int am = min(m0 + lr, G.M - 1), bn = min(n0 + lr, G.N - 1);
   const CDCC_GLOBAL double *arow = as_global(G.A) + int64_t(G.arows ? G.arows[am] : am) * G.lda;
@@ -209,7 +255,7 @@ __global__ __launch_bounds__(256) void cd_gemm_nt_kernel(CdGemm G) {
         const int n = n0 + wn * 32 + j * 16 + (lane & 15);
         if (m < G.M && n < G.N) {
           double *c = G.C + int64_t(m) * G.ldc + n;
-          *c = *c + G.alpha * acc[i][j][r];
+          *c = G.beta == 0.0 ? G.alpha * acc[i][j][r] : G.beta * *c + G.alpha * acc[i][j][r];
         }
       }
 }
@@ -235,71 +281,59 @@ __global__ __launch_bounds__(256) void cd_gather_metric_kernel(const double *__r
   }
 }
 
-// Lower Cholesky factor of the w x w block at (j0, j0) of K (ld), in place;
-// a non-positive pivot sets *bad.
-__global__ __launch_bounds__(256) void cd_potrf_diag_kernel(double *__restrict__ K, int ld, int j0, int w,
-                                                            int *__restrict__ bad) {
-  __shared__ double a[64][65];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < w * w; e += 256) {
-    const int i = e / w, j = e - (e / w) * w;
-    a[i][j] = K[int64_t(j0 + i) * ld + j0 + j];
-  }
-  __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    const double d = a[j][j];
-    __syncthreads();
-    if (!(d > 0.0)) {
-      if (tid == 0) *bad = 1;
-      return;  // uniform: every thread read the same d
-    }
-    const double s = sqrt(d);
-    for (int i = j + 1 + tid; i < w; i += 256) a[i][j] /= s;
-    if (tid == 0) a[j][j] = s;
-    __syncthreads();
-    for (int e = tid; e < (w - j - 1) * (w - j - 1); e += 256) {
-      const int i = j + 1 + e / (w - j - 1), k = j + 1 + e % (w - j - 1);
-      if (k <= i) a[i][k] -= a[i][j] * a[k][j];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < w * w; e += 256) {
-    const int i = e / w, j = e - (e / w) * w;
-    if (j <= i) K[int64_t(j0 + i) * ld + j0 + j] = a[i][j];
-  }
-}
-
-// Rows [r0, r0 + nr) of X, columns [c0, c0 + w): x K^T = y with K the lower
-// w x w block at (kb, kb) of Kf (ldk), solved row by row (one thread a row,
-// the block in LDS).
-__global__ __launch_bounds__(256) void cd_rowsolve_kernel(double *__restrict__ X, int64_t ldx, int64_t r0,
-                                                          int64_t nr, int c0, int w,
-                                                          const double *__restrict__ Kf, int ldk, int kb) {
-  __shared__ double kk[64][65];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < w * w; e += 256) {
-    const int i = e / w, j = e - (e / w) * w;
-    kk[i][j] = j <= i ? Kf[int64_t(kb + i) * ldk + kb + j] : 0.0;
-  }
-  __syncthreads();
-  const int64_t r = r0 + int64_t(blockIdx.x) * 256 + tid;
-  if (r >= r0 + nr) return;
-  double *__restrict__ x = X + r * ldx + c0;
-  double v[64];
+// Lower Cholesky factor of the w x w block at (j0, j0) of K (ld), in place,
+// and its inverse into Kinv (64 x 64, row-major, zero above the diagonal and
+// outside w), one workgroup per irrep of the batch; a non-positive pivot
+// sets *bad.  One wave: lane i holds row i
+// of the block in registers (factor), then column i of the inverse (forward
+// substitution against the factor, read from LDS).
+__global__ __launch_bounds__(64) void cd_potrf_diag_kernel(CdDiagBatch DB, int *__restrict__ bad) {
+  __shared__ double lf[64][65];
+  __shared__ double piv_s;
+  double *__restrict__ K = DB.K[blockIdx.x];
+  double *__restrict__ Kinv = DB.Kinv[blockIdx.x];
+  const int ld = DB.ld[blockIdx.x], j0 = DB.j0[blockIdx.x], w = DB.w[blockIdx.x];
+  const int i = threadIdx.x;
+  double a[64];
 #pragma unroll
-  for (int j = 0; j < 64; ++j) v[j] = j < w ? x[j] : 0.0;
+  for (int k = 0; k < 64; ++k) a[k] = (i < w && k <= i && k < w) ? K[int64_t(j0 + i) * ld + j0 + k] : 0.0;
+  bool ok = true;
 #pragma unroll
   for (int j = 0; j < 64; ++j) {
     if (j < w) {
-      double s = v[j];
+      if (i == j) piv_s = a[j];
+      __syncthreads();
+      const double d = piv_s;
+      ok = ok && (d > 0.0);
+      const double sd = sqrt(d > 0.0 ? d : 1.0);
+      const double lij = (i > j) ? a[j] / sd : (i == j ? sd : 0.0);
+      a[j] = lij;
+      lf[i][j] = lij;
+      __syncthreads();
+      // every lane updates its whole row: entries above its diagonal or past
+      // w collect values that are never read (lij = 0 for i < j, lf = 0
+      // past w), which keeps the loop free of lane-dependent branches
 #pragma unroll
-      for (int i = 0; i < j; ++i) s -= v[i] * kk[j][i];
-      v[j] = s / kk[j][j];
+      for (int k = j + 1; k < 64; ++k) a[k] -= lij * lf[k][j];
     }
   }
+  if (i == 0 && !ok) *bad = 1;
+  if (i < w) {
 #pragma unroll
-  for (int j = 0; j < 64; ++j)
-    if (j < w) x[j] = v[j];
+    for (int k = 0; k < 64; ++k)
+      if (k <= i && k < w) K[int64_t(j0 + i) * ld + j0 + k] = a[k];
+  }
+  // inverse: lane c solves L x = e_c (x = column c of L^-1)
+  double x[64];
+#pragma unroll
+  for (int r = 0; r < 64; ++r) {
+    double t = (r == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < r; ++k) t -= lf[r][k] * x[k];
+    x[r] = (r < w && i < w && r >= i) ? t / lf[r][r] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 64; ++r) Kinv[r * 64 + i] = x[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -318,19 +352,25 @@ hipError_t launch_cd_gather_cols(const double *V, int64_t n, const int32_t *qrow
   return hipGetLastError();
 }
 
-hipError_t launch_cd_micro(const CdQ *q, int nq, const CdPtrs &P, int64_t nmax, CdState *st, int steps,
-                           hipStream_t s) {
-  for (int t = 0; t < steps; ++t) {
-    cd_argmax_kernel<<<1, 1024, 0, s>>>(q, nq, P, st);
-    cd_column_kernel<<<int((nmax + 255) / 256), 256, 0, s>>>(P, st);
+hipError_t launch_cd_micro(const CdQ *q, int nq, const CdPtrs &P, int64_t nmax, CdState *st, double *dq,
+                           int qcap, int t0, int steps, hipStream_t s) {
+  const int grid = int((nmax * 32 + 255) / 256);
+  for (int t = t0; t < t0 + steps; ++t) {
+    const int par = t & 1;
+    cd_micro_kernel<<<std::max(grid, 1), 256, 0, s>>>(q, nq, P, st, par, dq + par * qcap, dq + (par ^ 1) * qcap);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_cd_gemm_nt(const CdGemm &G, hipStream_t s) {
-  if (G.M <= 0 || G.N <= 0) return hipSuccess;
-  dim3 grid((G.N + 63) / 64, (G.M + 63) / 64);
-  cd_gemm_nt_kernel<<<grid, 256, 0, s>>>(G);
+hipError_t launch_cd_gemm_nt(const CdGemmBatch &B, hipStream_t s) {
+  int mm = 0, nn = 0;
+  for (int k = 0; k < B.n; ++k) {
+    mm = std::max(mm, B.g[k].M);
+    nn = std::max(nn, B.g[k].N);
+  }
+  if (B.n <= 0 || mm <= 0 || nn <= 0) return hipSuccess;
+  dim3 grid((nn + 63) / 64, (mm + 63) / 64, B.n);
+  cd_gemm_nt_kernel<<<grid, 256, 0, s>>>(B);
   return hipGetLastError();
 }
 
@@ -342,15 +382,9 @@ hipError_t launch_cd_gather_metric(const double *V, int64_t n, const int32_t *pi
   return hipGetLastError();
 }
 
-hipError_t launch_cd_potrf_diag(double *K, int ld, int j0, int w, int *bad, hipStream_t s) {
-  cd_potrf_diag_kernel<<<1, 256, 0, s>>>(K, ld, j0, w, bad);
-  return hipGetLastError();
-}
-
-hipError_t launch_cd_rowsolve(double *X, int64_t ldx, int64_t r0, int64_t nr, int c0, int w, const double *K,
-                              int ldk, int kb, hipStream_t s) {
-  if (nr <= 0 || w <= 0) return hipSuccess;
-  cd_rowsolve_kernel<<<int((nr + 255) / 256), 256, 0, s>>>(X, ldx, r0, nr, c0, w, K, ldk, kb);
+hipError_t launch_cd_potrf_diag(const CdDiagBatch &D, int *bad, hipStream_t s) {
+  if (D.n <= 0) return hipSuccess;
+  cd_potrf_diag_kernel<<<D.n, 64, 0, s>>>(D, bad);
   return hipGetLastError();
 }
 

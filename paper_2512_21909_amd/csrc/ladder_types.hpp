@@ -214,6 +214,7 @@ struct CdPtrs {
   double *L1[8];         // vectors so far, [r][p], ld n (capacity n vectors)
   double *M[8];          // residual columns of the qualified pairs, [r][slot], ld qcap
   int32_t *piv[8];       // pivots in the order chosen (capacity n)
+  int32_t *qpos[8];      // row -> entry of the qualified list, or -1
   int64_t n[8];
   int32_t qcap[8];
 };
@@ -227,13 +228,27 @@ struct CdState {
   double cur_d, tau_mic;
 };
 
-// C[m][n] += alpha sum_k A[arow(m)][k] B[brow(n)][k].
+// C[m][n] = beta C[m][n] + alpha sum_k A[arow(m)][k] B[brow(n)][k].
 struct CdGemm {
   const double *A, *B;
   double *C;
   const int32_t *arows, *brows;  // NULL: identity
   int32_t M, N, K, lda, ldb, ldc;
-  double alpha;
+  double alpha, beta;            // C = beta C + alpha A B^T (C not read when beta = 0)
+};
+
+// Up to eight independent GEMMs in one launch (one per irrep).
+struct CdGemmBatch {
+  CdGemm g[8];
+  int32_t n, pad0;
+};
+
+// Diagonal-block factorisations of one launch (one per irrep).
+struct CdDiagBatch {
+  double *K[8];
+  double *Kinv[8];
+  int32_t ld[8], j0[8], w[8];
+  int32_t n, pad0;
 };
 
 }  // namespace cdcc
