@@ -89,7 +89,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--workloads", default="c1_small,d2h_medium,d2h_medium_B,serving_large,batch64")
     ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--precisions", default="fp64,mixed", help="paths to tune (the others keep their entries)")
     args = ap.parse_args()
+    precs = tuple(p for p in args.precisions.split(",") if p)
     syms, kinds = [], {}
     for w in args.workloads.split(","):
         if w == "c1_small":
@@ -109,7 +111,7 @@ def main():
     t0 = time.time()
     table = load_table(args.out)
     for sym, ks in syms:
-        table = tune([sym], kinds=ks, table=table)
+        table = tune([sym], kinds=ks, precisions=precs, table=table)
     write_table(table, args.out)
     _lib.load().cdcc_release()
     print(f"[autotune] {len(table)} entries -> {args.out} in {time.time() - t0:.1f} s")

@@ -17,6 +17,7 @@
 
 namespace cdcc {
 
+typedef double d2 __attribute__((ext_vector_type(2)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // MFMA f64 16x16x4 lane mapping (gfx950): A[i][k] in lane i + 16k,
@@ -165,27 +166,27 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
     const int m0 = tl.tm * BM, n0 = tl.tn * BN;
     const int K = D.K;
 
+    // rows past M / N read a clamped row: they only reach results that are
+    // never stored
     const CDCC_GLOBAL double *arow[RA];
     const CDCC_GLOBAL double *brow[RB];
-    double am[RA], bmk[RB];  // 1 for a real row, 0 for a padding row
 #pragma unroll
     for (int q = 0; q < RA; ++q) {
-      const int m = m0 + lr + 64 * q;
-      am[q] = m < D.M ? 1.0 : 0.0;
-      arow[q] = as_global(op) + D.aoff + int64_t(m < D.M ? m : D.M - 1) * K;
+      const int m = min(m0 + lr + 64 * q, D.M - 1);
+      arow[q] = as_global(op) + D.aoff + int64_t(m) * K + lk;
     }
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
-      const int n = n0 + lr + 64 * q;
-      bmk[q] = n < D.N ? 1.0 : 0.0;
-      const int nn = n < D.N ? n : D.N - 1;
+      const int nn = min(n0 + lr + 64 * q, D.N - 1);
       if constexpr (MODE == 1) {
-        brow[q] = as_global(op) + D.boff + int64_t(nn) * K;
+        brow[q] = as_global(op) + D.boff + int64_t(nn) * K + lk;
       } else {
         const int dd = nn / D.nb, b = nn - dd * D.nb;
-        brow[q] = as_global(op) + D.boff + (int64_t(b) * D.vd + dd) * K;
+        brow[q] = as_global(op) + D.boff + (int64_t(b) * D.vd + dd) * K + lk;
       }
     }
+    // 16-byte operand loads when every row starts on a 16-byte boundary
+    const bool vec = ((D.aoff | D.boff | int64_t(K)) & 1) == 0 && (reinterpret_cast<uintptr_t>(op) & 15) == 0;
 
     d4 acc[FM][FN];
 #pragma unroll
@@ -193,21 +194,62 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // loads are unconditional (clamped index) and masked by a multiply, so
-    // the K loop is one basic block
     double ra[RA][4], rb[RB][4];
+    // a whole K block: no k mask; the right operand is negated from kneg on
     auto gload = [&](int k0) {
+      if (vec) {
+#pragma unroll
+        for (int q = 0; q < RA; ++q) {
+          const CDCC_GLOBAL d2 *p = reinterpret_cast<const CDCC_GLOBAL d2 *>(arow[q] + k0);
+          const d2 u = p[0], v = p[1];
+          ra[q][0] = u.x;
+          ra[q][1] = u.y;
+          ra[q][2] = v.x;
+          ra[q][3] = v.y;
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          const CDCC_GLOBAL d2 *p = reinterpret_cast<const CDCC_GLOBAL d2 *>(brow[q] + k0);
+          const d2 u = p[0], v = p[1];
+          rb[q][0] = u.x;
+          rb[q][1] = u.y;
+          rb[q][2] = v.x;
+          rb[q][3] = v.y;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+#pragma unroll
+          for (int q = 0; q < RA; ++q) ra[q][e] = arow[q][k0 + e];
+#pragma unroll
+          for (int q = 0; q < RB; ++q) rb[q][e] = brow[q][k0 + e];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double sg = k0 + lk + e >= D.kneg ? -1.0 : 1.0;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) rb[q][e] *= sg;
+      }
+    };
+    // the last, partial block: k past K reads a clamped address, zeroed by a select
+    auto gload_tail = [&](int k0) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = k0 + lk + e;
         const bool kin = k < K;
-        const int kc = kin ? k : (K > 0 ? K - 1 : 0);
-        const double ka = kin ? 1.0 : 0.0;
-        const double kb = kin ? (k >= D.kneg ? -1.0 : 1.0) : 0.0;
+        const int kc = (kin ? k : K - 1) - lk;
+        const double sg = k >= D.kneg ? -1.0 : 1.0;
 #pragma unroll
-        for (int q = 0; q < RA; ++q) ra[q][e] = arow[q][kc] * (am[q] * ka);
+        for (int q = 0; q < RA; ++q) {
+          const double x = arow[q][kc];
+          ra[q][e] = kin ? x : 0.0;
+        }
 #pragma unroll
-        for (int q = 0; q < RB; ++q) rb[q][e] = brow[q][kc] * (bmk[q] * kb);
+        for (int q = 0; q < RB; ++q) {
+          const double x = brow[q][kc];
+          rb[q][e] = kin ? sg * x : 0.0;
+        }
       }
     };
     auto lstore = [&](int buf) {
@@ -221,15 +263,15 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
         for (int e = 0; e < 4; ++e) Bs[buf][lk + e][lr + 64 * q] = rb[q][e];
     };
 
-    const int nk = (K + BK - 1) / BK;
-    gload(0);
-    lstore(0);
+    const int nfull = K / BK, nk = (K + BK - 1) / BK;
+    if (nfull > 0) gload(0);
+    else if (nk > 0) gload_tail(0);
+    if (nk > 0) lstore(0);
     __syncthreads();
     for (int kb = 0; kb < nk; ++kb) {
-      const int cur = kb & 1;
-      // unconditional prefetch (clamped, zeroed past K): no branch, so the
-      // wait for these loads lands after the MFMAs below
-      gload((kb + 1) * BK);
+      const int cur = kb & 1, kn = kb + 1;
+      if (kn < nfull) gload(kn * BK);
+      else if (kn < nk) gload_tail(kn * BK);
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
@@ -244,7 +286,7 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
       }
-      lstore(cur ^ 1);
+      if (kn < nk) lstore(cur ^ 1);
       __syncthreads();
     }
 
