@@ -35,7 +35,7 @@ HBM_PEAK = 8000.0  # GB/s
 # step; per (workload, path), for the kernels as committed (profiles/).  The
 # vvvv density and partial-contraction entries are the launch of their GEMM
 # kernel, counted the same way.
-TRAFFIC = {("d2h_medium", "mixed"): 2.8905e9,
+TRAFFIC = {("d2h_medium", "mixed"): 2.7548e9, ("d2h_medium", "fp64"): 2.0648e9,
            ("vvvv_d2h_medium", "fp64"): 3.800e9,
            ("pm_d2h_medium", "fp64"): 0.277e9, ("pm_d2h_large", "fp64"): 7.494e9}
 
