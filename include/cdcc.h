@@ -122,6 +122,7 @@ typedef struct {
   int32_t tile_policy;       /* 0 = tile table, k = force assembly class k-1:   */
                              /* 1..3 (FP64), 1..4 (CDCC_MIXED)                 */
   int64_t batch_bytes;       /* cap of the (ac|bd) batch buffer, 0 = default    */
+                             /* (4 GiB, or CDCC_BATCH_MB megabytes)             */
 } cdcc_opts_t;
 
 /*
@@ -175,7 +176,7 @@ typedef struct {
 /*
  * vvvv density contraction for nsys >= 0 independent systems, FP64 MFMA,
  * asynchronous on `stream`.  The (ab|cd) intermediate exists only in bounded
- * batches (opts->batch_bytes, default 1 GiB).  opts may be NULL; precision
+ * batches (opts->batch_bytes, default 4 GiB).  opts may be NULL; precision
  * must be CDCC_FP64 (CDCC_MIXED returns CDCC_EUNSUPPORTED); tile_policy is
  * ignored.  Errors as for cdcc_ladder_t2 (CDCC_EINVAL for a NULL required
  * pointer); inputs must not overlap G.
