@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
                                                     const int2 *__restrict__ rows,
                                                     const SysPtrs *__restrict__ sp) {
   extern __shared__ double srow[];
-  __shared__ double red[256];
+  __shared__ double red[4];
   const int2 jr = rows[blockIdx.x];
   const SliceJob J = jobs[jr.x];
   const int row = jr.y;
@@ -96,13 +96,11 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
       mx = fmax(mx, fabs(u));
     }
   }
-  red[threadIdx.x] = mx;
+  // row maximum: within each wave by shuffles, then across the four waves
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  mx = red[0];
+  mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   int e = 0;
   if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)  =>  |x| < 2^e
   const double sigma = ldexp(1.0, e), inv = ldexp(1.0, -e);
