@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void cd_gather_cols_kernel(const double *__res
 // largest diagonal over the qualified list, from this step's copy dq_in of
 // the qualified diagonals, which no workgroup writes during the step), and
 // the workgroups together compute the new vector over the rows of the
-// pivot's irrep, 32 lanes per row (partial dot products over the vectors of
+// pivot's irrep, 16 lanes per row (partial dot products over the vectors of
 // this macro iteration, combined by shuffles): L_r = (M[r][slot] -
 // sum_mic L1[r] L1[q]) / sqrt(d), Diag(r) -= L_r^2 (the pivot's own diagonal
 // set to 0).  The next step's qualified diagonals go to dq_out and the next
@@ -140,9 +140,9 @@ __global__ __launch_bounds__(256) void cd_micro_kernel(const CdQ *__restrict__ q
     for (int e = tid; e < nq; e += 256)  // entries of the other irreps carry over
       if (q[e].g != g) dq_out[e] = dq_in[e];
   }
-  const int64_t r = (int64_t(blockIdx.x) * 256 + tid) >> 5;
-  const int sub = tid & 31;
-  if (r >= n) return;  // whole 32-lane groups leave together
+  const int64_t r = (int64_t(blockIdx.x) * 256 + tid) >> 4;
+  const int sub = tid & 15;
+  if (r >= n) return;  // whole 16-lane groups leave together
   if (!P.inP[g][r]) {
     if (sub == 0) L1[r * n + col] = 0.0;
     return;
@@ -154,13 +154,12 @@ __global__ __launch_bounds__(256) void cd_micro_kernel(const CdQ *__restrict__ q
   const CDCC_GLOBAL double *lq = as_global(L1) + int64_t(bx.r) * n + k0;
   double a = 0.0, b = 0.0;
   int i = sub;
-  for (; i + 32 < nm; i += 64) {
+  for (; i + 16 < nm; i += 32) {
     a += lr[i] * lq[i];
-    b += lr[i + 32] * lq[i + 32];
+    b += lr[i + 16] * lq[i + 16];
   }
   if (i < nm) a += lr[i] * lq[i];
   a += b;
-  a += __shfl_xor(a, 16);
   a += __shfl_xor(a, 8);
   a += __shfl_xor(a, 4);
   a += __shfl_xor(a, 2);
@@ -354,7 +353,7 @@ hipError_t launch_cd_gather_cols(const double *V, int64_t n, const int32_t *qrow
 
 hipError_t launch_cd_micro(const CdQ *q, int nq, const CdPtrs &P, int64_t nmax, CdState *st, double *dq,
                            int qcap, int t0, int steps, hipStream_t s) {
-  const int grid = int((nmax * 32 + 255) / 256);
+  const int grid = int((nmax * 16 + 255) / 256);
   for (int t = t0; t < t0 + steps; ++t) {
     const int par = t & 1;
     cd_micro_kernel<<<std::max(grid, 1), 256, 0, s>>>(q, nq, P, st, par, dq + par * qcap, dq + (par ^ 1) * qcap);
