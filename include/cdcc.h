@@ -51,6 +51,8 @@ extern "C" {
 
 #define CDCC_FP64  0  /* FP64 MFMA throughout                                     */
 #define CDCC_MIXED 1  /* split-BF16 MFMA, FP32 accumulation, FP64 combination     */
+#define CDCC_MIXED_I8 2  /* four signed 8-bit digits per operand element, int8  */
+                         /* MFMA with exact int32 accumulation, FP64 combination */
 
 /* Orbital and Cholesky-vector counts per irrep (entries >= nirrep ignored). */
 typedef struct {
@@ -118,9 +120,9 @@ typedef struct {
 } cdcc_problem_t;
 
 typedef struct {
-  int32_t precision;         /* CDCC_FP64 or CDCC_MIXED                         */
+  int32_t precision;         /* CDCC_FP64, CDCC_MIXED or CDCC_MIXED_I8          */
   int32_t tile_policy;       /* 0 = tile table, k = force assembly class k-1:   */
-                             /* 1..3 (FP64), 1..4 (CDCC_MIXED)                 */
+                             /* 1..3 (FP64), 1..4 (the two split precisions)   */
   int64_t batch_bytes;       /* cap of the (ac|bd) batch buffer, 0 = default    */
                              /* (4 GiB, or CDCC_BATCH_MB megabytes)             */
 } cdcc_opts_t;
@@ -177,7 +179,7 @@ typedef struct {
  * vvvv density contraction for nsys >= 0 independent systems, FP64 MFMA,
  * asynchronous on `stream`.  The (ab|cd) intermediate exists only in bounded
  * batches (opts->batch_bytes, default 4 GiB).  opts may be NULL; precision
- * must be CDCC_FP64 (CDCC_MIXED returns CDCC_EUNSUPPORTED); tile_policy is
+ * must be CDCC_FP64 (the split precisions return CDCC_EUNSUPPORTED); tile_policy is
  * ignored.  Errors as for cdcc_ladder_t2 (CDCC_EINVAL for a NULL required
  * pointer); inputs must not overlap G.
  */
@@ -236,7 +238,7 @@ typedef struct {
 /*
  * The contraction above for nsys >= 0 independent systems, FP64 MFMA,
  * asynchronous on `stream`.  opts may be NULL; precision must be CDCC_FP64
- * (CDCC_MIXED returns CDCC_EUNSUPPORTED); the other options are ignored.
+ * (the split precisions return CDCC_EUNSUPPORTED); the other options are ignored.
  * CDCC_EINVAL for nsys < 0, NULL probs with nsys > 0 or a NULL required
  * pointer; CDCC_ENOMEM, CDCC_EDEVICE as for cdcc_ladder_t2.  Inputs must not
  * overlap M.

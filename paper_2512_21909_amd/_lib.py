@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(_HERE, "libcdcc.so")
 
 MAX_IRREP = 8
 OK, EINVAL, ENOMEM, EUNSUPPORTED, EDEVICE = 0, -1, -2, -3, -4
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_I8 = 0, 1, 2
 
 _i32, _i64 = ctypes.c_int32, ctypes.c_int64
 _A8 = _i32 * MAX_IRREP

@@ -37,12 +37,12 @@ def load_table(path: str = TABLE) -> dict:
 def write_table(table: dict, path: str = TABLE) -> None:
     with open(path, "w") as f:
         f.write("# precision kind h nocc[h] nvir[h] ncd[h] -> assembly tile class "
-                "(fp64: 0=64x64 1=128x64 2=128x128; mixed: 0=64x128 1=128x64 2=128x128/8 waves 3=64x64)\n")
+                "(fp64: 0=64x64 1=128x64 2=128x128; mixed, mixed_i8: 0=64x128 1=128x64 2=128x128/8 waves 3=64x64)\n")
         for k in sorted(table):
             f.write(f"{k} {table[k]}\n")
 
 
-NCLASS = {"fp64": 3, "mixed": 4}
+NCLASS = {"fp64": 3, "mixed": 4, "mixed_i8": 4}
 
 
 def time_classes(cdcc, dev_problem: dict, kind: str, precision: str, reps: int = 3) -> list[float]:

@@ -42,12 +42,12 @@ hipError_t launch_reduce_unpack(int njobs, const P2Group *groups, const Tile *jo
                                 const double *part, const int4 *ijtab, const int4 *vvtab, hipStream_t s);
 int occupancy_f64(int which, int cls);
 hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, const int *vvfull, hipStream_t s);
-// mixed path (kernels_mixed.hip)
-hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, int stage_bytes,
-                        hipStream_t s);
-hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q,
-                                 int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
-int occupancy_mixed(int cls);
+// split paths (kernels_mixed.hip); fmt 0 = BF16 slices, 1 = 8-bit digits
+hipError_t launch_slice(int fmt, const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp,
+                        int stage_bytes, hipStream_t s);
+hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int grid, const P1Desc *descs, const Tile *tiles,
+                                 const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
+int occupancy_mixed(int fmt, int cls);
 // vvvv density (kernels_f64.hip, kernels_density.hip)
 hipError_t launch_assemble_density(int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
                                    const SysPtrs *sp, double *xbuf, hipStream_t s);
@@ -89,6 +89,16 @@ constexpr int kP1BM[3] = {64, 128, 128};
 constexpr int kP1BN[3] = {64, 64, 128};
 constexpr int kMixBM[4] = {64, 128, 128, 64};   // mixed path assembly tiles
 constexpr int kMixBN[4] = {128, 64, 128, 64};
+
+// Split precisions: slice format (0 BF16, 1 8-bit digits), K block width and
+// bytes per sliced element.
+inline bool is_split(int precision) { return precision == CDCC_MIXED || precision == CDCC_MIXED_I8; }
+inline int split_fmt(int precision) { return precision == CDCC_MIXED_I8 ? 1 : 0; }
+inline int split_kblock(int precision) { return precision == CDCC_MIXED_I8 ? 32 : 16; }
+inline int split_elem_bytes(int precision) { return precision == CDCC_MIXED_I8 ? 4 : 8; }
+// Longest K that the 8-bit kernels accumulate exactly in one pass (1023
+// blocks of 32); longer rows go to the kernel with K segments.
+constexpr int kI8MaxK = 1023 * 32;
 // Contraction tiles: 16 * fm packed (ij) rows x 32 group columns, fm = 1..4
 // per group (the kernel switches on it per tile).
 constexpr int kP2BN = 32;
@@ -101,6 +111,7 @@ inline int contract_fm(int n_ij) {
 
 struct Launch {
   int cls = 0, start = 0, count = 0, grid = 0;
+  int longk = 0;  // 8-bit split path: some tile has K > kI8MaxK (the K-segment kernel)
   Queues q{};
 };
 struct BatchPlan {
@@ -116,8 +127,8 @@ struct SysPlan {
   cdcc_layout_t lay{};
   int64_t th_elems = 0;      // packed +/- amplitudes
   int64_t u_elems = 0;       // Lambda operand stack
-  int64_t slice_u16 = 0;     // mixed path: sliced operand (uint16 units)
-  int64_t scale_rows = 0;    // mixed path: row scales
+  int64_t slice_bytes = 0;   // split paths: sliced operand
+  int64_t scale_rows = 0;    // split paths: row scales
   int p1cls = 0;
 };
 
@@ -276,14 +287,15 @@ std::string plan_key(int dev, int nsys, const cdcc_problem_t *p, int lambda, int
 }
 
 // Tile table written by the autotuner (paper_2512_21909_amd/autotune.py):
-// lines "<fp64|mixed> <t2|lambda> h nocc[h] nvir[h] ncd[h] class", looked up by
+// lines "<fp64|mixed|mixed_i8> <t2|lambda> h nocc[h] nvir[h] ncd[h] class", looked up by
 // the exact shape of each system.  Read once from $CDCC_TILE_TABLE or from
 // tile_table.txt next to this library.
 std::map<std::string, int> *g_tile_table = nullptr;
 
-std::string shape_key(const cdcc_sym_t &y, int mixed, int lambda) {
+std::string shape_key(const cdcc_sym_t &y, int precision, int lambda) {
   std::ostringstream k;
-  k << (mixed ? "mixed" : "fp64") << ' ' << (lambda ? "lambda" : "t2") << ' ' << y.nirrep;
+  k << (precision == CDCC_MIXED_I8 ? "mixed_i8" : precision == CDCC_MIXED ? "mixed" : "fp64") << ' '
+    << (lambda ? "lambda" : "t2") << ' ' << y.nirrep;
   for (const int32_t *a : {y.nocc, y.nvir, y.ncd})
     for (int g = 0; g < y.nirrep; ++g) k << ' ' << a[g];
   return k.str();
@@ -314,12 +326,16 @@ const std::map<std::string, int> &tile_table() {
   return *g_tile_table;
 }
 
-int choose_p1_class(const cdcc_layout_t &L, int policy, int mixed, int lambda) {
+int choose_p1_class(const cdcc_layout_t &L, int policy, int precision, int lambda) {
+  const bool mixed = is_split(precision);
   if (policy >= 1 && policy <= (mixed ? 4 : 3)) return policy - 1;
   const auto &T = tile_table();
-  const auto it = T.find(shape_key(L.sym, mixed, lambda));
+  const auto it = T.find(shape_key(L.sym, precision, lambda));
   if (it != T.end() && it->second >= 0 && it->second <= (mixed ? 3 : 2)) return it->second;
-  if (mixed) return 1;  // 128 x 64: best measured default for the split-BF16 kernel
+  // untuned shapes: 128 x 64 for split-BF16; 64 x 64 for the 8-bit digits
+  // (thirteen accumulators per 32 x 32 block: the 64-wide waves of the other
+  // classes run at one wave per SIMD)
+  if (mixed) return precision == CDCC_MIXED_I8 ? 3 : 1;
   // Tile-table heuristic: the largest tile that still gives >= 2 tiles per CU.
   const int h = L.sym.nirrep;
   const int32_t *nv = L.sym.nvir, *nc = L.sym.ncd;
@@ -394,7 +410,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
       for (int g = 0; g < probs[s].lay->sym.nirrep; ++g) mxrow = std::max<int64_t>(mxrow, int64_t(km) * probs[s].lay->sym.ncd[g] * 8);
     const bool fits = mxrow <= kSliceStageMax;
     P.slice_stage = fits ? int(std::max<int64_t>(mxrow, 8)) : 0;
-    P.fuse_dress = fits && lambda && opts.precision == CDCC_MIXED;
+    P.fuse_dress = fits && lambda && is_split(opts.precision);
   }
   for (int s = 0; s < nsys; ++s) {
     SysPlan &SP = P.sys[s];
@@ -403,16 +419,17 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     const int h = L.sym.nirrep;
     const int32_t *no = L.sym.nocc, *nv = L.sym.nvir, *nc = L.sym.ncd;
     const int kmul = (lambda && dressed) ? 2 : 1;
-    const bool mixed = opts.precision == CDCC_MIXED;
-    SP.p1cls = choose_p1_class(L, opts.tile_policy, mixed, lambda);
+    const bool mixed = is_split(opts.precision);
+    const int kblk = split_kblock(opts.precision), ebytes = split_elem_bytes(opts.precision);
+    SP.p1cls = choose_p1_class(L, opts.tile_policy, opts.precision, lambda);
     if (lambda && !P.fuse_dress) SP.u_elems = kmul * L.b_size;
     // mixed path: slice every operand block once per call
     int64_t blk_s[CDCC_MAX_IRREP][CDCC_MAX_IRREP], blk_sc[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
     int blk_kp[CDCC_MAX_IRREP];
-    for (int gP = 0; gP < h; ++gP) blk_kp[gP] = kmul * ((nc[gP] + 15) / 16 * 16);
+    for (int gP = 0; gP < h; ++gP) blk_kp[gP] = kmul * ((nc[gP] + kblk - 1) / kblk * kblk);
     for (int gP = 0; gP < h; ++gP)
       for (int ga = 0; ga < h; ++ga) {
-        blk_s[gP][ga] = SP.slice_u16;
+        blk_s[gP][ga] = SP.slice_bytes;
         blk_sc[gP][ga] = SP.scale_rows;
         const int64_t r = int64_t(nv[ga]) * nv[ga ^ gP];
         if (!mixed || nc[gP] == 0 || r == 0) continue;
@@ -423,7 +440,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
         J.halves = kmul;
         J.Kp = blk_kp[gP];
         J.src_off = kmul * L.b_off[gP][ga];
-        J.dst_off = SP.slice_u16;
+        J.dst_off = SP.slice_bytes;
         J.scale_off = SP.scale_rows;
         if (P.fuse_dress) {
           const int ge = ga ^ gP;
@@ -437,7 +454,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
         const int jid = int(slicejobs.size());
         slicejobs.push_back(J);
         for (int q = 0; q < r; ++q) slicerows.push_back(int2{jid, q});
-        SP.slice_u16 += r * J.Kp * 4;
+        SP.slice_bytes += r * J.Kp * ebytes;
         SP.scale_rows += r;
       }
 
@@ -610,8 +627,8 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
               d.aoff = kmul * L.b_off[gP][ga] + int64_t(as) * vc * K;
               d.boff = kmul * L.b_off[gP][gb];
               d.Kp = blk_kp[gP];
-              d.kneg_blk = (lambda && dressed) ? blk_kp[gP] / 32 : blk_kp[gP] / 16;
-              d.a_soff = blk_s[gP][ga] + int64_t(as) * vc * d.Kp * 4;
+              d.kneg_blk = (lambda && dressed) ? blk_kp[gP] / 2 / kblk : blk_kp[gP] / kblk;
+              d.a_soff = blk_s[gP][ga] + int64_t(as) * vc * d.Kp * ebytes;
               d.b_soff = blk_s[gP][gb];
               d.a_scoff = blk_sc[gP][ga] + int64_t(as) * vc;
               d.b_scoff = blk_sc[gP][gb];
@@ -646,13 +663,14 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     // once, with balanced A and B row counts
     int st_m[4], st_n[4], st_chunk[4];
     for (int c = 0; c < 4; ++c) {
-      const bool mx = P.precision == CDCC_MIXED;
+      const bool mx = is_split(P.precision);
       if (!mx && c == 3) {
         st_m[c] = st_n[c] = st_chunk[c] = 1;
         continue;
       }
       const int bm = mx ? kMixBM[c] : kP1BM[c], bn = mx ? kMixBN[c] : kP1BN[c];
-      const int conc = std::max(1, g_num_cu / 8 * (mx ? occupancy_mixed(c) : occupancy_f64(0, c)));
+      const int occ = mx ? occupancy_mixed(split_fmt(P.precision), c) : occupancy_f64(0, c);
+      const int conc = std::max(1, g_num_cu / 8 * occ);
       st_m[c] = std::max(1, int(std::lround(std::sqrt(double(conc) * bn / bm))));
       st_n[c] = std::max(1, conc / st_m[c]);
       st_chunk[c] = st_m[c] * st_n[c];
@@ -705,7 +723,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
       }
       p2.push_back(R.g);
       const int c1 = P.sys[R.sys].p1cls;
-      const bool mixed = P.precision == CDCC_MIXED;
+      const bool mixed = is_split(P.precision);
       const int bm = mixed ? kMixBM[c1] : kP1BM[c1], bn = mixed ? kMixBN[c1] : kP1BN[c1];
       const int stm = st_m[c1], stn = st_n[c1];
       for (P1Desc d : R.descs) {
@@ -733,10 +751,15 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     P.part_elems = std::max(P.part_elems, po);
     red.count = int(redjobs.size()) - red.start;
     B.red = red;
-    const bool mixedp = P.precision == CDCC_MIXED;
+    const bool mixedp = is_split(P.precision);
     for (int c = 0; c < 4; ++c)
-      emit(t1[c], st_chunk[c], c, mixedp ? occupancy_mixed(c) : occupancy_f64(0, c), p1tiles, B.p1);
+      emit(t1[c], st_chunk[c], c, mixedp ? occupancy_mixed(split_fmt(P.precision), c) : occupancy_f64(0, c), p1tiles,
+           B.p1);
     emit(t2[0], 8, 0, occupancy_f64(1, 0), p2tiles, B.p2);
+    if (P.precision == CDCC_MIXED_I8)
+      for (Launch &l : B.p1)
+        for (int i = l.start; i < l.start + l.count; ++i)
+          if (p1[p1tiles[i].desc].Kp > kI8MaxK) l.longk = 1;
     P.batches.push_back(std::move(B));
     gi = gj;
   }
@@ -805,7 +828,7 @@ WsLayout ws_layout(const Plan &P) {
     W.u[s] = o;
     o = align_up(o + P.sys[s].u_elems * 8);
     W.sl[s] = o;
-    o = align_up(o + P.sys[s].slice_u16 * 2);
+    o = align_up(o + P.sys[s].slice_bytes);
     W.sc[s] = o;
     o = align_up(o + P.sys[s].scale_rows * 8);
   }
@@ -914,9 +937,9 @@ int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, 
     Span sp(0, P->ndressrows > 0, stream);
     HIPCHK(launch_dress(P->dressjobs, P->dressrows, P->ndressrows, dsp, stream));
   }
-  if (P->precision == CDCC_MIXED) {
+  if (is_split(P->precision)) {
     Span sp(5, P->nslicerows > 0, stream);
-    HIPCHK(launch_slice(P->slicejobs, P->slicerows, P->nslicerows, dsp, P->slice_stage, stream));
+    HIPCHK(launch_slice(split_fmt(P->precision), P->slicejobs, P->slicerows, P->nslicerows, dsp, P->slice_stage, stream));
   }
   {
     Span sp(1, P->npackrows > 0, stream);
@@ -928,8 +951,9 @@ int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, 
       Span sp(2, int(B.p1.size()), stream);
       for (const Launch &l : B.p1) {
         int *cnt = counters + 8 * kQueueStride * ci++;
-        if (P->precision == CDCC_MIXED)
-          HIPCHK(launch_assemble_mixed(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
+        if (is_split(P->precision))
+          HIPCHK(launch_assemble_mixed(split_fmt(P->precision), l.cls, l.longk, l.grid, P->p1, P->p1tiles + l.start,
+                                       l.q, cnt, dsp, xbuf, stream));
         else
           HIPCHK(launch_assemble_f64(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
       }
@@ -964,9 +988,9 @@ hipStream_t capture_stream(int dev) {
 int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *popts, void *vstream, int lambda) {
   cdcc_opts_t opts{};
   if (popts) opts = *popts;
-  if (opts.precision != CDCC_FP64 && opts.precision != CDCC_MIXED) return CDCC_EINVAL;
+  if (opts.precision != CDCC_FP64 && !is_split(opts.precision)) return CDCC_EINVAL;
   if (opts.tile_policy < 0 || opts.tile_policy > 4) return CDCC_EINVAL;
-  if (opts.tile_policy == 4 && opts.precision != CDCC_MIXED) return CDCC_EINVAL;
+  if (opts.tile_policy == 4 && !is_split(opts.precision)) return CDCC_EINVAL;
   int dressed = 0;
   int rc = validate(nsys, probs, lambda, &dressed);
   if (rc != CDCC_OK) return rc;
@@ -1001,7 +1025,7 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
     q.B = p.B;
     q.Bvo = p.Bvo;
     q.t1 = p.t1;
-    q.slices = reinterpret_cast<uint16_t *>(base + W.sl[s]);
+    q.slices = reinterpret_cast<unsigned char *>(base + W.sl[s]);
     q.rowscale = reinterpret_cast<double *>(base + W.sc[s]);
     hs[s] = q;
   }
@@ -1306,7 +1330,7 @@ DensWs dens_ws_layout(const DensPlan &P) {
 int run_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_opts_t *popts, void *vstream) {
   cdcc_opts_t opts{};
   if (popts) opts = *popts;
-  if (opts.precision != CDCC_FP64) return opts.precision == CDCC_MIXED ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+  if (opts.precision != CDCC_FP64) return is_split(opts.precision) ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
   int rc = validate_density(nsys, probs);
   if (rc != CDCC_OK) return rc;
   if (nsys == 0) return CDCC_OK;
@@ -1523,7 +1547,7 @@ int validate_partial(int32_t nsys, const cdcc_partial_problem_t *probs) {
 int run_partial(int32_t nsys, const cdcc_partial_problem_t *probs, const cdcc_opts_t *popts, void *vstream) {
   cdcc_opts_t opts{};
   if (popts) opts = *popts;
-  if (opts.precision != CDCC_FP64) return opts.precision == CDCC_MIXED ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+  if (opts.precision != CDCC_FP64) return is_split(opts.precision) ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
   int rc = validate_partial(nsys, probs);
   if (rc != CDCC_OK) return rc;
   if (nsys == 0) return CDCC_OK;

@@ -1,14 +1,34 @@
-// Split-BF16 kernels of the (ac|bd) batch assembly for gfx950 (mixed path).
+// Split-precision kernels of the (ac|bd) batch assembly for gfx950.
 //
 // Each operand row x (one (a,c) pair over the Cholesky index) is scaled by a
-// power of two sigma >= max|x| and cut into four exponent-aligned BF16 slices
+// power of two sigma and cut into four slices, and the product of two rows is
+// a sum of slice products.  Two slice formats:
+//
+// BF16 (CDCC_MIXED).  sigma >= max|x|, exponent-aligned BF16 slices
 //   y = x / sigma = s0 + s1 + s2 + s3 + r,   s_t = m_t 2^-8(t+1), |m_t| <= 256,
-// so that |r| <= 2^-33.  The product of two rows is the sum of the ten slice
-// products with t + u <= 3.  The leading product s0 * s0 has 16-bit integer
+// so that |r| <= 2^-33.  The ten slice products with t + u <= 3 are formed.
+// The leading product s0 * s0 has 16-bit integer
 // terms in units of 2^-16: accumulated in FP32 on MFMA it is exact for up to
 // 256 terms, so it is flushed into an FP64 total every 256 K.  The nine
 // lower-order products go to a second FP32 accumulator (their rounding is
 // 2^-32 relative to the result scale) and are flushed at the same points.
+//
+// 8-bit digits (CDCC_MIXED_I8).  y = x / sigma = sum_t m_t 2^-(7+8t) + r with
+// signed digits m_0 in [-126, 127], m_t in [-128, 127] (t >= 1) and
+// |r| <= 2^-32: a base-256 expansion by rounding to nearest, then a carry
+// pass that moves a digit of +128 into the one above it (sigma is chosen with
+// |128 y| < 126.5, so the leading digit cannot overflow).  The leading digit
+// has one bit less than a BF16 slice (BF16 takes it from its exponent), so
+// the thirteen products with t + u <= 4 are formed: the dropped ones are then
+// below 2^-39 of the row scales and the error is that of the truncation.
+// Products of two digits are at most 2^14, so MFMA i32 32x32x32 accumulates
+// them exactly; the products of one weight t + u = w share an int32
+// accumulator, exact for K <= 32736 (four products of weight 3 per K), and
+// longer K runs in segments whose FP64 results are added in order.  The Lambda stack's subtracted half
+// is handled by negating the accumulators (exact in int32) at its first K
+// block and the total at the end.  The accumulators are combined once, in
+// FP64: sum_w acc_w 2^-8w.
+//
 // The FP64 total is finally scaled by sigma_x sigma_y (exact).
 #include <hip/hip_runtime.h>
 
@@ -17,12 +37,17 @@
 namespace cdcc {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+typedef int i4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // MFMA f32 32x32x16 bf16 lane mapping (gfx950): A[i][k] in lane i + 32(k/8),
 // element k%8; B[k][j] in lane j + 32(k/8); result register r of lane l is
-// D[8(r/4) + 4(l/32) + r%4][l%32].
+// D[8(r/4) + 4(l/32) + r%4][l%32].  MFMA i32 32x32x32 i8 has the same row,
+// column and result mapping with 16 bytes of K per lane; A and B fragments are
+// read with the same K order, so the order inside a 16-byte chunk never
+// matters.
 
 // s_waitcnt immediate (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
 // 6:4, lgkmcnt in 11:8): wait for vmcnt <= v and lgkmcnt <= l.
@@ -41,6 +66,13 @@ __device__ __forceinline__ uint16_t bf16_bits_exact(double v) {
   return uint16_t(__float_as_uint(float(v)) >> 16);
 }
 
+// K segment of the 8-bit path: 1023 blocks of 32 (K <= 32736 keeps the
+// weight-3 accumulator, four products of at most 2^14 per K, below 2^31).
+// Launches whose tiles all fit one segment use the kernel without the
+// segment loop (LONGK = false): the loop and its read-modify-write epilogue
+// cost registers.
+constexpr int kI8SegBlocks = 1023;
+
 // ---------------------------------------------------------------------------
 // slice: one workgroup per operand row.  With STAGE the row is first written
 // to LDS (dynamic size: halves * np doubles) and read from there twice (for
@@ -49,8 +81,10 @@ __device__ __forceinline__ uint16_t bf16_bits_exact(double v) {
 // as the dress kernel builds them:
 //   U[P] = B^P_ea - t^P_ea,  U[np + P] = t^P_ea,  t^P_ea = sum_m t_m^e L^P_am
 // (without singles, U = B), so the FP64 stack never goes to memory.
+// Output per K block: BF16, 16 K x 4 slices x 2 bytes (slice t at bytes
+// [32t, 32t + 32)); I8, 32 K x 4 digits x 1 byte (digit t at [32t, 32t + 32)).
 // ---------------------------------------------------------------------------
-template <bool STAGE>
+template <bool STAGE, bool I8>
 __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__ jobs,
                                                     const int2 *__restrict__ rows,
                                                     const SysPtrs *__restrict__ sp) {
@@ -102,47 +136,86 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
   __syncthreads();
   mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   int e = 0;
-  if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)  =>  |x| < 2^e
+  if (mx > 0.0) {
+    const double f = frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)  =>  |x| < 2^e
+    if (I8 && f >= 253.0 / 256.0) ++e;  // keeps |128 x / sigma| < 126.5
+  }
   const double sigma = ldexp(1.0, e), inv = ldexp(1.0, -e);
   if (threadIdx.x == 0) S.rowscale[J.scale_off + row] = sigma;
   const int Kh = J.Kp / J.halves;
-  uint16_t *__restrict__ dst = S.slices + J.dst_off + int64_t(row) * J.Kp * 4;
-#pragma unroll 4
-  for (int kp = threadIdx.x; kp < J.Kp; kp += 256) {
+  unsigned char *__restrict__ dst = S.slices + J.dst_off + int64_t(row) * J.Kp * (I8 ? 4 : 8);
+  auto elem = [&](int kp) {
     const int half = kp >= Kh ? 1 : 0;
     const int k = kp - half * Kh;
-    const double x = k < J.np ? (STAGE ? srow[half * J.np + k] : src[half * J.np + k]) : 0.0;
-    const double y = x * inv;
-    const double s0 = rint(y * 256.0) * (1.0 / 256.0);
-    double r = y - s0;
-    const double s1 = rint(r * 65536.0) * (1.0 / 65536.0);
-    r -= s1;
-    const double s2 = rint(r * 16777216.0) * (1.0 / 16777216.0);
-    r -= s2;
-    const double s3 = rint(r * 4294967296.0) * (1.0 / 4294967296.0);
-    uint16_t *o = dst + (kp >> 4) * 64 + (kp & 15);
-    o[0] = bf16_bits_exact(s0);
-    o[16] = bf16_bits_exact(s1);
-    o[32] = bf16_bits_exact(s2);
-    o[48] = bf16_bits_exact(s3);
+    return k < J.np ? (STAGE ? srow[half * J.np + k] : src[half * J.np + k]) : 0.0;
+  };
+  if constexpr (I8) {
+    // four consecutive K per thread (Kh is a multiple of 32: never across halves)
+    const double inv128 = inv * 128.0;
+#pragma unroll 2
+    for (int k4 = threadIdx.x * 4; k4 < J.Kp; k4 += 1024) {
+      unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double v = elem(k4 + q) * inv128;  // |v| < 126.5
+        int m[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double r = floor(v + 0.5);
+          m[t] = int(r);
+          v = (v - r) * 256.0;  // exact: v - r lies in [-0.5, 0.5)
+        }
+#pragma unroll
+        for (int t = 3; t > 0; --t)
+          if (m[t] >= 128) {  // +128 (or +129 after a carry) -> borrow from the digit above
+            m[t] -= 256;
+            m[t - 1] += 1;
+          }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) w[t] |= (unsigned(m[t]) & 0xffu) << (8 * q);
+      }
+      unsigned char *o = dst + int64_t(k4 >> 5) * 128 + (k4 & 31);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) *reinterpret_cast<unsigned *>(o + 32 * t) = w[t];
+    }
+  } else {
+    uint16_t *d16 = reinterpret_cast<uint16_t *>(dst);
+#pragma unroll 4
+    for (int kp = threadIdx.x; kp < J.Kp; kp += 256) {
+      const double y = elem(kp) * inv;
+      const double s0 = rint(y * 256.0) * (1.0 / 256.0);
+      double r = y - s0;
+      const double s1 = rint(r * 65536.0) * (1.0 / 65536.0);
+      r -= s1;
+      const double s2 = rint(r * 16777216.0) * (1.0 / 16777216.0);
+      r -= s2;
+      const double s3 = rint(r * 4294967296.0) * (1.0 / 4294967296.0);
+      uint16_t *o = d16 + (kp >> 4) * 64 + (kp & 15);
+      o[0] = bf16_bits_exact(s0);
+      o[16] = bf16_bits_exact(s1);
+      o[32] = bf16_bits_exact(s2);
+      o[48] = bf16_bits_exact(s3);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// assemble (mixed): tile BM x BN, (BM/32) x (BN/WN) waves of 32 x WN (WN/32
-// blocks of 32x32 each).  An LDS row holds one 16-wide K block of all four
-// slices of one operand row (128 B, eight 16-byte chunks).  Rows are copied
-// from global memory straight into LDS (global_load_lds_dwordx4) through a
-// ring of three stages (three LDS arrays, the K loop unrolled by three),
-// two K blocks ahead of the MFMAs, with one barrier per K block.  A copy instruction writes 64 consecutive 16-byte chunks, so
-// the chunk order inside a row is permuted on the source side (physical
-// chunk c of row r holds logical chunk c ^ ((r / 2) % 8)): the 16 rows a
-// 16-lane group of a fragment read touches then fall on 16 different
-// 16-byte bank groups of the 256-byte bank width.  Rows past the tile edge are read
-// clamped: they only reach results that are never stored.  The sign of the
-// subtracted part of the Lambda stack is applied to the B fragments.
+// assemble (split paths): tile BM x BN, (BM/32) x (BN/WN) waves of 32 x WN
+// (WN/32 blocks of 32x32 each).  An LDS row holds one K block (16 K of BF16
+// slices or 32 K of 8-bit digits) of all four slices of one operand row (128
+// B, eight 16-byte chunks).  Rows are copied from global memory straight into
+// LDS (global_load_lds_dwordx4) through a ring of three stages (three LDS
+// arrays, the K loop unrolled by three), two K blocks ahead of the MFMAs,
+// with one barrier per K block.  A copy instruction writes 64 consecutive
+// 16-byte chunks, so the chunk order inside a row is permuted on the source
+// side (physical chunk c of row r holds logical chunk c ^ ((r / 2) % 8)): the
+// 16 rows a 16-lane group of a fragment read touches then fall on 16
+// different 16-byte bank groups of the 256-byte bank width.  Rows past the
+// tile edge are read clamped: they only reach results that are never stored.
+// BF16: the sign of the subtracted part of the Lambda stack is applied to the
+// B fragments.  I8: the accumulators are negated at that part's first block.
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int WN>
+template <int BM, int BN, int WN, bool I8, bool LONGK>
 __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_kernel(
     const P1Desc *__restrict__ descs, const Tile *__restrict__ tiles, Queues Q, int *__restrict__ cnt,
     const SysPtrs *__restrict__ sp, double *__restrict__ xbuf) {
@@ -152,7 +225,9 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
   constexpr int ROWB = 128;                    // bytes per LDS row
   constexpr int STAGE = (BM + BN) * ROWB;      // bytes per ring stage
   constexpr int NI = (BM + BN) / (8 * NW);     // copy instructions per wave per K block (8 rows each)
+  constexpr int KBW = I8 ? 32 : 16;            // K per block
   static_assert((BM + BN) % (8 * NW) == 0, "staging");
+  static_assert(I8 || !LONGK, "K segments are an 8-bit-path feature");
   __shared__ __attribute__((aligned(16))) unsigned char st0[STAGE];
   __shared__ __attribute__((aligned(16))) unsigned char st1[STAGE];
   __shared__ __attribute__((aligned(16))) unsigned char st2[STAGE];
@@ -170,8 +245,8 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
     const P1Desc D = descs[tl.desc];
     const SysPtrs S = sp[D.sys];
     const int m0 = tl.tm * BM, n0 = tl.tn * BN;
-    const int nkb = D.Kp / 16;
-    const int64_t rowstride = int64_t(D.Kp) * 8;  // bytes per sliced row
+    const int nkb = D.Kp / KBW;
+    const int64_t rowstride = int64_t(D.Kp) * (I8 ? 4 : 8);  // bytes per sliced row
 
     // source of the 16-byte chunk this lane copies in each instruction
     const CDCC_GLOBAL unsigned char *src[NI];
@@ -182,11 +257,11 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
       const unsigned char *base;
       if (r < BM) {
         const int m = m0 + r < D.M ? m0 + r : D.M - 1;
-        base = reinterpret_cast<const unsigned char *>(S.slices + D.a_soff) + int64_t(m) * rowstride;
+        base = S.slices + D.a_soff + int64_t(m) * rowstride;
       } else {
         const int n = n0 + (r - BM) < D.N ? n0 + (r - BM) : D.N - 1;
         const int dd = n / D.nb, b = n - dd * D.nb;
-        base = reinterpret_cast<const unsigned char *>(S.slices + D.b_soff) + (int64_t(b) * D.vd + dd) * rowstride;
+        base = S.slices + D.b_soff + (int64_t(b) * D.vd + dd) * rowstride;
       }
       src[i] = as_global(base) + part * 16;
     }
@@ -197,15 +272,11 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
         lds_copy16(src[i] + int64_t(kb) * ROWB, st + (i * NW + wave) * 8 * ROWB);
     };
 
+    // BF16 state
     f16v acc0[NJ], acc1[NJ];
     double tot[NJ][16];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      acc0[j] = f16v{};
-      acc1[j] = f16v{};
-#pragma unroll
-      for (int r = 0; r < 16; ++r) tot[j][r] = 0.0;
-    }
+    // I8 state: accumulator w holds the products of weight t + u = w
+    i16v iacc[5][NJ];
     auto flush = [&]() {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -230,58 +301,72 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
       }
     }
 
-    auto step = [&](const unsigned char *L, int kb) {
-      const unsigned flip = kb >= D.kneg_blk ? 0x80008000u : 0u;
-      bf8 a[4];
+    // I8 step in two parts: every fragment of the block is read before the
+    // next block's copies are issued (with the reads after the copies, the
+    // compiler's LDS-DMA wait tracking falls back to waiting for every copy
+    // in flight, which drains the ring), then the ten products
+    i4v fa[4], fb[NJ][4];
+    auto read_i8 = [&](const unsigned char *L) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) a[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + aoff[s]));
+      for (int s = 0; s < 4; ++s) fa[s] = *reinterpret_cast<const i4v *>(L + aoff[s]);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) fb[j][s] = *reinterpret_cast<const i4v *>(L + boff[j][s]);
+    };
+    // the thirteen products with t + u <= 4, ordered so that no two
+    // consecutive ones share an accumulator
+    auto mfma_i8 = [&]() {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        bf8 b[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-          b[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + boff[j][s]) ^ flip);
-        acc0[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], acc0[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[3], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[2], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[1], acc1[j], 0, 0, 0);
-        acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[0], acc1[j], 0, 0, 0);
+#define CDCC_I8P(t, u) \
+  iacc[t + u][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[t], fb[j][u], iacc[t + u][j], 0, 0, 0)
+        CDCC_I8P(0, 0);
+        CDCC_I8P(0, 1);
+        CDCC_I8P(0, 2);
+        CDCC_I8P(0, 3);
+        CDCC_I8P(1, 3);
+        CDCC_I8P(1, 0);
+        CDCC_I8P(1, 1);
+        CDCC_I8P(1, 2);
+        CDCC_I8P(2, 2);
+        CDCC_I8P(2, 0);
+        CDCC_I8P(2, 1);
+        CDCC_I8P(3, 1);
+        CDCC_I8P(3, 0);
+#undef CDCC_I8P
       }
-      if ((kb & 15) == 15 || kb == nkb - 1) flush();  // every 256 K: keep the leading accumulator exact
+    };
+    auto step = [&](const unsigned char *L, int kb) {
+      {
+        const unsigned flip = kb >= D.kneg_blk ? 0x80008000u : 0u;
+        bf8 a[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + aoff[s]));
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          bf8 b[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            b[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + boff[j][s]) ^ flip);
+          acc0[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], acc0[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[3], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[2], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[1], acc1[j], 0, 0, 0);
+          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[0], acc1[j], 0, 0, 0);
+        }
+        if ((kb & 15) == 15 || kb == nkb - 1) flush();  // every 256 K: keep the leading accumulator exact
+      }
     };
 
-    if (nkb > 0) {
-      issue(stage[0], 0);
-      issue(stage[1], 1);
-    }
-    for (int kb = 0; kb < nkb; kb += 3) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        if (kb + q < nkb) {
-          // this wave's copies of block kb + q have landed once only the NI
-          // copies of the next block are in flight, and its fragment reads of
-          // the previous block are done; the barrier then makes every wave's
-          // copies visible and frees the stage read in the previous step
-          __builtin_amdgcn_s_waitcnt(waitcnt_imm(NI, 0));
-          __builtin_amdgcn_s_barrier();
-          __asm__ volatile("" ::: "memory");  // no LDS access moves above the barrier
-          issue(stage[(q + 2) % 3], kb + q + 2);
-          step(stage[q], kb + q);
-        }
-      }
-    }
-    // the redundant copies issued past the end must land before the stage
-    // memory is reused by the next tile
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
-
-    // epilogue: scale and permuted store (same numbering as the FP64 path).
-    // Quotients by vc and nb come from a float reciprocal estimate and are
-    // corrected to the exact floor (the estimate is off by at most one).
+    // epilogue constants: quotients by vc and nb come from a float
+    // reciprocal estimate and are corrected to the exact floor (the estimate
+    // is off by at most one)
     const float rvc = 1.0f / float(D.vc), rnb = 1.0f / float(D.nb);
     auto qdiv = [](int x, int d, float rd) {
       int q = int(float(x) * rd);
@@ -291,61 +376,161 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
     };
     const CDCC_GLOBAL double *rs = as_global(S.rowscale);
     const int mb = m0 + wm * 32 + 4 * (lane >> 5);
+
+    // K segments (several only in the LONGK kernel)
+    const int segb = LONGK ? kI8SegBlocks : (nkb > 0 ? nkb : 1);
+    for (int kb0 = 0; kb0 == 0 || kb0 < nkb; kb0 += segb) {
+      const int kb1 = nkb < kb0 + segb ? nkb : kb0 + segb;
+      if (LONGK && kb0 > 0) __syncthreads();  // every wave is done with the previous segment's stages
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int n = n0 + wn * WN + j * 32 + (lane & 31);
-      if (n >= D.N) continue;
-      const int dd = qdiv(n, D.nb, rnb), b = n - dd * D.nb;
-      const double sb = rs[D.b_scoff + int64_t(b) * D.vd + dd];
+      for (int j = 0; j < NJ; ++j) {
+        if constexpr (I8) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = mb + 8 * (r >> 2) + (r & 3);
-        if (m >= D.M) continue;
-        const int am = qdiv(m, D.vc, rvc), c = m - am * D.vc;
-        const int a = D.a_first + am;
-        if (D.tri && b > a) continue;
-        const double sa = rs[D.a_scoff + m];
-        const int64_t xcol = D.tri ? (int64_t(a) * (a + 1) / 2 - int64_t(D.ga0) * (D.ga0 + 1) / 2 + b)
-                                   : (int64_t(a - D.ga0) * D.vb + b);
-        const int64_t xrow = D.xrow0 + int64_t(c) * D.vd + dd;
-        xbuf[D.xoff + xrow * D.ldx + xcol] = 0.5 * (sa * sb) * tot[j][r];
+          for (int w = 0; w < 5; ++w) iacc[w][j] = i16v{};
+        } else {
+          acc0[j] = f16v{};
+          acc1[j] = f16v{};
+#pragma unroll
+          for (int r = 0; r < 16; ++r) tot[j][r] = 0.0;
+        }
+      }
+      if (kb1 > kb0) {
+        issue(stage[0], kb0);
+        issue(stage[1], kb0 + 1);
+      }
+      for (int kb = kb0; kb < kb1; kb += 3) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          if (kb + q < kb1) {
+            // this wave's copies of block kb + q have landed once only the NI
+            // copies of the next block are in flight, and its fragment reads of
+            // the previous block are done; the barrier then makes every wave's
+            // copies visible and frees the stage read in the previous step
+            __builtin_amdgcn_s_waitcnt(waitcnt_imm(NI, 0));
+            __builtin_amdgcn_s_barrier();
+            __asm__ volatile("" ::: "memory");  // no LDS access moves above the barrier
+            if constexpr (I8) {
+              // first block of the subtracted half: acc <- -acc (here, not
+              // between the copies and the fragment reads, so that the reads
+              // can still be scheduled ahead of the copies)
+              if (kb + q == D.kneg_blk) {
+#pragma unroll
+                for (int w = 0; w < 5; ++w)
+#pragma unroll
+                  for (int j = 0; j < NJ; ++j) iacc[w][j] = -iacc[w][j];
+              }
+            }
+            if constexpr (I8) {
+              read_i8(stage[q]);
+              __asm__ volatile("" ::: "memory");  // fragment reads stay ahead of the copies
+              issue(stage[(q + 2) % 3], kb + q + 2);
+              mfma_i8();
+            } else {
+              issue(stage[(q + 2) % 3], kb + q + 2);
+              step(stage[q], kb + q);
+            }
+          }
+        }
+      }
+      // the redundant copies issued past the end must land before the stage
+      // memory is reused by the next segment or tile
+      __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
+
+      // scale and permuted store (same numbering as the FP64 path); later
+      // segments add to what the earlier ones stored (same lane, same element)
+      const double sgn = (I8 && kb1 > D.kneg_blk) ? -1.0 : 1.0;
+      const double unit = I8 ? 0.5 * sgn * (1.0 / 16384.0) : 0.5;  // digit products are in units of 2^-14
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int n = n0 + wn * WN + j * 32 + (lane & 31);
+        if (n >= D.N) continue;
+        const int dd = qdiv(n, D.nb, rnb), b = n - dd * D.nb;
+        const double sb = rs[D.b_scoff + int64_t(b) * D.vd + dd];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = mb + 8 * (r >> 2) + (r & 3);
+          if (m >= D.M) continue;
+          const int am = qdiv(m, D.vc, rvc), c = m - am * D.vc;
+          const int a = D.a_first + am;
+          if (D.tri && b > a) continue;
+          const double sa = rs[D.a_scoff + m];
+          const int64_t xcol = D.tri ? (int64_t(a) * (a + 1) / 2 - int64_t(D.ga0) * (D.ga0 + 1) / 2 + b)
+                                     : (int64_t(a - D.ga0) * D.vb + b);
+          const int64_t xrow = D.xrow0 + int64_t(c) * D.vd + dd;
+          double v;
+          if constexpr (I8) {
+            v = (((double(iacc[4][j][r]) * 0x1p-32 + double(iacc[3][j][r]) * 0x1p-24) +
+                  double(iacc[2][j][r]) * 0x1p-16) + double(iacc[1][j][r]) * 0x1p-8) + double(iacc[0][j][r]);
+          } else {
+            v = tot[j][r];
+          }
+          double *px = xbuf + D.xoff + xrow * D.ldx + xcol;
+          const double x = (unit * (sa * sb)) * v;
+          *px = (LONGK && kb0 > 0) ? *px + x : x;
+        }
       }
     }
   }
 }
 
 // stage_bytes > 0: rows staged in that much dynamic LDS (required for dress
-// jobs); 0: rows read from global memory twice.
-hipError_t launch_slice(const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp, int stage_bytes,
-                        hipStream_t s) {
+// jobs); 0: rows read from global memory twice.  fmt: 0 BF16, 1 8-bit digits.
+hipError_t launch_slice(int fmt, const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp,
+                        int stage_bytes, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
-  if (stage_bytes > 0)
-    slice_kernel<true><<<nrows, 256, stage_bytes, s>>>(jobs, rows, sp);
-  else
-    slice_kernel<false><<<nrows, 256, 0, s>>>(jobs, rows, sp);
-  return hipGetLastError();
-}
-
-hipError_t launch_assemble_mixed(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q,
-                                 int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  switch (cls) {
-    case 0: assemble_mixed_kernel<64, 128, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
-    case 1: assemble_mixed_kernel<128, 64, 64><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
-    case 2: assemble_mixed_kernel<128, 128, 64><<<grid, 512, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
-    default: assemble_mixed_kernel<64, 64, 32><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+  if (fmt == 1) {
+    if (stage_bytes > 0)
+      slice_kernel<true, true><<<nrows, 256, stage_bytes, s>>>(jobs, rows, sp);
+    else
+      slice_kernel<false, true><<<nrows, 256, 0, s>>>(jobs, rows, sp);
+  } else {
+    if (stage_bytes > 0)
+      slice_kernel<true, false><<<nrows, 256, stage_bytes, s>>>(jobs, rows, sp);
+    else
+      slice_kernel<false, false><<<nrows, 256, 0, s>>>(jobs, rows, sp);
   }
   return hipGetLastError();
 }
 
-int occupancy_mixed(int cls) {
+template <bool I8, bool LONGK>
+static void launch_assemble_fmt(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
+                                const SysPtrs *sp, double *xbuf, hipStream_t s) {
+  switch (cls) {
+    case 0: assemble_mixed_kernel<64, 128, 64, I8, LONGK><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    case 1: assemble_mixed_kernel<128, 64, 64, I8, LONGK><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    case 2: assemble_mixed_kernel<128, 128, 64, I8, LONGK><<<grid, 512, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    default: assemble_mixed_kernel<64, 64, 32, I8, LONGK><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+  }
+}
+
+// longk: some tile of the launch has K > 32736 (8-bit path only)
+hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int grid, const P1Desc *descs, const Tile *tiles,
+                                 const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  if (fmt == 1 && longk)
+    launch_assemble_fmt<true, true>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+  else if (fmt == 1)
+    launch_assemble_fmt<true, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+  else
+    launch_assemble_fmt<false, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+  return hipGetLastError();
+}
+
+template <bool I8>
+static int occupancy_fmt(int cls) {
   int n = 0;
   hipError_t e;
-  if (cls == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 128, 64>, 256, 0);
-  else if (cls == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 64, 64>, 256, 0);
-  else if (cls == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 128, 64>, 512, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 64, 32>, 256, 0);
+  if (cls == 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 128, 64, I8, false>, 256, 0);
+  else if (cls == 1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 64, 64, I8, false>, 256, 0);
+  else if (cls == 2)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 128, 64, I8, false>, 512, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 64, 32, I8, false>, 256, 0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
+
+int occupancy_mixed(int fmt, int cls) { return fmt == 1 ? occupancy_fmt<true>(cls) : occupancy_fmt<false>(cls); }
 
 }  // namespace cdcc

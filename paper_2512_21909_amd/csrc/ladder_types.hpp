@@ -19,7 +19,7 @@ struct SysPtrs {
   const double *B;       // raw Cholesky vectors (Lambda dressing input)
   const double *Bvo;     // optional vo block (Lambda)
   const double *t1;      // optional singles (Lambda)
-  uint16_t *slices;      // workspace: BF16 slices of the assembly operand (mixed path)
+  unsigned char *slices; // workspace: sliced assembly operand (split paths: BF16 or 8-bit digits)
   double *rowscale;      // workspace: per-row power-of-two scales of the operand (mixed path)
 };
 
@@ -44,13 +44,13 @@ struct P1Desc {
   int32_t ga0;         // first a of the owning column group (column numbering)
   int32_t tri;         // Ga == Gb: only b <= a is stored
   int32_t ldx, xrow0;  // X region row length; first region row of this Gc block
-  int32_t Kp;          // mixed path: padded K of a sliced row (multiple of 16)
-  int32_t kneg_blk;    // mixed path: first 16-wide K block negated on the right
+  int32_t Kp;          // split paths: padded K of a sliced row (multiple of the K block)
+  int32_t kneg_blk;    // split paths: first K block (16 wide BF16, 32 wide 8-bit) of the subtracted half
   int64_t aoff;        // element offset of operand row (a_first, c=0)
   int64_t boff;        // element offset of operand row (b=0, d=0) of block (GP, Gb)
   int64_t xoff;        // element offset of the group's X region in the batch buffer
-  int64_t a_soff;      // mixed path: uint16 offset of sliced row (a_first, c=0)
-  int64_t b_soff;      // mixed path: uint16 offset of sliced row (0, 0) of block (GP, Gb)
+  int64_t a_soff;      // split paths: byte offset of sliced row (a_first, c=0)
+  int64_t b_soff;      // split paths: byte offset of sliced row (0, 0) of block (GP, Gb)
   int64_t a_scoff;     // mixed path: row-scale index of row (a_first, c=0)
   int64_t b_scoff;     // mixed path: row-scale index of row (0, 0) of block (GP, Gb)
 };
@@ -108,16 +108,17 @@ struct DressJob {
   int64_t t1_off;            // t1 block Ge: [m][e]
 };
 
-// Slicing of one operand block (mixed path): rows of length K = halves * np
-// (the Lambda stack has two halves), written as Kp = halves * roundup(np, 16)
-// padded K, 4 BF16 slices per element.
+// Slicing of one operand block (split paths): rows of length K = halves * np
+// (the Lambda stack has two halves), written as Kp = halves * roundup(np, kb)
+// padded K, four slices per element: BF16 (kb = 16, 8 bytes per element) or
+// 8-bit digits (kb = 32, 4 bytes per element).
 struct SliceJob {
   int32_t sys, rows, np, halves;
   int32_t Kp;
   int32_t dress;       // 1: rows of the Lambda stack built here from B, L and t1 (no U)
   int32_t ve, om;      // dress: rows are (a, e), e fastest; om = occupied count of irrep Ge
   int64_t src_off;     // element offset of row 0 in the operand (dress == 0)
-  int64_t dst_off;     // uint16 offset of row 0 in the slice buffer
+  int64_t dst_off;     // byte offset of row 0 in the slice buffer
   int64_t scale_off;   // row-scale index of row 0
   int64_t b_off;       // dress: B block (GP, Ge), [e][a][P]
   int64_t bvo_off;     // dress: L block (GP, Ga), [a][m][P]

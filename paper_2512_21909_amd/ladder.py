@@ -10,7 +10,7 @@ import numpy as np
 from . import _lib
 from .layout import Layout
 
-_PREC = {"fp64": _lib.FP64, "mixed": _lib.MIXED}
+_PREC = {"fp64": _lib.FP64, "mixed": _lib.MIXED, "mixed_i8": _lib.MIXED_I8}
 
 
 def _torch():

@@ -284,7 +284,7 @@ def measure(precision="fp64", n_requests=300, load=0.7, n_streams=3, max_batch=1
 
 def main():
     ap = argparse.ArgumentParser(description="serving loop of the ladder library")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_i8"])
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--streams", type=int, default=3)

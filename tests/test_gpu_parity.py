@@ -163,12 +163,16 @@ def _pair_energy_err(d, prob, ref):
     return float(np.max(np.abs(e_got - e_ref)))
 
 
+SPLIT = ["mixed", "mixed_i8"]   # split-BF16 slices; 8-bit digits with int32 accumulation
+
+
 @pytest.mark.parametrize("name,spec", SMALL)
 @pytest.mark.parametrize("kind", ["t2", "lambda"])
-def test_mixed_small(gpu_lib, name, spec, kind):
+@pytest.mark.parametrize("precision", SPLIT)
+def test_mixed_small(gpu_lib, name, spec, kind, precision):
     prob = problem(S.sym_custom(*spec), seed=9, kind=kind, symmetric_B=False)
     d = device_problem(gpu_lib, prob, want_energy=True)
-    run(gpu_lib, d, kind=kind, precision="mixed")
+    run(gpu_lib, d, kind=kind, precision=precision)
     ref = oracle_result(prob)
     _check(blocks(d), ref, MIXED_TOL, name)
     assert _pair_energy_err(d, prob, ref) <= PAIR_TOL
@@ -176,29 +180,97 @@ def test_mixed_small(gpu_lib, name, spec, kind):
 
 @pytest.mark.parametrize("wl", ["c1_small", "d2h_medium_A", "d2h_medium_B"])
 @pytest.mark.parametrize("kind", ["t2", "lambda"])
-def test_mixed_named_workloads(gpu_lib, wl, kind):
+@pytest.mark.parametrize("precision", SPLIT)
+def test_mixed_named_workloads(gpu_lib, wl, kind, precision):
     sym = {"c1_small": S.sym_c1_small(), "d2h_medium_A": S.sym_d2h_medium("A"),
            "d2h_medium_B": S.sym_d2h_medium("B")}[wl]
     prob = problem(sym, seed=0, kind=kind)
     d = device_problem(gpu_lib, prob, want_energy=True)
-    run(gpu_lib, d, kind=kind, precision="mixed")
+    run(gpu_lib, d, kind=kind, precision=precision)
     ref = oracle_result(prob)
     mx, fro = _check(blocks(d), ref, MIXED_TOL, wl)
     err_e = _pair_energy_err(d, prob, ref)
-    print(f"{wl} {kind} mixed: max {mx:.2e} fro {fro:.2e} pair-energy {err_e:.2e} Eh")
+    print(f"{wl} {kind} {precision}: max {mx:.2e} fro {fro:.2e} pair-energy {err_e:.2e} Eh")
     assert err_e <= PAIR_TOL
 
 
-def test_mixed_batched_equal_alone(gpu_lib):
+@pytest.mark.parametrize("precision", SPLIT)
+def test_mixed_batched_equal_alone(gpu_lib, precision):
     syms = S.batch_syms(5, seed=2)
     probs = [problem(s, seed=k) for k, s in enumerate(syms)]
     ds = [device_problem(gpu_lib, p) for p in probs]
-    run(gpu_lib, ds, precision="mixed")
+    run(gpu_lib, ds, precision=precision)
     for p, d in zip(probs, ds):
         alone = device_problem(gpu_lib, p)
-        run(gpu_lib, alone, precision="mixed")
+        run(gpu_lib, alone, precision=precision)
         assert np.array_equal(alone["R"].cpu().numpy(), d["R"].cpu().numpy())
         _check(blocks(d), oracle_result(p), MIXED_TOL, str(p["sym"]))
+
+
+@pytest.mark.parametrize("precision", SPLIT)
+@pytest.mark.parametrize("kind", ["t2", "lambda"])
+def test_mixed_tile_classes_agree(gpu_lib, precision, kind):
+    """Every assembly tile class of a split path gives bitwise the same result
+    (classes change the tile decomposition, never an element's arithmetic)."""
+    prob = problem(S.sym_custom([3, 2], [21, 14], [50, 31]), seed=3, kind=kind)
+    d0 = device_problem(gpu_lib, prob)
+    run(gpu_lib, d0, kind=kind, precision=precision)
+    r0 = d0["R"].cpu().numpy()
+    _check(blocks(d0), oracle_result(prob), MIXED_TOL, precision)
+    for cls in (1, 2, 3, 4):
+        d = device_problem(gpu_lib, prob)
+        run(gpu_lib, d, kind=kind, precision=precision, tile_policy=cls)
+        assert np.array_equal(d["R"].cpu().numpy(), r0), cls
+
+
+@pytest.mark.parametrize("precision", SPLIT)
+@pytest.mark.parametrize("kind", ["t2", "lambda"])
+def test_mixed_long_cholesky_index(gpu_lib, precision, kind):
+    """More than 32736 stacked Cholesky vectors (T2: N = 33000; Lambda: the
+    dressed stack of 2 x 16500): the 8-bit path runs its K in segments (the
+    int32 accumulators are exact for 32736 K at a time), the BF16 path
+    flushes every 256 K."""
+    n = 33000 if kind == "t2" else 16500
+    prob = problem(S.sym_custom([2], [6], [n]), seed=5, kind=kind)
+    d = device_problem(gpu_lib, prob, want_energy=True)
+    run(gpu_lib, d, kind=kind, precision=precision)
+    ref = oracle_result(prob)
+    _check(blocks(d), ref, MIXED_TOL, f"{kind} N={n}")
+    assert _pair_energy_err(d, prob, ref) <= PAIR_TOL
+
+
+def _digit_edge_B(sym, seed):
+    """Cholesky vectors whose entries sit on the rounding edges of the 8-bit
+    digit expansion (x in units of 1/128 of the row scale): exact halves
+    (a tie, the next digit becomes -128), fractions that round the second
+    digit up to +128 (a carry into the first), and one entry per row just
+    below a power of two (the row scale moves up one binade)."""
+    rng = np.random.default_rng([seed, 4242])
+    out = {}
+    for (gP, ga), blk in S.make_B(sym, seed, True).items():
+        m0 = rng.integers(0, 127, size=blk.shape).astype(np.float64)
+        kind = rng.integers(0, 3, size=blk.shape)
+        frac = np.where(kind == 0, 0.5, np.where(kind == 1, 0.4990234375 + 2.0 ** -30, rng.random(blk.shape)))
+        x = (m0 + frac) / 128.0 * np.where(rng.random(blk.shape) < 0.5, -1.0, 1.0)
+        x = np.clip(x, -0.99, 0.99)
+        if x.shape[-1]:
+            x[..., 0] = 0.995 * np.sign(x[..., 0] + 0.5)
+        out[(gP, ga)] = x * 2.0 ** int(rng.integers(-3, 4))
+    return out
+
+
+@pytest.mark.parametrize("kind", ["t2", "lambda"])
+def test_mixed_i8_digit_edges(gpu_lib, kind):
+    """Rounding ties, digit carries and row maxima just below a power of two
+    in the operand: the 8-bit path stays within the mixed tolerance (its
+    expansion is exact to 2^-32 of the row scale)."""
+    sym = S.sym_custom([3, 2], [13, 9], [40, 23])
+    prob = problem(sym, seed=6, kind=kind, dressed=False)
+    prob["B"] = _digit_edge_B(sym, 6)
+    d = device_problem(gpu_lib, prob)
+    run(gpu_lib, d, kind=kind, precision="mixed_i8")
+    mx, fro = _check(blocks(d), oracle_result(prob), MIXED_TOL, kind)
+    assert mx <= 1e-8, mx
 
 
 def test_graph_replay_with_new_pointers(gpu_lib):
@@ -232,7 +304,7 @@ def test_graph_replay_with_new_pointers(gpu_lib):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
 def test_uneven_batch_of_64_systems(gpu_lib, precision):
     """64 systems (o in [5,20], v in [40,160], N = 7.5(o+v), 1/2/4/8 irreps
     with Dirichlet splits) in one batched call: every system matches its

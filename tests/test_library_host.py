@@ -155,6 +155,12 @@ def test_error_codes_before_device_work(lib):
     o = lib.Opts()
     o.precision = 7
     assert L.cdcc_ladder_t2(1, arr, ctypes.byref(o), None) == lib.EINVAL
+    o.precision, o.tile_policy = lib.FP64, 4      # class 4 exists only on the split paths
+    assert L.cdcc_ladder_t2(1, arr, ctypes.byref(o), None) == lib.EINVAL
+    o.tile_policy = 5
+    for prec in (lib.MIXED, lib.MIXED_I8):
+        o.precision = prec
+        assert L.cdcc_ladder_t2(1, arr, ctypes.byref(o), None) == lib.EINVAL
     assert L.cdcc_status_string(lib.ENOMEM).decode().startswith("device workspace")
 
 
@@ -201,9 +207,10 @@ def test_density_error_codes_before_device_work(lib):
     assert L.cdcc_vvvv_density(-1, None, None, None) == lib.EINVAL
     assert L.cdcc_vvvv_density(0, None, None, None) == lib.OK         # nothing to do
     o = lib.Opts()
-    o.precision = lib.MIXED
     arr[0].L = arr[0].X = arr[0].Y = arr[0].G = ctypes.c_void_p(0x1000)
-    assert L.cdcc_vvvv_density(1, arr, ctypes.byref(o), None) == lib.EUNSUPPORTED
+    for prec in (lib.MIXED, lib.MIXED_I8):
+        o.precision = prec
+        assert L.cdcc_vvvv_density(1, arr, ctypes.byref(o), None) == lib.EUNSUPPORTED
     assert L.cdcc_density_flops(None, None) == lib.EINVAL
 
 
@@ -268,9 +275,10 @@ def test_partial_error_codes_before_device_work(lib):
     assert L.cdcc_partial_contract(-1, None, None, None) == lib.EINVAL
     assert L.cdcc_partial_contract(0, None, None, None) == lib.OK         # nothing to do
     o = lib.Opts()
-    o.precision = lib.MIXED
     arr[0].lam = arr[0].tau = arr[0].M = ctypes.c_void_p(0x1000)
-    assert L.cdcc_partial_contract(1, arr, ctypes.byref(o), None) == lib.EUNSUPPORTED
+    for prec in (lib.MIXED, lib.MIXED_I8):
+        o.precision = prec
+        assert L.cdcc_partial_contract(1, arr, ctypes.byref(o), None) == lib.EUNSUPPORTED
     assert L.cdcc_partial_flops(None, None) == lib.EINVAL
     assert L.cdcc_vo_layout(None, None) == lib.EINVAL
 
