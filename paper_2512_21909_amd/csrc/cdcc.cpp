@@ -67,7 +67,8 @@ hipError_t launch_pm_gemm(const PmDesc *descs, const int4 *tiles, int ntiles, co
 hipError_t launch_cd_diag(const double *V, int64_t n, double *D, hipStream_t s);
 hipError_t launch_cd_gather_cols(const double *V, int64_t n, const int32_t *qrows, int nq, double *M, int ldm,
                                  hipStream_t s);
-hipError_t launch_cd_micro(const CdQ *q, int nq, const CdPtrs &P, int64_t nmax, CdState *st, double *dq,
+hipError_t launch_cd_micro(const int32_t *qr, const CdQList &QL, const CdPtrs &P, int64_t nmax, int nirrep,
+                           CdState *st, double *dq,
                            int qcap, int t0, int steps, hipStream_t s);
 hipError_t launch_cd_gemm_nt(const CdGemmBatch &B, hipStream_t s);
 hipError_t launch_cd_gather_metric(const double *V, int64_t n, const int32_t *piv, int np, double *K, double *Y,
@@ -1666,7 +1667,7 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
   const int h = mat->nirrep;
   for (int g = 0; g < h; ++g)
     if (mat->n[g] > 0 && !piv_out[g]) return CDCC_EINVAL;
-  // device buffers: per irrep D, inP, L1 (n x n), M (n x qcap), piv; shared Q list, qrows, state
+  // device buffers: per irrep D, inP, L1 (n x n), M (n x qcap), piv; shared qrows, states, diagonals
   int64_t off[8][6], tot = 0, ntot = 0, nmax = 0;
   CdPtrs P{};
   for (int g = 0; g < h; ++g) {
@@ -1688,8 +1689,6 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
     off[g][5] = tot;
     tot = align_up(tot + n * 4);
   }
-  const int64_t o_q = tot;
-  tot = align_up(tot + int64_t(qmax) * sizeof(CdQ));
   const int64_t o_qr = tot;
   tot = align_up(tot + int64_t(qmax) * 4);
   const int64_t o_st = tot;
@@ -1707,7 +1706,6 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
     P.piv[g] = reinterpret_cast<int32_t *>(base + off[g][4]);
     P.qpos[g] = reinterpret_cast<int32_t *>(base + off[g][5]);
   }
-  CdQ *dq = reinterpret_cast<CdQ *>(base + o_q);
   int32_t *dqr = reinterpret_cast<int32_t *>(base + o_qr);
   CdState *dst = reinterpret_cast<CdState *>(base + o_st);  // two states, alternating per step
   double *ddq = reinterpret_cast<double *>(base + o_dq);     // two copies of the qualified diagonals
@@ -1717,7 +1715,7 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
   if ((rc = hP.alloc(size_t(ntot))) != CDCC_OK) return rc;
   if ((rc = hQ.alloc(size_t(qmax) * sizeof(CdQ))) != CDCC_OK) return rc;
   if ((rc = hQr.alloc(size_t(qmax) * 4)) != CDCC_OK) return rc;
-  if ((rc = hSt.alloc(sizeof(CdState))) != CDCC_OK) return rc;
+  if ((rc = hSt.alloc(2 * sizeof(CdState))) != CDCC_OK) return rc;
   if ((rc = hPos.alloc(size_t(ntot) * 4)) != CDCC_OK) return rc;
   if ((rc = hDq.alloc(size_t(qmax) * 8)) != CDCC_OK) return rc;
   double *Dh = static_cast<double *>(hD.p);
@@ -1781,18 +1779,26 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
       const int slot = fill[g]++;
       Qh[e] = CdQ{g, r, slot, 0};
       Qrh[qbeg[g] + slot] = r;
-      Posh[goff[g] + r] = e;
-      Dqh[e] = Dh[goff[g] + r];
+      Posh[goff[g] + r] = slot;
+      Dqh[qbeg[g] + slot] = Dh[goff[g] + r];
     }
-    *Sh = CdState{};
+    CdQList QL{};
+    int maxq = 0;
     for (int g = 0; g < h; ++g) {
-      Sh->k[g] = k[g];
-      Sh->k0[g] = k[g];
+      QL.beg[g] = qbeg[g];
+      QL.cnt[g] = nqg[g];
+      maxq = std::max(maxq, nqg[g]);
     }
-    Sh->tau_mic = std::max(tau, sigma * dmax);
-    HIPCHK(hipMemcpyAsync(dq, Qh, size_t(nq) * sizeof(CdQ), hipMemcpyHostToDevice, stream));
+    // both state records start equal (k0 and tau_mic stay fixed in both)
+    Sh[0] = CdState{};
+    for (int g = 0; g < h; ++g) {
+      Sh[0].k[g] = k[g];
+      Sh[0].k0[g] = k[g];
+    }
+    Sh[0].tau_mic = std::max(tau, sigma * dmax);
+    Sh[1] = Sh[0];
     HIPCHK(hipMemcpyAsync(dqr, Qrh, size_t(nq) * 4, hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemcpyAsync(dst, Sh, sizeof(CdState), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(dst, Sh, 2 * sizeof(CdState), hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(ddq, Dqh, size_t(nq) * 8, hipMemcpyHostToDevice, stream));
     for (int g = 0; g < h; ++g)
       if (mat->n[g] > 0)
@@ -1820,23 +1826,28 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
       }
       HIPCHK(launch_cd_gemm_nt(GB, stream));
     }
+    int nsteps = 0;
     {
-      // micro iterations, in chunks; the device ends them (done flag)
+      // micro iterations of all irreps side by side, in chunks; the device
+      // ends each irrep (done flags).  One more step than the longest
+      // irrep list: the last one marks that irrep done.
       Span sp(12, 1, stream);
-      // one more step than qualified pairs: the last one marks the state done
-      for (int launched = 0; launched <= nq;) {
-        const int c = std::min(kCdChunk, nq + 1 - launched);
-        HIPCHK(launch_cd_micro(dq, nq, P, nmax, dst, ddq, qmax, launched, c, stream));
+      for (int launched = 0; launched <= maxq;) {
+        const int c = std::min(kCdChunk, maxq + 1 - launched);
+        HIPCHK(launch_cd_micro(dqr, QL, P, nmax, h, dst, ddq, qmax, launched, c, stream));
         launched += c;
         HIPCHK(hipMemcpyAsync(Sh, dst + (launched & 1), sizeof(CdState), hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        if (Sh->done) break;
+        bool done = true;
+        for (int g = 0; g < h; ++g) done = done && Sh->gdone[g] != 0;
+        if (done) break;
       }
+      for (int g = 0; g < h; ++g) nsteps += Sh->steps[g];
     }
     if ((rc = pull_D()) != CDCC_OK) return rc;
     for (int e = 0; e < nq; ++e) Posh[goff[Qh[e].g] + Qh[e].r] = -1;
     for (int g = 0; g < h; ++g) k[g] = Sh->k[g];
-    if (Sh->steps == 0) return CDCC_EDEVICE;  // cannot happen: the largest qualified diagonal always pivots
+    if (nsteps == 0) return CDCC_EDEVICE;  // cannot happen: the largest qualified diagonal always pivots
     for (int64_t i = 0; i < ntot; ++i)
       if (Ph[i] && !(Dh[i] >= tau)) Ph[i] = 0;
     if ((rc = push_P()) != CDCC_OK) return rc;

@@ -50,95 +50,90 @@ __global__ __launch_bounds__(256) void cd_gather_cols_kernel(const double *__res
   M[r * ldm + s] = V[r * n + qrows[s]];
 }
 
-// One micro iteration, fused: every workgroup finds the pivot (the first
-// largest diagonal over the qualified list, from this step's copy dq_in of
-// the qualified diagonals, which no workgroup writes during the step), and
-// the workgroups together compute the new vector over the rows of the
-// pivot's irrep, 16 lanes per row (partial dot products over the vectors of
-// this macro iteration, combined by shuffles): L_r = (M[r][slot] -
-// sum_mic L1[r] L1[q]) / sqrt(d), Diag(r) -= L_r^2 (the pivot's own diagonal
-// set to 0).  The next step's qualified diagonals go to dq_out and the next
-// state to st[par ^ 1]; workgroup 0 writes the state and the pivot.  A value
-// below tau_mic (or Q used up) marks the state done; later steps then only
-// carry the state forward.  The loads of a step form two dependent rounds:
-// state, diagonals and the qualified list; then the rows.
-__global__ __launch_bounds__(256) void cd_micro_kernel(const CdQ *__restrict__ q, int nq, CdPtrs P,
+// One micro iteration of every irrep, fused (grid.y = irrep g): every
+// workgroup of irrep g finds that irrep's pivot (the first largest diagonal
+// over g's qualified pairs in Q order, from this step's copy dq_in of the
+// qualified diagonals, which no workgroup writes during the step), and the
+// workgroups of g together compute the new vector over the rows of g, 16
+// lanes per row (partial dot products over the vectors of this macro
+// iteration, combined by shuffles): L_r = (M[r][slot] - sum_mic L1[r] L1[q])
+// / sqrt(d), Diag(r) -= L_r^2 (the pivot's own diagonal set to 0).  The next
+// step's qualified diagonals of g go to dq_out and g's fields of the next
+// state to st[par ^ 1]; workgroup 0 of g writes them and the pivot.  A
+// largest value below tau_mic (or g's list used up) ends irrep g; later steps
+// only carry its fields forward.  A step of g changes only g's diagonals, so
+// running the irreps side by side gives each irrep the pivot sequence of the
+// one-pivot-at-a-time loop.  The loads of a step form two dependent rounds:
+// state and diagonals; then the rows.
+__global__ __launch_bounds__(256) void cd_micro_kernel(const int32_t *__restrict__ qr, CdQList QL, CdPtrs P,
                                                        CdState *__restrict__ st, int par,
                                                        const double *__restrict__ dq_in,
                                                        double *__restrict__ dq_out) {
   __shared__ double wv[4];
   __shared__ int wi[4];
-  __shared__ CdQ wq[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const CdState S = st[par];
+  const int g = blockIdx.y;
+  const CdState *S = st + par;
   CdState *__restrict__ nx = st + (par ^ 1);
-  // pivot: first maximum in Q order (the entry travels with its value)
+  const int col = S->k[g], steps = S->steps[g];
+  const bool lead = blockIdx.x == 0 && tid == 0;
+  if (S->gdone[g]) {
+    if (lead) {
+      nx->k[g] = col;
+      nx->gdone[g] = 1;
+      nx->steps[g] = steps;
+    }
+    return;
+  }
+  const int beg = QL.beg[g], nqg = QL.cnt[g];
+  // pivot: first maximum in Q order among g's entries
   double best = -__builtin_huge_val();
-  int bi = nq;
-  CdQ bx{0, 0, 0, 0};
-  for (int e = tid; e < nq; e += 256) {
-    const double v = dq_in[e];
-    const CdQ x = q[e];
+  int bi = nqg;
+  for (int e = tid; e < nqg; e += 256) {
+    const double v = dq_in[beg + e];
     if (v > best) {
       best = v;
       bi = e;
-      bx = x;
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
     const double v2 = __shfl_xor(best, o);
     const int i2 = __shfl_xor(bi, o);
-    const int g2 = __shfl_xor(bx.g, o), r2 = __shfl_xor(bx.r, o), s2 = __shfl_xor(bx.slot, o);
     if (v2 > best || (v2 == best && i2 < bi)) {
       best = v2;
       bi = i2;
-      bx = CdQ{g2, r2, s2, 0};
     }
   }
   if (lane == 0) {
     wv[wave] = best;
     wi[wave] = bi;
-    wq[wave] = bx;
   }
   __syncthreads();
   best = wv[0];
   bi = wi[0];
-  bx = wq[0];
   for (int w = 1; w < 4; ++w)
     if (wv[w] > best || (wv[w] == best && wi[w] < bi)) {
       best = wv[w];
       bi = wi[w];
-      bx = wq[w];
     }
-  if (S.done || bi >= nq || !(best >= S.tau_mic) || S.steps >= nq) {
-    if (blockIdx.x == 0 && tid == 0) {
-      CdState T = S;
-      T.done = 1;
-      T.step_valid = 0;
-      *nx = T;
+  if (bi >= nqg || !(best >= S->tau_mic) || steps >= nqg) {
+    if (lead) {
+      nx->k[g] = col;
+      nx->gdone[g] = 1;
+      nx->steps[g] = steps;
     }
     return;
   }
-  const int g = bx.g, col = S.k[g], k0 = S.k0[g];
+  const int prow = qr[beg + bi];
+  const int k0 = S->k0[g];
   const int64_t n = P.n[g];
   const int nm = col - k0;
   double *__restrict__ L1 = P.L1[g];
-  if (blockIdx.x == 0) {
-    if (tid == 0) {
-      CdState T = S;
-      T.k[g] = col + 1;
-      T.steps = S.steps + 1;
-      T.cur_g = g;
-      T.cur_r = bx.r;
-      T.cur_slot = bx.slot;
-      T.cur_col = col;
-      T.cur_d = best;
-      T.step_valid = 1;
-      *nx = T;
-      P.piv[g][col] = bx.r;
-    }
-    for (int e = tid; e < nq; e += 256)  // entries of the other irreps carry over
-      if (q[e].g != g) dq_out[e] = dq_in[e];
+  if (lead) {
+    nx->k[g] = col + 1;
+    nx->gdone[g] = 0;
+    nx->steps[g] = steps + 1;
+    P.piv[g][col] = prow;
   }
   const int64_t r = (int64_t(blockIdx.x) * 256 + tid) >> 4;
   const int sub = tid & 15;
@@ -147,11 +142,11 @@ __global__ __launch_bounds__(256) void cd_micro_kernel(const CdQ *__restrict__ q
     if (sub == 0) L1[r * n + col] = 0.0;
     return;
   }
-  const double m = P.M[g][r * P.qcap[g] + bx.slot];
+  const double m = P.M[g][r * P.qcap[g] + bi];
   const double dr = P.D[g][r];
   const int e2 = P.qpos[g][r];
   const CDCC_GLOBAL double *lr = as_global(L1) + r * n + k0;
-  const CDCC_GLOBAL double *lq = as_global(L1) + int64_t(bx.r) * n + k0;
+  const CDCC_GLOBAL double *lq = as_global(L1) + int64_t(prow) * n + k0;
   double a = 0.0, b = 0.0;
   int i = sub;
   for (; i + 16 < nm; i += 32) {
@@ -167,9 +162,9 @@ __global__ __launch_bounds__(256) void cd_micro_kernel(const CdQ *__restrict__ q
   if (sub == 0) {
     const double v = (m - a) / sqrt(best);
     L1[r * n + col] = v;
-    const double dn = (r == bx.r) ? 0.0 : dr - v * v;
+    const double dn = (r == prow) ? 0.0 : dr - v * v;
     P.D[g][r] = dn;
-    if (e2 >= 0) dq_out[e2] = dn;
+    if (e2 >= 0) dq_out[beg + e2] = dn;
   }
 }
 
@@ -351,12 +346,12 @@ hipError_t launch_cd_gather_cols(const double *V, int64_t n, const int32_t *qrow
   return hipGetLastError();
 }
 
-hipError_t launch_cd_micro(const CdQ *q, int nq, const CdPtrs &P, int64_t nmax, CdState *st, double *dq,
-                           int qcap, int t0, int steps, hipStream_t s) {
-  const int grid = int((nmax * 16 + 255) / 256);
+hipError_t launch_cd_micro(const int32_t *qr, const CdQList &QL, const CdPtrs &P, int64_t nmax, int nirrep,
+                           CdState *st, double *dq, int qcap, int t0, int steps, hipStream_t s) {
+  const dim3 grid(unsigned(std::max<int64_t>((nmax * 16 + 255) / 256, 1)), unsigned(nirrep));
   for (int t = t0; t < t0 + steps; ++t) {
     const int par = t & 1;
-    cd_micro_kernel<<<std::max(grid, 1), 256, 0, s>>>(q, nq, P, st, par, dq + par * qcap, dq + (par ^ 1) * qcap);
+    cd_micro_kernel<<<grid, 256, 0, s>>>(qr, QL, P, st, par, dq + par * qcap, dq + (par ^ 1) * qcap);
   }
   return hipGetLastError();
 }

@@ -215,18 +215,28 @@ struct CdPtrs {
   double *L1[8];         // vectors so far, [r][p], ld n (capacity n vectors)
   double *M[8];          // residual columns of the qualified pairs, [r][slot], ld qcap
   int32_t *piv[8];       // pivots in the order chosen (capacity n)
-  int32_t *qpos[8];      // row -> entry of the qualified list, or -1
+  int32_t *qpos[8];      // row -> its slot in the irrep's part of the qualified list, or -1
   int64_t n[8];
   int32_t qcap[8];
 };
 
-// Device-side state of the micro iterations.
+// Device-side state of the micro iterations.  The irreps run their micro
+// iterations side by side (one step of every irrep per launch): a step of
+// irrep g changes only the diagonals of irrep g, so each irrep's pivot
+// sequence is the one of the sequential loop.
 struct CdState {
   int32_t k[8];          // vectors per irrep
   int32_t k0[8];         // first vector of the current macro iteration
-  int32_t done, step_valid, steps, pad0;
-  int32_t cur_g, cur_r, cur_slot, cur_col;
-  double cur_d, tau_mic;
+  int32_t gdone[8];      // irrep g has ended its micro iterations
+  int32_t steps[8];      // micro iterations of irrep g in this macro iteration
+  double tau_mic, pad0;
+};
+
+// Qualified list of one macro iteration, grouped by irrep: entries
+// [beg[g], beg[g] + cnt[g]) are the qualified pairs of irrep g in Q order
+// (slot s of irrep g is entry beg[g] + s).
+struct CdQList {
+  int32_t beg[8], cnt[8];
 };
 
 // C[m][n] = beta C[m][n] + alpha sum_k A[arow(m)][k] B[brow(n)][k].
