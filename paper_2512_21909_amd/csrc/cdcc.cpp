@@ -1654,7 +1654,7 @@ int validate_cd_matrix(const cdcc_cd_matrix_t *m) {
   return CDCC_OK;
 }
 
-constexpr int kCdChunk = 32;  // micro iterations launched between host checks
+constexpr int kCdChunk = 64;  // micro-iteration launches between host checks
 
 int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64_t *const piv_out[CDCC_MAX_IRREP],
                  int64_t npiv[CDCC_MAX_IRREP], hipStream_t stream) {
@@ -1768,8 +1768,10 @@ int run_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *prm, int64
     for (int g = 0; g < h; ++g)
       for (int64_t r = 0; r < mat->n[g]; ++r)
         if (Ph[goff[g] + r] && Dh[goff[g] + r] >= sigma * dmax) cand.emplace_back(-Dh[goff[g] + r], g, int(r));
-    std::sort(cand.begin(), cand.end());
+    // only the first qmax in (-D, irrep, index) order are kept, in order
     const int nq = int(std::min<size_t>(cand.size(), size_t(qmax)));
+    if (cand.size() > size_t(nq)) std::nth_element(cand.begin(), cand.begin() + nq, cand.end());
+    std::sort(cand.begin(), cand.begin() + nq);
     int nqg[8] = {0}, qbeg[8] = {0};
     for (int e = 0; e < nq; ++e) ++nqg[std::get<1>(cand[e])];
     for (int g = 1; g < h; ++g) qbeg[g] = qbeg[g - 1] + nqg[g - 1];
