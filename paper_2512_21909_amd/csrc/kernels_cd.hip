@@ -63,8 +63,11 @@ __global__ __launch_bounds__(256) void cd_gather_cols_kernel(const double *__res
 // largest value below tau_mic (or g's list used up) ends irrep g; later steps
 // only carry its fields forward.  A step of g changes only g's diagonals, so
 // running the irreps side by side gives each irrep the pivot sequence of the
-// one-pivot-at-a-time loop.  The loads of a step form two dependent rounds:
-// state and diagonals; then the rows.
+// one-pivot-at-a-time loop.  Everything a row needs that does not depend on
+// the pivot (membership, diagonal, slot and its first 256 entries of this
+// macro iteration's vectors) is loaded before the pivot search, so a step
+// has two dependent rounds of loads: state, diagonals and row data; then
+// the pivot's row and residual column.
 __global__ __launch_bounds__(256) void cd_micro_kernel(const int32_t *__restrict__ qr, CdQList QL, CdPtrs P,
                                                        CdState *__restrict__ st, int par,
                                                        const double *__restrict__ dq_in,
@@ -86,6 +89,28 @@ __global__ __launch_bounds__(256) void cd_micro_kernel(const int32_t *__restrict
     return;
   }
   const int beg = QL.beg[g], nqg = QL.cnt[g];
+  const int k0 = S->k0[g];
+  const int64_t n = P.n[g];
+  const int nm = col - k0;
+  double *__restrict__ L1 = P.L1[g];
+  const int64_t r = (int64_t(blockIdx.x) * 256 + tid) >> 4;
+  const int sub = tid & 15;
+  const bool live = r < n;
+  // row data that does not depend on the pivot, in flight during the search
+  constexpr int kPre = 16;  // entries per lane held in registers (nm <= 256)
+  int inp = 0, e2 = -1;
+  double dr = 0.0, lrv[kPre];
+  const CDCC_GLOBAL double *lr = as_global(L1) + (live ? r : 0) * n + k0;
+  if (live) {
+    inp = P.inP[g][r];
+    dr = P.D[g][r];
+    e2 = P.qpos[g][r];
+  }
+#pragma unroll
+  for (int t = 0; t < kPre; ++t) {
+    const int i = sub + 16 * t;
+    lrv[t] = (live && i < nm) ? lr[i] : 0.0;
+  }
   // pivot: first maximum in Q order among g's entries
   double best = -__builtin_huge_val();
   int bi = nqg;
@@ -125,36 +150,26 @@ __global__ __launch_bounds__(256) void cd_micro_kernel(const int32_t *__restrict
     return;
   }
   const int prow = qr[beg + bi];
-  const int k0 = S->k0[g];
-  const int64_t n = P.n[g];
-  const int nm = col - k0;
-  double *__restrict__ L1 = P.L1[g];
   if (lead) {
     nx->k[g] = col + 1;
     nx->gdone[g] = 0;
     nx->steps[g] = steps + 1;
     P.piv[g][col] = prow;
   }
-  const int64_t r = (int64_t(blockIdx.x) * 256 + tid) >> 4;
-  const int sub = tid & 15;
-  if (r >= n) return;  // whole 16-lane groups leave together
-  if (!P.inP[g][r]) {
+  if (!live) return;  // whole 16-lane groups leave together
+  if (!inp) {
     if (sub == 0) L1[r * n + col] = 0.0;
     return;
   }
   const double m = P.M[g][r * P.qcap[g] + bi];
-  const double dr = P.D[g][r];
-  const int e2 = P.qpos[g][r];
-  const CDCC_GLOBAL double *lr = as_global(L1) + r * n + k0;
   const CDCC_GLOBAL double *lq = as_global(L1) + int64_t(prow) * n + k0;
-  double a = 0.0, b = 0.0;
-  int i = sub;
-  for (; i + 16 < nm; i += 32) {
-    a += lr[i] * lq[i];
-    b += lr[i + 16] * lq[i + 16];
+  double a = 0.0;
+#pragma unroll
+  for (int t = 0; t < kPre; ++t) {
+    const int i = sub + 16 * t;
+    a += lrv[t] * (i < nm ? lq[i] : 0.0);
   }
-  if (i < nm) a += lr[i] * lq[i];
-  a += b;
+  for (int i = sub + 16 * kPre; i < nm; i += 16) a += lr[i] * lq[i];
   a += __shfl_xor(a, 8);
   a += __shfl_xor(a, 4);
   a += __shfl_xor(a, 2);
