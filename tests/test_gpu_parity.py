@@ -273,7 +273,8 @@ def test_mixed_i8_digit_edges(gpu_lib, kind):
     assert mx <= 1e-8, mx
 
 
-def test_graph_replay_with_new_pointers(gpu_lib):
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
+def test_graph_replay_with_new_pointers(gpu_lib, precision):
     """The captured launch sequence is replayed for new buffers of the same
     shape: alternating calls on two inputs give each input's own result, and
     the graph path equals the direct launches bitwise."""
@@ -283,12 +284,13 @@ def test_graph_replay_with_new_pointers(gpu_lib):
     probs = [problem(sym, seed=s) for s in (21, 22)]
     ds = [device_problem(gpu_lib, p, want_energy=True) for p in probs]
     refs = [oracle_result(p) for p in probs]
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
     first = []
     for rep in range(3):
         for d, ref in zip(ds, refs):
             d["R"].fill_(float("nan"))
-            run(gpu_lib, d)
-            _check(blocks(d), ref, FP64_TOL, f"replay {rep}")
+            run(gpu_lib, d, precision=precision)
+            _check(blocks(d), ref, tol, f"replay {rep}")
             if rep == 0:
                 first.append(d["R"].cpu().numpy().copy())
             else:
@@ -297,7 +299,7 @@ def test_graph_replay_with_new_pointers(gpu_lib):
     try:
         for d, f in zip(ds, first):
             d["R"].fill_(float("nan"))
-            run(gpu_lib, d)
+            run(gpu_lib, d, precision=precision)
             assert np.array_equal(d["R"].cpu().numpy(), f)
     finally:
         del os.environ["CDCC_GRAPH"]
