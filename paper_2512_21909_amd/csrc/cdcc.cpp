@@ -712,14 +712,19 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
       R.g.tiles_n = tn;
       R.g.part_off = po;
       if (R.g.n_ij > 0 && R.g.ncols > 0) {
-        for (int a = 0; a < tm; ++a)
-          for (int b = 0; b < tn; ++b) {
-            for (int ks = 0; ks < R.g.nsplit; ++ks) {
+        // the row tiles of one column block and K segment read the same X
+        // columns: listed next to each other they land in one chunk of one
+        // XCD's queue and run together, so X comes from that XCD's L2 once
+        // instead of from HBM once per row tile
+        for (int b = 0; b < tn; ++b)
+          for (int ks = 0; ks < R.g.nsplit; ++ks)
+            for (int a = 0; a < tm; ++a) {
               const int len = std::min(R.g.kseg, R.g.ktab_len - ks * R.g.kseg);
               t2[0].push_back({int64_t(len) * R.g.fm + 1, Tile{gid, a, b, ks}});
             }
-            if (R.g.nsplit > 1) redjobs.push_back(Tile{gid, a, b, 0});
-          }
+        if (R.g.nsplit > 1)
+          for (int a = 0; a < tm; ++a)
+            for (int b = 0; b < tn; ++b) redjobs.push_back(Tile{gid, a, b, 0});
         if (R.g.nsplit > 1) po += int64_t(tm) * tn * R.g.nsplit * 2 * bm2 * kP2BN;
       }
       p2.push_back(R.g);
@@ -756,7 +761,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     for (int c = 0; c < 4; ++c)
       emit(t1[c], st_chunk[c], c, mixedp ? occupancy_mixed(split_fmt(P.precision), c) : occupancy_f64(0, c), p1tiles,
            B.p1);
-    emit(t2[0], 8, 0, occupancy_f64(1, 0), p2tiles, B.p2);
+    emit(t2[0], 12, 0, occupancy_f64(1, 0), p2tiles, B.p2);  // 12: whole column blocks of 1-4 or 6 row tiles
     if (P.precision == CDCC_MIXED_I8)
       for (Launch &l : B.p1)
         for (int i = l.start; i < l.start + l.count; ++i)
