@@ -702,6 +702,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     int64_t po = 0;
     Launch red;
     red.start = int(redjobs.size());
+    int max_tm = 1;  // most row tiles of one contraction column block in the batch
     for (size_t k = gi; k < gj; ++k) {
       GroupRec &R = groups[k];
       R.g.xoff = xo;
@@ -709,6 +710,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
       const int gid = int(p2.size());
       const int bm2 = 16 * R.g.fm;
       const int tm = (R.g.n_ij + bm2 - 1) / bm2, tn = (R.g.ncols + kP2BN - 1) / kP2BN;
+      max_tm = std::max(max_tm, tm);
       R.g.tiles_n = tn;
       R.g.part_off = po;
       if (R.g.n_ij > 0 && R.g.ncols > 0) {
@@ -761,7 +763,9 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     for (int c = 0; c < 4; ++c)
       emit(t1[c], st_chunk[c], c, mixedp ? occupancy_mixed(split_fmt(P.precision), c) : occupancy_f64(0, c), p1tiles,
            B.p1);
-    emit(t2[0], 12, 0, occupancy_f64(1, 0), p2tiles, B.p2);  // 12: whole column blocks of 1-4 or 6 row tiles
+    // chunks of whole column blocks (12 holds 1-4 or 6 row tiles); 8 where
+    // blocks have one or two (finer dealing balances the queues better)
+    emit(t2[0], max_tm > 2 ? 12 : 8, 0, occupancy_f64(1, 0), p2tiles, B.p2);
     if (P.precision == CDCC_MIXED_I8)
       for (Launch &l : B.p1)
         for (int i = l.start; i < l.start + l.count; ++i)

@@ -179,22 +179,30 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
       for (int t = 0; t < 4; ++t) *reinterpret_cast<unsigned *>(o + 32 * t) = w[t];
     }
   } else {
+    // four consecutive K per thread (Kh is a multiple of 16: never across
+    // halves), one 8-byte store per slice
     uint16_t *d16 = reinterpret_cast<uint16_t *>(dst);
-#pragma unroll 4
-    for (int kp = threadIdx.x; kp < J.Kp; kp += 256) {
-      const double y = elem(kp) * inv;
-      const double s0 = rint(y * 256.0) * (1.0 / 256.0);
-      double r = y - s0;
-      const double s1 = rint(r * 65536.0) * (1.0 / 65536.0);
-      r -= s1;
-      const double s2 = rint(r * 16777216.0) * (1.0 / 16777216.0);
-      r -= s2;
-      const double s3 = rint(r * 4294967296.0) * (1.0 / 4294967296.0);
-      uint16_t *o = d16 + (kp >> 4) * 64 + (kp & 15);
-      o[0] = bf16_bits_exact(s0);
-      o[16] = bf16_bits_exact(s1);
-      o[32] = bf16_bits_exact(s2);
-      o[48] = bf16_bits_exact(s3);
+#pragma unroll 2
+    for (int k4 = threadIdx.x * 4; k4 < J.Kp; k4 += 1024) {
+      unsigned long long w[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double y = elem(k4 + q) * inv;
+        const double s0 = rint(y * 256.0) * (1.0 / 256.0);
+        double r = y - s0;
+        const double s1 = rint(r * 65536.0) * (1.0 / 65536.0);
+        r -= s1;
+        const double s2 = rint(r * 16777216.0) * (1.0 / 16777216.0);
+        r -= s2;
+        const double s3 = rint(r * 4294967296.0) * (1.0 / 4294967296.0);
+        w[0] |= (unsigned long long)bf16_bits_exact(s0) << (16 * q);
+        w[1] |= (unsigned long long)bf16_bits_exact(s1) << (16 * q);
+        w[2] |= (unsigned long long)bf16_bits_exact(s2) << (16 * q);
+        w[3] |= (unsigned long long)bf16_bits_exact(s3) << (16 * q);
+      }
+      uint16_t *o = d16 + (k4 >> 4) * 64 + (k4 & 15);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) *reinterpret_cast<unsigned long long *>(o + 16 * t) = w[t];
     }
   }
 }
