@@ -34,7 +34,7 @@ def _alone(cdcc, req, precision):
     return R.cpu().numpy(), E.cpu().numpy()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
 def test_results_identical_alone_and_in_the_mix(gpu_lib, precision):
     import torch
     from paper_2512_21909_amd import serve
