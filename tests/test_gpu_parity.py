@@ -239,6 +239,24 @@ def test_mixed_long_cholesky_index(gpu_lib, precision, kind):
     assert _pair_energy_err(d, prob, ref) <= PAIR_TOL
 
 
+@pytest.mark.parametrize("spec", [([17], [24], [60]), ([23], [56], [40])])
+@pytest.mark.parametrize("kind", ["t2", "lambda"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
+def test_many_contraction_row_tiles(gpu_lib, spec, kind, precision):
+    """More than 128 packed occupied pairs in C1 (o=17: 153 rows in three
+    64-row contraction tiles per column block; o=23, v=56: 276 rows in six
+    48-row tiles and the K table split in two segments), so the row tiles of
+    a column block are listed together and share X.  Every element against
+    the oracle."""
+    prob = problem(S.sym_custom(*spec), seed=13, kind=kind)
+    d = device_problem(gpu_lib, prob, want_energy=True)
+    run(gpu_lib, d, kind=kind, precision=precision)
+    ref = oracle_result(prob)
+    _check(blocks(d), ref, FP64_TOL if precision == "fp64" else MIXED_TOL, f"{spec} {kind}")
+    if precision != "fp64":
+        assert _pair_energy_err(d, prob, ref) <= PAIR_TOL
+
+
 def _digit_edge_B(sym, seed):
     """Cholesky vectors whose entries sit on the rounding edges of the 8-bit
     digit expansion (x in units of 1/128 of the row scale): exact halves
