@@ -140,7 +140,9 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
     const double f = frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)  =>  |x| < 2^e
     if (I8 && f >= 253.0 / 256.0) ++e;  // keeps |128 x / sigma| < 126.5
   }
-  const double sigma = ldexp(1.0, e), inv = ldexp(1.0, -e);
+  // x / sigma as ldexp(x, -e): exact, and finite even when the row maximum
+  // is subnormal (2^-e itself would overflow there)
+  const double sigma = ldexp(1.0, e);
   if (threadIdx.x == 0) S.rowscale[J.scale_off + row] = sigma;
   const int Kh = J.Kp / J.halves;
   unsigned char *__restrict__ dst = S.slices + J.dst_off + int64_t(row) * J.Kp * (I8 ? 4 : 8);
@@ -151,13 +153,12 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
   };
   if constexpr (I8) {
     // four consecutive K per thread (Kh is a multiple of 32: never across halves)
-    const double inv128 = inv * 128.0;
 #pragma unroll 2
     for (int k4 = threadIdx.x * 4; k4 < J.Kp; k4 += 1024) {
       unsigned w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        double v = elem(k4 + q) * inv128;  // |v| < 126.5
+        double v = ldexp(elem(k4 + q), 7 - e);  // 128 x / sigma, |v| < 126.5
         int m[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
       unsigned long long w[4] = {0ull, 0ull, 0ull, 0ull};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const double y = elem(k4 + q) * inv;
+        const double y = ldexp(elem(k4 + q), -e);
         const double s0 = rint(y * 256.0) * (1.0 / 256.0);
         double r = y - s0;
         const double s1 = rint(r * 65536.0) * (1.0 / 65536.0);

@@ -257,6 +257,26 @@ def test_many_contraction_row_tiles(gpu_lib, spec, kind, precision):
         assert _pair_energy_err(d, prob, ref) <= PAIR_TOL
 
 
+@pytest.mark.parametrize("precision", SPLIT)
+@pytest.mark.parametrize("kind", ["t2", "lambda"])
+def test_split_paths_rows_of_subnormal_magnitude(gpu_lib, precision, kind):
+    """Operand rows whose largest entry is subnormal (the row scale 2^e is
+    then below 2^-1022): the slicing scales by ldexp, so the result stays
+    finite and within the tolerance of the FP64 oracle."""
+    sym = S.sym_custom([3, 2], [13, 9], [40, 23])
+    prob = problem(sym, seed=14, kind=kind, dressed=False)
+    B = {k: v.copy() for k, v in prob["B"].items()}
+    for blk in B.values():
+        if blk.shape[0] and blk.shape[1]:
+            blk[0, :, :] *= 2.0 ** -1060      # every entry of these rows subnormal
+    prob["B"] = B
+    d = device_problem(gpu_lib, prob)
+    run(gpu_lib, d, kind=kind, precision=precision)
+    got = d["R"].cpu().numpy()
+    assert np.all(np.isfinite(got))
+    _check(blocks(d), oracle_result(prob), MIXED_TOL, kind)
+
+
 def _digit_edge_B(sym, seed):
     """Cholesky vectors whose entries sit on the rounding edges of the 8-bit
     digit expansion (x in units of 1/128 of the row scale): exact halves
