@@ -24,10 +24,10 @@
 // Products of two digits are at most 2^14, so MFMA i32 32x32x32 accumulates
 // them exactly; the products of one weight t + u = w share an int32
 // accumulator, exact for K <= 32736 (four products of weight 3 per K), and
-// longer K runs in segments whose FP64 results are added in order.  The Lambda stack's subtracted half
-// is handled by negating the accumulators (exact in int32) at its first K
-// block and the total at the end.  The accumulators are combined once, in
-// FP64: sum_w acc_w 2^-8w.
+// longer K runs in segments whose FP64 results are added in order.  The
+// Lambda stack's subtracted half is handled by negating the accumulators
+// (exact in int32) at its first K block and the total at the end.  The
+// accumulators are combined once per segment, in FP64: sum_w acc_w 2^-8w.
 //
 // The FP64 total is finally scaled by sigma_x sigma_y (exact).
 #include <hip/hip_runtime.h>
