@@ -95,3 +95,16 @@ def test_indefinite_metric_is_rejected(gpu_lib):
     dV = _dev([np.array([[1.0, 2.0], [2.0, 1.0]])])
     with pytest.raises(CdccError):
         _vectors(gpu_lib, dV, [np.array([0, 1], dtype=np.int64)])
+
+
+def test_irrep_screened_out_entirely(gpu_lib):
+    """An irrep whose every diagonal is below tau takes no pivot (its vector
+    matrix has no columns) while the others decompose as usual; and a matrix
+    screened out completely gives no pivots at all."""
+    V = S.make_cd_matrices([70, 40, 55, 30], seed=8, kappa=15.0)
+    V[1] = V[1] * 1e-9          # every diagonal of irrep 1 far below tau
+    piv = _check(gpu_lib, V, 1e-6, 1e-2, 64)
+    assert piv[1].size == 0 and all(p.size > 0 for g, p in enumerate(piv) if g != 1)
+    W = [v * 1e-12 for v in S.make_cd_matrices([20, 10], seed=9, kappa=5.0)]
+    piv = _check(gpu_lib, W, 1e-6, 1e-2, 64)
+    assert all(p.size == 0 for p in piv)
