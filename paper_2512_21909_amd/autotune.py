@@ -64,7 +64,7 @@ def time_classes(cdcc, dev_problem: dict, kind: str, precision: str, reps: int =
     return out
 
 
-def tune(syms: list[dict], kinds=("t2", "lambda"), precisions=("fp64", "mixed"), seed: int = 0,
+def tune(syms: list[dict], kinds=("t2", "lambda"), precisions=("fp64", "mixed", "mixed_i8"), seed: int = 0,
          table: dict | None = None, log=print) -> dict:
     import synth as S
     import paper_2512_21909_amd as cdcc
@@ -89,7 +89,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--workloads", default="c1_small,d2h_medium,d2h_medium_B,serving_large,batch64")
     ap.add_argument("--out", default=TABLE)
-    ap.add_argument("--precisions", default="fp64,mixed", help="paths to tune (the others keep their entries)")
+    ap.add_argument("--precisions", default="fp64,mixed,mixed_i8", help="paths to tune (the others keep their entries)")
     args = ap.parse_args()
     precs = tuple(p for p in args.precisions.split(",") if p)
     syms, kinds = [], {}
