@@ -326,9 +326,14 @@ __device__ __forceinline__ void unpack_store(const SysPtrs &S, const P2Group &g,
                                              const int4 *__restrict__ vvtab) {
   const int4 ij = ijtab[g.ij_off + m];
   const int4 ab = vvtab[g.col_off + n];
+  const bool oab = ab.x != ab.y, oij = ij.x != ij.y;
+  // On a column a = b, W(-) is X_cd^aa - X_dc^aa = 0 identically (both are
+  // sum_P B_ac^P B_ad^P).  The split-precision assemblies round the two
+  // operand orders differently, so the exact zero is restored here; this
+  // keeps R_ij^aa = R_ji^aa bitwise in every precision.
+  if (!oab) av = 0.0;
   const double pp = sv + av, pm = sv - av;
   const int64_t ld = g.ldr;
-  const bool oab = ab.x != ab.y, oij = ij.x != ij.y;
   double *__restrict__ R = S.R + g.r_off;
   R[int64_t(ij.x) * ld + ab.x] = pp;
   if (oab) R[int64_t(ij.x) * ld + ab.y] = pm;

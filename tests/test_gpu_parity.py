@@ -121,13 +121,17 @@ def test_repeatable_bitwise(gpu_lib):
     assert np.array_equal(r1, d["R"].cpu().numpy())
 
 
-def test_t2_d2h_large_sampled_fp64(gpu_lib):
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
+def test_t2_d2h_large_sampled(gpu_lib, precision):
     """o=40, v=400, 3000 vectors at full size: sampled elements against the
-    oracle's one-by-one evaluation, plus R_ij^ab = R_ji^ba everywhere."""
+    oracle's one-by-one evaluation (1e-12 for FP64, 1e-7 for the split
+    paths, relative to the largest element), plus R_ij^ab = R_ji^ba
+    bitwise at every sample (the a = b columns included, where the
+    antisymmetric part is zero by construction)."""
     prob = problem(S.sym_d2h_large(), seed=0)
     sym = prob["sym"]
     d = device_problem(gpu_lib, prob)
-    run(gpu_lib, d)
+    run(gpu_lib, d, precision=precision)
     lay = d["layout"]
     R = d["R"].cpu().numpy()
     assert np.all(np.isfinite(R))
@@ -148,7 +152,7 @@ def test_t2_d2h_large_sampled_fp64(gpu_lib):
         ref = O.element_t2(sym, prob["B"], prob["X"], I, J, A, Bg)
         worst = max(worst, abs(Rb[(G, gi, ga)][i, j, a, b] - ref) / scale)
         assert Rb[(G, gi, ga)][i, j, a, b] == Rb[(G, gj, gb)][j, i, b, a]
-    assert worst <= FP64_TOL, worst
+    assert worst <= (FP64_TOL if precision == "fp64" else 1e-7), worst
 
 
 # ---------------------------------------------------------------- mixed path
