@@ -170,6 +170,13 @@ def _pair_energy_err(d, prob, ref):
 SPLIT = ["mixed", "mixed_i8"]   # split-BF16 slices; 8-bit digits with int32 accumulation
 
 
+def _assert_pair_symmetric(sym, got):
+    """R_ij^ab = R_ji^ba bitwise over the whole tensor: one (S, A) pair gives
+    both elements, and A is exactly zero on the a = b columns."""
+    full = OracleLayout(sym).full_amp(got)
+    assert np.array_equal(full, full.transpose(1, 0, 3, 2))
+
+
 @pytest.mark.parametrize("name,spec", SMALL)
 @pytest.mark.parametrize("kind", ["t2", "lambda"])
 @pytest.mark.parametrize("precision", SPLIT)
@@ -178,7 +185,9 @@ def test_mixed_small(gpu_lib, name, spec, kind, precision):
     d = device_problem(gpu_lib, prob, want_energy=True)
     run(gpu_lib, d, kind=kind, precision=precision)
     ref = oracle_result(prob)
-    _check(blocks(d), ref, MIXED_TOL, name)
+    got = blocks(d)
+    _check(got, ref, MIXED_TOL, name)
+    _assert_pair_symmetric(prob["sym"], got)
     assert _pair_energy_err(d, prob, ref) <= PAIR_TOL
 
 
@@ -192,7 +201,9 @@ def test_mixed_named_workloads(gpu_lib, wl, kind, precision):
     d = device_problem(gpu_lib, prob, want_energy=True)
     run(gpu_lib, d, kind=kind, precision=precision)
     ref = oracle_result(prob)
-    mx, fro = _check(blocks(d), ref, MIXED_TOL, wl)
+    got = blocks(d)
+    mx, fro = _check(got, ref, MIXED_TOL, wl)
+    _assert_pair_symmetric(sym, got)
     err_e = _pair_energy_err(d, prob, ref)
     print(f"{wl} {kind} {precision}: max {mx:.2e} fro {fro:.2e} pair-energy {err_e:.2e} Eh")
     assert err_e <= PAIR_TOL
