@@ -84,6 +84,9 @@ constexpr int kI8SegBlocks = 1023;
 // Output per K block: BF16, 16 K x 4 slices x 2 bytes (slice t at bytes
 // [32t, 32t + 32)); I8, 32 K x 4 digits x 1 byte (digit t at [32t, 32t + 32)).
 // ---------------------------------------------------------------------------
+constexpr int kRowPer = 8;    // operand elements per thread in flight while a row is read
+constexpr int kDressPer = 4;  // the same for a dressed row (om + 1 loads each)
+
 template <bool STAGE, bool I8>
 __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__ jobs,
                                                     const int2 *__restrict__ rows,
@@ -111,23 +114,58 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
     } else {
       const CDCC_GLOBAL double *lam = as_global(S.Bvo) + J.bvo_off + int64_t(a) * J.om * J.np;
       const CDCC_GLOBAL double *t1e = as_global(S.t1) + J.t1_off + e;
-#pragma unroll 2
-      for (int P = threadIdx.x; P < J.np; P += 256) {
-        double tea = 0.0;
-        for (int m = 0; m < J.om; ++m) tea += t1e[int64_t(m) * J.ve] * lam[int64_t(m) * J.np + P];
-        const double u = bea[P] - tea;
-        srow[P] = u;
-        srow[J.np + P] = tea;
-        mx = fmax(mx, fmax(fabs(u), fabs(tea)));
+      // m outermost over chunks of kDressPer P per thread: the loads of one m
+      // are independent, so a chunk costs about om + 1 memory round trips;
+      // the sums still run over m in increasing order (P past the end reads
+      // a clamped address and is not stored)
+      for (int P0 = 0; P0 < J.np; P0 += 256 * kDressPer) {
+        int pc[kDressPer];
+        double tea[kDressPer], bv[kDressPer];
+#pragma unroll
+        for (int j = 0; j < kDressPer; ++j) {
+          const int P = P0 + 256 * j + int(threadIdx.x);
+          pc[j] = P < J.np ? P : J.np - 1;
+          bv[j] = bea[pc[j]];
+          tea[j] = 0.0;
+        }
+#pragma unroll 1
+        for (int m = 0; m < J.om; ++m) {
+          const double c = t1e[int64_t(m) * J.ve];
+          const CDCC_GLOBAL double *lm = lam + int64_t(m) * J.np;
+#pragma unroll
+          for (int j = 0; j < kDressPer; ++j) tea[j] += c * lm[pc[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kDressPer; ++j) {
+          const int P = P0 + 256 * j + int(threadIdx.x);
+          if (P < J.np) {
+            const double u = bv[j] - tea[j];
+            srow[P] = u;
+            srow[J.np + P] = tea[j];
+            mx = fmax(mx, fmax(fabs(u), fabs(tea[j])));
+          }
+        }
       }
     }
   } else {
     src = S.opnd + J.src_off + int64_t(row) * K;
-#pragma unroll 4
-    for (int k = threadIdx.x; k < K; k += 256) {
-      const double u = src[k];
-      if (STAGE) srow[k] = u;
-      mx = fmax(mx, fabs(u));
+    // kRowPer independent loads per thread in flight (clamped addresses past
+    // the end, not used)
+    for (int k0 = 0; k0 < K; k0 += 256 * kRowPer) {
+      double v[kRowPer];
+#pragma unroll
+      for (int j = 0; j < kRowPer; ++j) {
+        const int k = k0 + 256 * j + int(threadIdx.x);
+        v[j] = src[k < K ? k : K - 1];
+      }
+#pragma unroll
+      for (int j = 0; j < kRowPer; ++j) {
+        const int k = k0 + 256 * j + int(threadIdx.x);
+        if (k < K) {
+          if (STAGE) srow[k] = v[j];
+          mx = fmax(mx, fabs(v[j]));
+        }
+      }
     }
   }
   // row maximum: within each wave by shuffles, then across the four waves
