@@ -114,37 +114,12 @@ __global__ __launch_bounds__(256) void dress_kernel(const DressJob *__restrict__
   }
   const CDCC_GLOBAL double *lam = as_global(S.Bvo) + J.bvo_off + int64_t(a) * J.om * J.np;
   const CDCC_GLOBAL double *t1e = as_global(S.t1) + J.t1_off + e;
-  // m outermost over chunks of kDressPer P per thread: the loads of one m
-  // are independent of each other and of the running sums, so a chunk costs
-  // about om + 1 memory round trips instead of one per (P, m).  The sums
-  // still run over m in increasing order.  P past the end reads a clamped
-  // address and is not stored.
-  constexpr int kDressPer = 4;
-  for (int P0 = 0; P0 < J.np; P0 += 256 * kDressPer) {
-    int pc[kDressPer];
-    double tea[kDressPer], bv[kDressPer];
-#pragma unroll
-    for (int j = 0; j < kDressPer; ++j) {
-      const int P = P0 + 256 * j + int(threadIdx.x);
-      pc[j] = P < J.np ? P : J.np - 1;
-      bv[j] = bea[pc[j]];
-      tea[j] = 0.0;
-    }
-#pragma unroll 1
-    for (int m = 0; m < J.om; ++m) {
-      const double c = t1e[int64_t(m) * J.ve];
-      const CDCC_GLOBAL double *lm = lam + int64_t(m) * J.np;
-#pragma unroll
-      for (int j = 0; j < kDressPer; ++j) tea[j] += c * lm[pc[j]];
-    }
-#pragma unroll
-    for (int j = 0; j < kDressPer; ++j) {
-      const int P = P0 + 256 * j + int(threadIdx.x);
-      if (P < J.np) {
-        urow[P] = bv[j] - tea[j];
-        urow[J.np + P] = tea[j];
-      }
-    }
+#pragma unroll 2
+  for (int P = threadIdx.x; P < J.np; P += 256) {
+    double tea = 0.0;
+    for (int m = 0; m < J.om; ++m) tea += t1e[int64_t(m) * J.ve] * lam[int64_t(m) * J.np + P];
+    urow[P] = bea[P] - tea;
+    urow[J.np + P] = tea;
   }
 }
 
