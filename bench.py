@@ -43,7 +43,7 @@ HBM_PEAK = 8000.0  # GB/s
 # step; per (workload, path), for the kernels as committed (profiles/).  The
 # vvvv density and partial-contraction entries are the launch of their GEMM
 # kernel, counted the same way.
-TRAFFIC = {("d2h_medium", "mixed"): 3.459e9, ("d2h_medium", "fp64"): 2.034e9, ("d2h_medium", "mixed_i8"): 1.356e9,
+TRAFFIC = {("d2h_medium", "mixed"): 3.528e9, ("d2h_medium", "fp64"): 2.046e9, ("d2h_medium", "mixed_i8"): 1.345e9,
            ("d2h_large", "fp64"): 11.355e9, ("d2h_large", "mixed"): 10.819e9, ("d2h_large", "mixed_i8"): 6.694e9,
            ("vvvv_d2h_medium", "fp64"): 3.800e9,
            ("pm_d2h_medium", "fp64"): 0.277e9, ("pm_d2h_large", "fp64"): 7.494e9}
