@@ -282,14 +282,53 @@ def measure(precision="fp64", n_requests=300, load=0.7, n_streams=3, max_batch=1
             "n_streams": n_streams, "max_batch": max_batch, "hbm_budget_bytes": budget}
 
 
+def measure_sweep(precision="fp64", n_requests=2000, loads=(0.3, 0.5, 0.7, 0.9), n_streams=3, max_batch=16,
+                  seed=5, warmup=200, log=None):
+    """Warm-up (``warmup`` requests at t=0, at least two per pool shape, not
+    counted), saturation throughput of the mix, then one Poisson stream of
+    ``n_requests`` per entry of ``loads`` (a fraction of the saturation
+    rate).  ``log(str)`` is called after each measured run."""
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    budget = int(free * 0.6)
+    pool = request_pool(seed=seed)
+
+    def server():
+        return LadderServer(budget, n_streams, precision, max_batch)
+
+    server().serve(make_stream(pool, max(warmup, 2 * len(pool)), 0, seed + 1))
+    sat = latency_stats(server().serve(make_stream(pool, n_requests, 0.0, seed)))
+    if log:
+        log(f"{precision} saturation: {sat.get('requests_per_s', 0):.1f} requests/s")
+    out = {"precision": precision, "requests": n_requests, "warmup": warmup, "saturation": sat, "streams": [],
+           "n_streams": n_streams, "max_batch": max_batch, "hbm_budget_bytes": budget}
+    for load in loads:
+        rate = load * sat["requests_per_s"]
+        st = latency_stats(server().serve(make_stream(pool, n_requests, rate, seed)))
+        out["streams"].append({"load": load, "rate_hz": rate, **st})
+        if log:
+            log(f"{precision} load {load}: p50 {st.get('p50_ms', 0):.2f} ms, p99 {st.get('p99_ms', 0):.2f} ms")
+    return out
+
+
 def main():
+    import sys
     ap = argparse.ArgumentParser(description="serving loop of the ladder library")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_i8"])
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--load", type=float, default=0.7)
+    ap.add_argument("--loads", default=None,
+                    help="comma-separated loads: saturation once, then one Poisson stream per load")
+    ap.add_argument("--warmup", type=int, default=200, help="warm-up requests of a --loads sweep")
     ap.add_argument("--streams", type=int, default=3)
     args = ap.parse_args()
-    print(json.dumps(measure(args.precision, args.requests, args.load, args.streams)))
+    if args.loads:
+        loads = [float(x) for x in args.loads.split(",")]
+        res = measure_sweep(args.precision, args.requests, loads, args.streams, warmup=args.warmup,
+                            log=lambda m: print(m, file=sys.stderr, flush=True))
+    else:
+        res = measure(args.precision, args.requests, args.load, args.streams)
+    print(json.dumps(res))
 
 
 if __name__ == "__main__":

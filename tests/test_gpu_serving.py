@@ -89,3 +89,16 @@ def test_allocation_failure_fails_one_request_only(gpu_lib):
             assert r.status == "done", (k, r.status, r.error)
             Ra, _ = _alone(gpu_lib, r, "fp64")
             assert np.array_equal(r.R.cpu().numpy(), Ra)
+
+
+def test_load_sweep_reports_every_load(gpu_lib):
+    """The sweep measures saturation once and one Poisson stream per load;
+    every request of every run completes."""
+    from paper_2512_21909_amd import serve
+    out = serve.measure_sweep("mixed", n_requests=24, loads=(0.3, 0.9), warmup=4, max_batch=4)
+    assert out["saturation"]["done"] == 24 and out["saturation"]["requests_per_s"] > 0
+    assert [s["load"] for s in out["streams"]] == [0.3, 0.9]
+    for s in out["streams"]:
+        assert s["done"] == 24 and s["rejected"] == 0 and s["failed"] == 0
+        assert s["rate_hz"] == pytest.approx(s["load"] * out["saturation"]["requests_per_s"])
+        assert 0 < s["p50_ms"] <= s["p99_ms"]
