@@ -66,6 +66,10 @@ def workload(name):
         sym = S.sym_d2h_large()
         return ("d2h_large: 8 irreps, o=40, v=400, Ncd=3000 (even split); T2 ladder",
                 [("t2", [S.make_problem(sym, 0, "t2")])])
+    if name == "c1_large":
+        sym = S.sym_custom([40], [400], [3000])
+        return ("c1_large: 1 irrep, o=40, v=400, Ncd=3000 (the o=40 system without point-group symmetry); "
+                "T2 ladder", [("t2", [S.make_problem(sym, 0, "t2")])])
     if name == "batch64":
         syms = S.batch_syms(64, seed=0)
         return ("batch64: 64 uneven systems (o 5-20, v 40-160, Ncd 7.5(o+v), 1/2/4/8 irreps) in one batched "
@@ -214,7 +218,9 @@ def density_workload(name):
                                 "irrep)", S.sym_d2h_medium("A")),
             "vvvv_d2h_medium_B": ("vvvv density: 8 irreps, o=20, v=200, Ncd=1500 (even split)",
                                   S.sym_d2h_medium("B")),
-            "vvvv_c1_small": ("vvvv density: 1 irrep, o=8, v=40, Ncd=300", S.sym_c1_small())}
+            "vvvv_c1_small": ("vvvv density: 1 irrep, o=8, v=40, Ncd=300", S.sym_c1_small()),
+            "vvvv_c1_medium": ("vvvv density: 1 irrep, o=20, v=200, Ncd=1500 (the o=20 system without "
+                               "point-group symmetry)", S.sym_custom([20], [200], [1500]))}
     if name not in syms:
         raise SystemExit(f"unknown workload {name}")
     desc, sym = syms[name]
