@@ -171,15 +171,17 @@ def kernel_times(cdcc, dev, precision, steps):
     return cdcc.timing_read()
 
 
-def cpu_baseline(entries, flops_step, budget_s=12.0):
+def cpu_baseline(entries, flops_step, budget_s=12.0, budget_1t=6.0):
     """The FP64 oracle (NumPy + host BLAS) on the same workload, repeated for
     a bounded time on the host cores (whole steps while they fit the budget,
-    else the first problems of the first call)."""
+    else the first problems of the first call); then the same with the host
+    BLAS held to one thread, on a shorter budget."""
     import oracle as O
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count())
     except Exception:  # pragma: no cover
+        threadpool_limits = None
         cores = os.cpu_count()
 
     def run_one(kind, p):
@@ -189,24 +191,33 @@ def cpu_baseline(entries, flops_step, budget_s=12.0):
             O.lambda_ladder_blocks(p["sym"], p["B"], p["Bvo"], p["t1"], p["X"])
 
     from paper_2512_21909_amd import Layout
-    t0 = time.perf_counter()
-    done_flops, reps, items = 0.0, 0, 0
-    while time.perf_counter() - t0 < budget_s and reps < 50:
-        for kind, probs in entries:
-            for p in probs:
-                run_one(kind, p)
-                f = Layout(p["sym"]).flops(0 if kind == "t2" else 2)
-                done_flops += sum(f)
-                items += 1
-                if time.perf_counter() - t0 >= budget_s:
+
+    def timed(budget):
+        t0 = time.perf_counter()
+        done_flops, reps, items = 0.0, 0, 0
+        while time.perf_counter() - t0 < budget and reps < 50:
+            for kind, probs in entries:
+                for p in probs:
+                    run_one(kind, p)
+                    done_flops += sum(Layout(p["sym"]).flops(0 if kind == "t2" else 2))
+                    items += 1
+                    if time.perf_counter() - t0 >= budget:
+                        break
+                if time.perf_counter() - t0 >= budget:
                     break
-            if time.perf_counter() - t0 >= budget_s:
-                break
-        reps += 1
-    dt = time.perf_counter() - t0
-    return {"value": done_flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{items} ladder evaluations of this workload (symmetry-blocked plain FP64 contraction, "
-                      f"NumPy + host BLAS) in {dt:.1f} s; rate = their algorithmic flops / time"}
+            reps += 1
+        return done_flops, time.perf_counter() - t0, items
+
+    done_flops, dt, items = timed(budget_s)
+    out = {"value": done_flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{items} ladder evaluations of this workload (symmetry-blocked plain FP64 contraction, "
+                     f"NumPy + host BLAS) in {dt:.1f} s; rate = their algorithmic flops / time"}
+    if threadpool_limits is not None and budget_1t > 0:
+        with threadpool_limits(limits=1):
+            f1, d1, n1 = timed(budget_1t)
+        out["value_1_thread"] = f1 / d1 / 1e12
+        out["sample_1_thread"] = f"{n1} evaluations in {d1:.1f} s with the host BLAS on one thread"
+    return out
 
 
 DENSITY_METRIC = "vvvv two-body-density contraction with Cholesky vectors, TFLOP/s (FP64)"
