@@ -147,15 +147,22 @@ def accuracy(cdcc, dev, precision, samples=300):
 
 
 def timed(cdcc, dev, precision, steps, warmup):
+    """Mean seconds per step over the timed steps (host clock around the
+    whole loop), plus the per-step device times (ms) from events recorded on
+    the launch stream between the steps."""
     import torch
     for _ in range(warmup):
         step(cdcc, dev, precision)
     torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         step(cdcc, dev, precision)
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    sec = (time.perf_counter() - t0) / steps
+    return sec, [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
 
 
 def kernel_times(cdcc, dev, precision, steps):
@@ -584,13 +591,14 @@ def main():
         except cdcc.CdccError as e:
             print(f"[bench] {prec}: unavailable ({e})", file=sys.stderr, flush=True)
             continue
-        sec = timed(cdcc, dev, prec, args.steps, args.warmup)
+        sec, per_step = timed(cdcc, dev, prec, args.steps, args.warmup)
         kt = kernel_times(cdcc, dev, prec, args.steps)
         gate = 1e-12 if prec == "fp64" else 1e-7
         ok = acc is None or all(a["max_rel"] <= gate and a["fro_rel"] <= gate and
                                 (prec == "fp64" or a["pair_energy_abs"] <= 1e-8) for a in acc.values())
         results[prec] = {"ms_per_step": sec * 1e3, "tflops": flops_step / sec / 1e12, "accuracy": acc,
-                         "passes_gate": ok, "kernels": kt}
+                         "passes_gate": ok, "kernels": kt,
+                         "step_ms_median": float(np.median(per_step)), "step_ms_min": float(np.min(per_step))}
         print(f"[bench] {prec}: {sec * 1e3:.3f} ms/step, {flops_step / sec / 1e12:.2f} TFLOP/s, gate ok={ok}, "
               f"kernels={kt}", file=sys.stderr, flush=True)
 
