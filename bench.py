@@ -66,6 +66,10 @@ def workload(name):
         sym = S.sym_d2h_large()
         return ("d2h_large: 8 irreps, o=40, v=400, Ncd=3000 (even split); T2 ladder",
                 [("t2", [S.make_problem(sym, 0, "t2")])])
+    if name == "hbc_shape":
+        sym = S.sym_hbc_shape()
+        return ("hbc_shape: 8 irreps, o=135, v=543, Ncd=3710 (even split; the size of the paper's largest D2h "
+                "molecule); T2 ladder", [("t2", [S.make_problem(sym, 0, "t2")])])
     if name == "c1_large":
         sym = S.sym_custom([40], [400], [3000])
         return ("c1_large: 1 irrep, o=40, v=400, Ncd=3000 (the o=40 system without point-group symmetry); "

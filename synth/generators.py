@@ -50,7 +50,7 @@ import numpy as np
 
 __all__ = [
     "SPLIT_D2H", "largest_remainder_split", "sym_c1_small", "sym_d2h_medium",
-    "sym_d2h_large", "sym_serving_large", "sym_custom", "dirichlet_sym",
+    "sym_d2h_large", "sym_hbc_shape", "sym_serving_large", "sym_custom", "dirichlet_sym",
     "batch_syms", "make_eps", "make_B", "make_Bvo", "make_t1", "make_t2",
     "make_tau", "make_lambda", "make_problem", "make_density_problem", "make_lam_vo",
     "make_partial_problem", "make_cd_matrices", "irrep_pairs",
@@ -111,6 +111,15 @@ def sym_d2h_large() -> dict:
     return sym_custom(largest_remainder_split(40, SPLIT_D2H),
                       largest_remainder_split(400, SPLIT_D2H),
                       largest_remainder_split(3000, [1] * 8))
+
+
+def sym_hbc_shape() -> dict:
+    """The size of the paper's largest D2h test molecule (135 occupied, 543
+    virtual orbitals, 3710 Cholesky vectors), split over the 8 irreps like
+    the o=40 system (vectors evenly)."""
+    return sym_custom(largest_remainder_split(135, SPLIT_D2H),
+                      largest_remainder_split(543, SPLIT_D2H),
+                      largest_remainder_split(3710, [1] * 8))
 
 
 def sym_serving_large() -> dict:
