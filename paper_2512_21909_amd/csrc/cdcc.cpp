@@ -718,12 +718,26 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
         // columns: listed next to each other they land in one chunk of one
         // XCD's queue and run together, so X comes from that XCD's L2 once
         // instead of from HBM once per row tile
-        for (int b = 0; b < tn; ++b)
+        auto push = [&](int a, int b, int ks) {
+          const int len = std::min(R.g.kseg, R.g.ktab_len - ks * R.g.kseg);
+          t2[0].push_back({int64_t(len) * R.g.fm + 1, Tile{gid, a, b, ks}});
+        };
+        if (tm > 4) {
+          // many row tiles: a tile also reads 2x as many tauhat bytes (16 fm
+          // rows x 2 halves) as X bytes (32 columns x 2 rows), and tauhat is
+          // shared along a row of tiles, X along a column; a chunk of 3 row
+          // tiles x 4 column blocks of one K segment reads each once
+          constexpr int SA = 3, SB = 4;
           for (int ks = 0; ks < R.g.nsplit; ++ks)
-            for (int a = 0; a < tm; ++a) {
-              const int len = std::min(R.g.kseg, R.g.ktab_len - ks * R.g.kseg);
-              t2[0].push_back({int64_t(len) * R.g.fm + 1, Tile{gid, a, b, ks}});
-            }
+            for (int a0 = 0; a0 < tm; a0 += SA)
+              for (int b0 = 0; b0 < tn; b0 += SB)
+                for (int b = b0; b < std::min(tn, b0 + SB); ++b)
+                  for (int a = a0; a < std::min(tm, a0 + SA); ++a) push(a, b, ks);
+        } else {
+          for (int b = 0; b < tn; ++b)
+            for (int ks = 0; ks < R.g.nsplit; ++ks)
+              for (int a = 0; a < tm; ++a) push(a, b, ks);
+        }
         if (R.g.nsplit > 1)
           for (int a = 0; a < tm; ++a)
             for (int b = 0; b < tn; ++b) redjobs.push_back(Tile{gid, a, b, 0});

@@ -259,10 +259,10 @@ def test_mixed_long_cholesky_index(gpu_lib, precision, kind):
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
 def test_many_contraction_row_tiles(gpu_lib, spec, kind, precision):
     """More than 128 packed occupied pairs in C1 (o=17: 153 rows in three
-    64-row contraction tiles per column block; o=23, v=56: 276 rows in six
-    48-row tiles and the K table split in two segments), so the row tiles of
-    a column block are listed together and share X.  Every element against
-    the oracle."""
+    64-row contraction tiles per column block, listed together so that they
+    share X; o=23, v=56: 276 rows in six 48-row tiles and the K table split
+    in two segments, listed in blocks of 3 row tiles x 4 column blocks of
+    one segment, ragged at both edges).  Every element against the oracle."""
     prob = problem(S.sym_custom(*spec), seed=13, kind=kind)
     d = device_problem(gpu_lib, prob, want_energy=True)
     run(gpu_lib, d, kind=kind, precision=precision)
