@@ -595,11 +595,14 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           g.th_off = th_off[G];
           g.th_rs = int(align_up(n_ij, 16));
           g.r_off = L.amp_off[G];
-          g.nsplit = std::max(1, (kt_len + kKSeg / 2) / kKSeg);
+          g.fm = contract_fm(int(n_ij));
+          // groups with more than four row tiles have tiles enough to fill
+          // the chip with segments twice as long (half the split-K partials)
+          const int kseg_len = n_ij > 4 * 16 * g.fm ? 2 * kKSeg : kKSeg;
+          g.nsplit = std::max(1, (kt_len + kseg_len / 2) / kseg_len);
           g.kseg = ((kt_len + g.nsplit - 1) / g.nsplit + 15) / 16 * 16;
           if (g.nsplit > 1) g.nsplit = (kt_len + g.kseg - 1) / g.kseg;
           R.region = nrows * g.ldx;
-          g.fm = contract_fm(int(n_ij));
           // assembly GEMMs
           const int bm = mixed ? kMixBM[SP.p1cls] : kP1BM[SP.p1cls];
           for (int gc = 0; gc < h; ++gc) {

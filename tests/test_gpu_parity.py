@@ -254,15 +254,16 @@ def test_mixed_long_cholesky_index(gpu_lib, precision, kind):
     assert _pair_energy_err(d, prob, ref) <= PAIR_TOL
 
 
-@pytest.mark.parametrize("spec", [([17], [24], [60]), ([23], [56], [40])])
+@pytest.mark.parametrize("spec", [([17], [24], [60]), ([23], [80], [40])])
 @pytest.mark.parametrize("kind", ["t2", "lambda"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
 def test_many_contraction_row_tiles(gpu_lib, spec, kind, precision):
     """More than 128 packed occupied pairs in C1 (o=17: 153 rows in three
     64-row contraction tiles per column block, listed together so that they
-    share X; o=23, v=56: 276 rows in six 48-row tiles and the K table split
-    in two segments, listed in blocks of 3 row tiles x 4 column blocks of
-    one segment, ragged at both edges).  Every element against the oracle."""
+    share X; o=23, v=80: 276 rows in six 48-row tiles and the K table of
+    3240 entries split in two segments, listed in blocks of 3 row tiles x 4
+    column blocks of one segment, ragged at both edges).  Every element
+    against the oracle."""
     prob = problem(S.sym_custom(*spec), seed=13, kind=kind)
     d = device_problem(gpu_lib, prob, want_energy=True)
     run(gpu_lib, d, kind=kind, precision=precision)
