@@ -44,7 +44,7 @@ HBM_PEAK = 8000.0  # GB/s
 # vvvv density and partial-contraction entries are the launch of their GEMM
 # kernel, counted the same way.
 TRAFFIC = {("d2h_medium", "mixed"): 3.528e9, ("d2h_medium", "fp64"): 2.046e9, ("d2h_medium", "mixed_i8"): 1.345e9,
-           ("d2h_large", "fp64"): 11.355e9, ("d2h_large", "mixed"): 10.819e9, ("d2h_large", "mixed_i8"): 6.694e9,
+           ("d2h_large", "fp64"): 11.333e9, ("d2h_large", "mixed"): 10.771e9, ("d2h_large", "mixed_i8"): 6.690e9,
            ("vvvv_d2h_medium", "fp64"): 3.800e9,
            ("pm_d2h_medium", "fp64"): 0.277e9, ("pm_d2h_large", "fp64"): 7.494e9}
 
