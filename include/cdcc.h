@@ -157,15 +157,20 @@ int cdcc_ladder_lambda(int32_t nsys, const cdcc_problem_t *probs,
 /*
  * One vvvv two-body-density contraction (Appendix "CCSD two-body density
  * matrices": Gamma_AbCd = 1/2 P_+(ab,cd) V_AbCd, V_AbCd = sum_mn
- * tau~_Mn^Cd lambda_Ab^Mn; gradient section: Gamma^P_pr = sum_qs
- * Gamma_pqrs L~^P_qs, contracted on the fly), closed-shell spatial form:
+ * tau~_Mn^Cd lambda_Ab^Mn; section "CCSD density matrices": for an RHF
+ * reference the spin-adapted Gamma~_pqrs = 2 Gamma_PqRs - Gamma_PqSr;
+ * gradient section, eq. for Gamma^P_pr: Gamma^P_pr = sum_qs Gamma~_pqrs
+ * L~^P_qs, contracted on the fly), closed-shell spatial form with
+ * p = a, q = b, r = c, s = d:
  *
- *   G^P_ac = 1/2 sum_bd sum_mn [Y_mn^ab X_mn^cd + Y_mn^cd X_mn^ab] L^P_bd
+ *   V_abcd  = sum_mn Y_mn^ab X_mn^cd,   Gamma_abcd = 1/2 (V_abcd + V_cdab)
+ *   G^P_ac  = sum_bd (2 Gamma_abcd - Gamma_abdc) L^P_bd
  *
  * X = tau~ and Y = lambda in the amplitude layout (any values; the paper
- * leaves tau~ to the caller), L = the transformed Cholesky vectors L~^P_bd
- * and G = the result G^P_ac, both in the Cholesky-vector layout of B
- * (block (GP, Ga) = [a][c][P]).  G receives every stored element.
+ * leaves tau~ to the caller; no pair symmetry is assumed), L = the
+ * transformed Cholesky vectors L~^P_bd and G = the result G^P_ac, both in the
+ * Cholesky-vector layout of B (block (GP, Ga) = [a][c][P]).  G receives every
+ * stored element.
  */
 typedef struct {
   const cdcc_layout_t *lay;  /* host pointer, read during the call only        */

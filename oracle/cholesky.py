@@ -2,43 +2,48 @@
 semidefinite "two-electron integral" matrix, FP64, on the CPU (oracle, test
 infrastructure only).
 
-Paper (arXiv 2512.21909), section "Symmetry-adapted two-step CD algorithm",
-Algorithm 1 (first step: the Cholesky basis) and the equation for the
-vectors of the second step in the section on CD/DF integrals
-(``L^P_rs = sum_R K^-1_PR (R|rs)`` with ``K K^T`` the metric ``(Q|R)`` over
-the basis).  Here the integrals are given as dense per-irrep matrices
-``V[g]`` (rows and columns: the basis-function pairs of irrep g; pairs of
-different irreps do not couple, so the matrix is block diagonal), so
-"computing a shell quartet" is reading matrix entries and every pair is its
-own shell.
+Paper (arXiv 2512.21909): section "Symmetry-adapted two-step CD algorithm"
+(Algorithm 1: the Cholesky basis) and the CD/DF section's equation for the
+second-step vectors, ``L^P_rs = sum_R K^-1_PR (R|rs)`` with ``K K^T`` the
+metric ``(Q|R)`` over the basis.
 
-First step, in the paper's order and notation:
+What the first step computes, stated as a pivoted partial Cholesky
+factorisation with restricted pivot choice.  The integrals are dense
+per-irrep matrices ``V[g]`` (pairs of different irreps do not couple), so
+every pair is its own shell and "computing a shell quartet" is reading
+matrix entries.  The residual of irrep g after the vectors chosen so far is
+``R_g = V_g - sum_p l_p l_p^T``; its diagonal is the quantity every choice
+looks at.
 
-* P = pairs with Diag(r) = (r|r) >= tau, D = their diagonals;
-* while P is not empty:
-  - D_max = max over P; the qualified list Q = the (at most Q_max) largest
-    members of P with Diag >= sigma D_max (ties: lower irrep, then lower
-    index first);
-  - residual columns M~_rq = (r|q) - sum over the vectors L(G_q) of
-    L_r^p L_q^p for r in P of the irrep of q;
-  - micro iterations: while the largest Diag over Q is >= tau_mic, take it
-    as pivot q; for every r in P of the irrep of q,
-    L_r^q = (M~_rq - sum over this iteration's vectors of L_r^p L_q^p) /
-    sqrt(Diag(q)) and Diag(r) -= (L_r^q)^2; the vector joins L_mic(G_q);
-  - L(G) gains L_mic(G); pairs with Diag < tau leave P (their entries of
-    later vectors are zero).
+* A pair is *active* while its residual diagonal is at least tau (the
+  screening threshold); inactive pairs are zero in every later vector.
+* The factorisation proceeds in rounds.  A round fixes D_max (the largest
+  active residual diagonal over all irreps) and a candidate list: the at
+  most Q_max active pairs with the largest diagonals among those at least
+  sigma D_max (sigma: the span factor), ordered by diagonal, ties to the
+  lower irrep and then the lower index.
+* Within a round, pivots are taken from the candidate list only: each time
+  the candidate with the largest current residual diagonal (the first in
+  list order among equal ones), as long as that diagonal is at least the
+  round's threshold tau_mic.  Eliminating pivot q of irrep g adds the vector
+  ``l = R_g[:, q] / sqrt(R_g[q, q])`` (active rows only) and subtracts
+  ``l l^T`` from R_g; the pivot's own diagonal is then exactly zero.
+* After the round every pair whose diagonal fell below tau becomes inactive.
+  The factorisation ends when no pair is active.
 
-``tau_mic`` is not spelled out in the paper; it is read as
-``max(tau, sigma D_max)`` with the D_max of the current macro iteration
-(the span factor bounds both which diagonals qualify and how far the
-qualified ones are decomposed).  The pivot of a micro iteration is the
-first maximum in Q order.  After a pivot its own diagonal is set to zero.
+The paper does not spell out tau_mic; it is read as ``max(tau, sigma
+D_max)`` with the D_max of the round (the span factor bounds both which
+diagonals qualify and how far the qualified ones are decomposed).  Pinned in
+``tests/test_oracle_cd.py`` by a hand-worked five-pair matrix whose pivot
+order differs from greedy pivoting and from tau_mic = tau, by the Q_max = 1
+reduction to textbook greedy pivoting, by the decomposition error bound, by
+exact low rank and by invariance under reordering of the pairs.
 
 Second step: for each irrep, K = the lower Cholesky factor of the metric
 V[piv, piv] and L = K^-1 V[piv, :] (triangular solve), returned as the
 matrix ``L[r, P]`` (pair-major, vector index fastest).
 
-Library primitives: numpy matmul, numpy.linalg.cholesky and
+Library primitives: numpy outer products, numpy.linalg.cholesky and
 scipy.linalg.solve_triangular.
 """
 from __future__ import annotations
@@ -49,55 +54,49 @@ __all__ = ["cd_basis", "cd_vectors", "cd_tau_mic"]
 
 
 def cd_tau_mic(tau: float, sigma: float, dmax: float) -> float:
+    """Threshold of the pivots taken within one round."""
     return max(tau, sigma * dmax)
 
 
 def cd_basis(V: list, tau: float, sigma: float = 1e-2, qmax: int = 1000):
     """First step.  V: list of dense symmetric (n_g, n_g) matrices, one per
     irrep.  Returns (piv, diag): piv[g] = pivot indices of irrep g in the
-    order they were chosen; diag[g] = the final diagonals of the pairs still
-    in P (np.nan for pairs that left P, the diagonal at leaving time is
-    below tau)."""
+    order they were chosen; diag[g] = the final residual diagonals of the
+    pairs still active (np.nan for pairs that became inactive; their
+    diagonal was then below tau)."""
     h = len(V)
-    D = [np.array(np.diag(v), dtype=np.float64) for v in V]
-    inP = [d >= tau for d in D]
-    vecs = [np.zeros((v.shape[0], 0)) for v in V]      # L(G): rows r, one column per vector
+    R = [np.array(v, dtype=np.float64) for v in V]           # residual matrices
+    active = [np.diag(r) >= tau for r in R]
+    for g in range(h):                                       # screened pairs: zero rows and columns
+        R[g][~active[g], :] = 0.0
+        R[g][:, ~active[g]] = 0.0
     piv = [[] for _ in range(h)]
-    while any(m.any() for m in inP):
-        dmax = max(float(D[g][inP[g]].max()) for g in range(h) if inP[g].any())
-        cand = [(-D[g][r], g, r) for g in range(h) for r in np.nonzero(inP[g])[0]
-                if D[g][r] >= sigma * dmax]
-        cand.sort()
-        Q = [(g, int(r)) for _, g, r in cand[:qmax]]
-        # residual columns over P for every qualified pair
-        res = {}
-        for g, q in Q:
-            col = V[g][:, q] - vecs[g] @ vecs[g][q, :]
-            col[~inP[g]] = 0.0
-            res[(g, q)] = col
-        tmic = cd_tau_mic(tau, sigma, dmax)
-        mic = [np.zeros((V[g].shape[0], 0)) for g in range(h)]
+
+    def diag(g, r):
+        return R[g][r, r]
+
+    while any(a.any() for a in active):
+        dmax = max(float(np.diag(R[g])[active[g]].max()) for g in range(h) if active[g].any())
+        ranked = sorted(((-diag(g, r), g, int(r)) for g in range(h) for r in np.flatnonzero(active[g])
+                         if diag(g, r) >= sigma * dmax))
+        cands = [(g, r) for _, g, r in ranked[:qmax]]
+        thr = cd_tau_mic(tau, sigma, dmax)
         while True:
-            best, bq = -np.inf, None
-            for g, q in Q:               # first maximum in Q order
-                if D[g][q] > best:
-                    best, bq = D[g][q], (g, q)
-            if bq is None or best < tmic:
+            g, q = max(cands, key=lambda c: diag(*c))       # max() keeps the first of equal values
+            d = diag(g, q)
+            if d < thr:
                 break
-            g, q = bq
-            m = mic[g]
-            col = (res[(g, q)] - m @ m[q, :]) / np.sqrt(D[g][q])
-            col[~inP[g]] = 0.0
-            D[g] = D[g] - col * col
-            D[g][q] = 0.0
-            mic[g] = np.concatenate([m, col[:, None]], axis=1)
+            l = np.where(active[g], R[g][:, q], 0.0) / np.sqrt(d)
+            R[g] -= np.outer(l, l)
+            R[g][q, q] = 0.0
             piv[g].append(q)
         for g in range(h):
-            vecs[g] = np.concatenate([vecs[g], mic[g]], axis=1)
-            leave = inP[g] & (D[g] < tau)
-            inP[g] = inP[g] & ~leave
-    diag = [np.where(inP[g], D[g], np.nan) for g in range(h)]
-    return [np.array(p, dtype=np.int64) for p in piv], diag
+            drop = active[g] & (np.diag(R[g]) < tau)
+            active[g] &= ~drop
+            R[g][drop, :] = 0.0
+            R[g][:, drop] = 0.0
+    final = [np.where(active[g], np.diag(R[g]), np.nan) for g in range(h)]
+    return [np.array(p, dtype=np.int64) for p in piv], final
 
 
 def cd_vectors(V: list, piv: list) -> list:

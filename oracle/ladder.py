@@ -28,7 +28,7 @@ __all__ = [
     "t2_ladder_loops", "t2_ladder_full", "t2_ladder_blocks", "t1_dressing_full",
     "lambda_w_full", "lambda_ladder_full", "lambda_ladder_blocks",
     "t2_ladder_symantisym_full", "pair_energies_full", "denominator_update_full",
-    "element_t2", "element_lambda", "rel_errors", "max_abs_diff_blocks",
+    "element_t2", "element_lambda", "rel_errors",
 ]
 
 
@@ -273,7 +273,3 @@ def rel_errors(got: dict, ref: dict):
     if mx_r == 0.0:
         return (0.0 if mx_d == 0.0 else np.inf), (0.0 if s_d == 0.0 else np.inf)
     return mx_d / mx_r, np.sqrt(s_d) / np.sqrt(s_r)
-
-
-def max_abs_diff_blocks(got: dict, ref: dict) -> float:
-    return max((float(np.max(np.abs(np.asarray(got[k]) - r))) for k, r in ref.items() if r.size), default=0.0)

@@ -52,8 +52,8 @@ int occupancy_mixed(int fmt, int cls);
 hipError_t launch_assemble_density(int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
                                    const SysPtrs *sp, double *xbuf, hipStream_t s);
 int occupancy_density_w();
-hipError_t launch_density_pack(const DensPackJob *jobs, const int2 *tiles, int ntiles, const DensPtrs *dp,
-                               hipStream_t s);
+hipError_t launch_density_pack(const DensPackJob *jobs, const int2 *tiles, int ntiles, const int *swap,
+                               const DensPtrs *dp, hipStream_t s);
 hipError_t launch_density_gemm(int grid, const GemmDesc *descs, const Tile *tiles, const Queues &Q, int *cnt,
                                const DensPtrs *dp, const double *xbuf, double *part, hipStream_t s);
 hipError_t launch_density_reduce(int njobs, const GemmDesc *descs, const Tile *jobs, const DensPtrs *dp,
@@ -1090,8 +1090,10 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
 }
 
 // ===========================================================================
-// vvvv two-body density (Appendix two-body densities; gradient section):
-//   W_(ab),(cd) = sum_mn [Y_mn^ab X_mn^cd + X_mn^ab Y_mn^cd]
+// vvvv spin-adapted two-body density (Appendix two-body densities; density
+// section, Gamma~ = 2 Gamma_PqRs - Gamma_PqSr; gradient section):
+//   W_(ab),(cd) = sum_mn [Y_mn^ab X'_mn^cd + X_mn^ab Y'_mn^cd]  = 2 Gamma~_abcd
+//   X'^cd = 2 X^cd - X^dc,  Y'^cd = 2 Y^cd - Y^dc
 //   G^P_ac      = 1/2 sum_bd W_(ab),(cd) L^P_bd
 // Regions: for each (system, Cholesky irrep GP, Ga) and range of a, the W
 // rows (a, c) (c in Ga^GP) times all (b, d) pairs of GP go to the batch
@@ -1111,6 +1113,7 @@ struct DensPlan {
   void *dtab = nullptr;
   DensPackJob *packjobs = nullptr;
   int2 *packtiles = nullptr;
+  int *swap = nullptr;  // per (system, pair irrep): column of (d,c) for each column (c,d)
   int npacktiles = 0;
   P1Desc *wdesc = nullptr;
   Tile *wtiles = nullptr;
@@ -1156,6 +1159,7 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
   const int64_t cap_elems = std::max<int64_t>(cap / 8, 1);
   std::vector<DensPackJob> packjobs;
   std::vector<int2> packtiles;
+  std::vector<int> swap;
   struct Region {
     int sys;
     int64_t elems;
@@ -1167,7 +1171,7 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
     const cdcc_layout_t &L = *probs[s].lay;
     const int h = L.sym.nirrep;
     const int32_t *no = L.sym.nocc, *nv = L.sym.nvir, *nc = L.sym.ncd;
-    // T tables: per pair irrep G, [Y | X] rows then [X | Y] rows (K = 2 n_oo)
+    // T tables: per pair irrep G, [Y | X] rows then [X' | Y'] rows (K = 2 n_oo)
     int64_t tw_off[CDCC_MAX_IRREP], tv_off[CDCC_MAX_IRREP];
     int64_t t = 0;
     for (int G = 0; G < h; ++G) {
@@ -1181,6 +1185,15 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
         J.ncol = int(nr);
         J.x_off = L.amp_off[G];
         J.tw_off = t;
+        J.sw_off = int(swap.size());
+        swap.resize(swap.size() + size_t(nr), -1);
+        for (int gc = 0; gc < h; ++gc) {
+          const int gd = gc ^ G;
+          for (int c = 0; c < nv[gc]; ++c)
+            for (int d = 0; d < nv[gd]; ++d)
+              swap[size_t(J.sw_off) + size_t(L.vv_off[G][gc] + int64_t(c) * nv[gd] + d)] =
+                  int(L.vv_off[G][gd] + int64_t(d) * nv[gc] + c);
+        }
         const int jid = int(packjobs.size());
         packjobs.push_back(J);
         const int nt = int((L.n_oo[G] + 63) / 64 * ((nr + 63) / 64));
@@ -1301,7 +1314,7 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
   P.ncounters = 8 * std::max(nl, 1) * kQueueStride;
   TableBuilder T;
   const int64_t o_pj = T.add(packjobs), o_pt = T.add(packtiles), o_wd = T.add(wd), o_wt = T.add(wt);
-  const int64_t o_gd = T.add(gd), o_gt = T.add(gt), o_rj = T.add(rjobs);
+  const int64_t o_gd = T.add(gd), o_gt = T.add(gt), o_rj = T.add(rjobs), o_sw = T.add(swap);
   if (hipMalloc(&P.dtab, std::max<size_t>(T.bytes.size(), 256)) != hipSuccess) return CDCC_ENOMEM;
   if (hipMemcpy(P.dtab, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return CDCC_EDEVICE;
   char *b = static_cast<char *>(P.dtab);
@@ -1313,6 +1326,7 @@ int build_density_plan(int nsys, const cdcc_density_problem_t *probs, int64_t ca
   P.gdesc = reinterpret_cast<GemmDesc *>(b + o_gd);
   P.gtiles = reinterpret_cast<Tile *>(b + o_gt);
   P.rjobs = reinterpret_cast<Tile *>(b + o_rj);
+  P.swap = reinterpret_cast<int *>(b + o_sw);
   return CDCC_OK;
 }
 
@@ -1422,7 +1436,7 @@ int run_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_op
   HIPCHK(launch_fill_int(counters, P->ncounters, 0, stream));
   {
     Span sp(1, P->npacktiles > 0, stream);
-    HIPCHK(launch_density_pack(P->packjobs, P->packtiles, P->npacktiles, ddp, stream));
+    HIPCHK(launch_density_pack(P->packjobs, P->packtiles, P->npacktiles, P->swap, ddp, stream));
   }
   int ci = 0;
   for (const DensBatch &B : P->batches) {

@@ -1,19 +1,26 @@
-// vvvv block of the CCSD two-body density contracted with Cholesky vectors,
-// FP64 kernels for gfx950 (CDNA4).
+// vvvv block of the spin-adapted CCSD two-body density contracted with
+// Cholesky vectors, FP64 kernels for gfx950 (CDNA4).
 //
 // Paper: Appendix "CCSD two-body density matrices" (Gamma_AbCd =
-// 1/2 P_+(ab,cd) V_AbCd, V_AbEf = sum_mn tau_Mn^Ef lambda_Ab^Mn) and the
-// gradient section (Gamma^P_pr = sum_qs Gamma_pqrs L~^P_qs, contracted on the
-// fly).  Closed-shell spatial form computed here:
+// 1/2 P_+(ab,cd) V_AbCd, V_AbEf = sum_mn tau_Mn^Ef lambda_Ab^Mn), the
+// spin-adapted density Gamma~_pqrs = 2 Gamma_PqRs - Gamma_PqSr of the section
+// on CCSD density matrices, and the gradient section (Gamma^P_pr = sum_qs
+// Gamma~_pqrs L~^P_qs, contracted on the fly).  Closed-shell spatial form
+// computed here, with X = tau~, Y = lambda and X'^cd = 2 X^cd - X^dc,
+// Y'^cd = 2 Y^cd - Y^dc:
 //
-//   W_(ab),(cd) = sum_mn [Y_mn^ab X_mn^cd + X_mn^ab Y_mn^cd]   = 2 Gamma_abcd
+//   W_(ab),(cd) = sum_mn [Y_mn^ab X'_mn^cd + X_mn^ab Y'_mn^cd]  = 2 Gamma~_abcd
 //   G^P_ac      = 1/2 sum_bd W_(ab),(cd) L^P_bd
+//
+// (2 Gamma~_abcd = sum_mn [Y^ab (2X^cd - X^dc) + X^ab (2Y^cd - Y^dc)]: the
+// P_+ pair of V_abcd and V_cdab, minus half the pair of V_abdc and V_dcab.)
 //
 // Pipeline of one call:
 //   pack   amplitude blocks (rows mn, columns ab) -> T tables, rows (ab) of
-//          [Y | X] and of [X | Y] (K = 2 n_oo(G), contiguous), so W is one
-//          GEMM T T'^T with K = 2 n_oo (the assembly kernel, mode 1, writes
-//          W with rows (a, c) and columns (b, d) into a bounded batch buffer)
+//          [Y | X] and rows (cd) of [X' | Y'] (K = 2 n_oo(G), contiguous), so
+//          W is one GEMM T T'^T with K = 2 n_oo (the assembly kernel, mode 1,
+//          writes W with rows (a, c) and columns (b, d) into a bounded batch
+//          buffer)
 //   gemm   G[(a,c)][P] = 1/2 W[(a,c)][(b,d)] L[(b,d)][P] over the (b, d) pairs
 //          of the Cholesky irrep (below), K cut into fixed segments
 //   reduce partial tiles of the segments summed in segment order
@@ -27,11 +34,15 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
-// pack: one workgroup per 64 x 64 tile (64 mn rows x 64 ab columns) of one
-// (system, G) amplitude block; read along ab, written along mn through LDS.
+// pack: one workgroup per 64 x 64 tile (64 mn rows x 64 columns) of one
+// (system, G) amplitude block; read along the columns, written along mn
+// through LDS, in two passes: [Y | X] for the rows (ab), then [X' | Y'] for
+// the rows (cd), whose exchange partners X^dc, Y^dc are read at the swapped
+// column of the same mn row (swap table of the job).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void density_pack_kernel(const DensPackJob *__restrict__ jobs,
                                                            const int2 *__restrict__ tiles,
+                                                           const int *__restrict__ swap,
                                                            const DensPtrs *__restrict__ dp) {
   __shared__ double ly[64][65], lx[64][65];
   const int2 jt = tiles[blockIdx.x];
@@ -43,29 +54,40 @@ __global__ __launch_bounds__(256) void density_pack_kernel(const DensPackJob *__
   const CDCC_GLOBAL double *y = as_global(P.Y) + J.x_off;
   const CDCC_GLOBAL double *x = as_global(P.X) + J.x_off;
   const int c = c0 + tx;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int kk = ty + 4 * q, k = k0 + kk;
-    const bool in = k < J.nrow && c < J.ncol;
-    const int64_t o = int64_t(in ? k : 0) * J.ncol + (in ? c : 0);
-    const double yv = y[o], xv = x[o];
-    ly[kk][tx] = in ? yv : 0.0;
-    lx[kk][tx] = in ? xv : 0.0;
-  }
-  __syncthreads();
+  const bool cin = c < J.ncol;
+  const int csw = cin ? swap[J.sw_off + c] : 0;
   const int K2 = 2 * J.nrow;
   double *__restrict__ tw = P.T + J.tw_off;                  // [Y | X]
-  double *__restrict__ tv = tw + int64_t(J.ncol) * K2;       // [X | Y]
+  double *__restrict__ tv = tw + int64_t(J.ncol) * K2;       // [X' | Y']
   const int k = k0 + tx;
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int cc = ty + 4 * q, col = c0 + cc;
-    if (k >= J.nrow || col >= J.ncol) continue;
-    const int64_t r = int64_t(col) * K2;
-    tw[r + k] = ly[tx][cc];
-    tw[r + J.nrow + k] = lx[tx][cc];
-    tv[r + k] = lx[tx][cc];
-    tv[r + J.nrow + k] = ly[tx][cc];
+    for (int q = 0; q < 16; ++q) {
+      const int kk = ty + 4 * q, kr = k0 + kk;
+      const bool in = kr < J.nrow && cin;
+      const int64_t row = int64_t(in ? kr : 0) * J.ncol;
+      const int64_t o = row + (in ? c : 0);
+      double yv = y[o], xv = x[o];
+      if (pass == 1) {
+        const int64_t os = row + (in ? csw : 0);
+        yv = 2.0 * yv - y[os];
+        xv = 2.0 * xv - x[os];
+      }
+      ly[kk][tx] = in ? yv : 0.0;
+      lx[kk][tx] = in ? xv : 0.0;
+    }
+    __syncthreads();
+    double *__restrict__ tt = pass == 0 ? tw : tv;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int cc = ty + 4 * q, col = c0 + cc;
+      if (k >= J.nrow || col >= J.ncol) continue;
+      const int64_t r = int64_t(col) * K2;
+      tt[r + k] = pass == 0 ? ly[tx][cc] : lx[tx][cc];
+      tt[r + J.nrow + k] = pass == 0 ? lx[tx][cc] : ly[tx][cc];
+    }
+    __syncthreads();
   }
 }
 
@@ -257,10 +279,10 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(const GemmDesc *__rest
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_density_pack(const DensPackJob *jobs, const int2 *tiles, int ntiles, const DensPtrs *dp,
-                               hipStream_t s) {
+hipError_t launch_density_pack(const DensPackJob *jobs, const int2 *tiles, int ntiles, const int *swap,
+                               const DensPtrs *dp, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  density_pack_kernel<<<ntiles, 256, 0, s>>>(jobs, tiles, dp);
+  density_pack_kernel<<<ntiles, 256, 0, s>>>(jobs, tiles, swap, dp);
   return hipGetLastError();
 }
 

@@ -131,12 +131,14 @@ struct DensPtrs {
   const double *Y;     // lambda amplitudes (amplitude layout)
   const double *L;     // transformed Cholesky vectors (Cholesky layout)
   double *G;           // result G^P_ac (Cholesky layout)
-  double *T;           // workspace: per pair irrep, rows (ab) of [Y | X] then rows of [X | Y]
+  double *T;           // workspace: per pair irrep, rows (ab) of [Y | X], then rows (cd) of
+                       // [2X^cd - X^dc | 2Y^cd - Y^dc] (the spin-adapted exchange partner)
 };
 
 // Transposition of one pair-irrep amplitude block into the T tables.
 struct DensPackJob {
-  int32_t sys, nrow, ncol, pad0;   // nrow = n_oo(G) (K half), ncol = n_vv(G) (pair rows)
+  int32_t sys, nrow, ncol;         // nrow = n_oo(G) (K half), ncol = n_vv(G) (pair rows)
+  int32_t sw_off;                  // column swap table entries [sw_off, sw_off + ncol): column of (d,c)
   int64_t x_off;                   // amp_off[G]
   int64_t tw_off;                  // element offset of row 0 of [Y | X] in T; [X | Y] follows
 };

@@ -102,9 +102,10 @@ def ladder_lambda(problems, precision="fp64", stream=None, tile_policy=0, batch_
 
 
 def vvvv_density(problems, stream=None, batch_bytes=0) -> None:
-    """vvvv two-body-density contraction G^P_ac = 1/2 sum_bd sum_mn
-    [Y_mn^ab X_mn^cd + Y_mn^cd X_mn^ab] L^P_bd (FP64) for one problem dict or
-    a list of them.  Keys: layout (Layout), L, X (tau~), Y (lambda), G (out;
+    """vvvv contraction of the spin-adapted two-body density, G^P_ac =
+    sum_bd (2 Gamma_abcd - Gamma_abdc) L^P_bd with Gamma_abcd = 1/2 sum_mn
+    [Y_mn^ab X_mn^cd + Y_mn^cd X_mn^ab] (FP64), for one problem dict or a
+    list of them.  Keys: layout (Layout), L, X (tau~), Y (lambda), G (out;
     Cholesky layout).  Asynchronous on ``stream``."""
     if isinstance(problems, dict):
         problems = [problems]

@@ -108,3 +108,16 @@ def test_irrep_screened_out_entirely(gpu_lib):
     W = [v * 1e-12 for v in S.make_cd_matrices([20, 10], seed=9, kappa=5.0)]
     piv = _check(gpu_lib, W, 1e-6, 1e-2, 64)
     assert all(p.size == 0 for p in piv)
+
+
+def test_hand_worked_pivot_order(gpu_lib):
+    """The hand-worked five-pair matrix of the oracle pins (sigma = 1/2,
+    Q_max = 2, tau = 1/2): the device takes the pivots in the literal order
+    [0, 1, 2, 4, 3], as one irrep and split into two irreps."""
+    from tests.test_oracle_cd import HAND_ALG1, HAND_V
+    piv = _check(gpu_lib, [HAND_V], 0.5, 0.5, 2)
+    assert piv[0].tolist() == HAND_ALG1
+    v0 = HAND_V[np.ix_([0, 1, 4], [0, 1, 4])]
+    v1 = HAND_V[np.ix_([2, 3], [2, 3])]
+    piv = _check(gpu_lib, [v0, v1], 0.5, 0.5, 2)
+    assert piv[0].tolist() == [0, 1, 2] and piv[1].tolist() == [0, 1]
