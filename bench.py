@@ -2,16 +2,21 @@
 """Benchmark of the Cholesky-decomposed CCSD particle-particle ladder on one
 MI355X.
 
-One step = one pass of the whole hot path over one synthetic input: the T2
-ladder R = sum_cd tau (ac|bd) and the T1-dressed Lambda ladder
-Z = sum_ef lambda W_efab, each with the symmetric-antisymmetric split, the
-(ac|bd) batches assembled on the fly, the FP64 epilogue (R/D and pair
-energies), on the 8-irrep workload o=20 (4,2,3,2,3,2,2,2), v=200
-(40,22,30,20,32,18,22,16), 1500 Cholesky vectors in the totally symmetric
-irrep.  Inputs are resident in HBM before the timed region.
+Default workload (the largest single-GPU ladder configuration): the T2 ladder
+R = sum_cd tau (ac|bd) on 8 irreps, o=40 (8,5,6,4,6,4,4,3), v=400
+(80,44,60,40,64,36,44,32), 3000 Cholesky vectors split evenly, with the
+symmetric-antisymmetric split, the (ac|bd) batches assembled on the fly and
+the FP64 epilogue (R/D and pair energies).  One step = one such evaluation;
+inputs are resident in HBM before the timed region.  Every path is gated
+against the FP64 oracle on every element (1e-12 FP64, 1e-7 split paths
+normwise; pair energies 1e-8 Eh).
 
-value = algorithmic TFLOP/s (symmetry-blocked, stored-halves flop count of
-both ladders) of the fastest path that passes its accuracy gate.
+value = algorithmic TFLOP/s (symmetry-blocked, stored-halves flop count) of
+the fastest of the FP64 and split-BF16 paths that passes its gate.  Beside
+it: the 8-bit digit path, the roofline of the dominant kernel of every path,
+the 8-irrep o=20/v=200 workload (T2 + T1-dressed Lambda) and the batch of 64
+uneven systems as extra workloads with their own gates, rooflines and CPU
+baselines, and the serving loop (FP64 and split-BF16) with p50/p99 latency.
 """
 from __future__ import annotations
 
@@ -32,21 +37,58 @@ PEAK = {"fp64": 78.6, "bf16": 2500.0, "int8": 5000.0}  # MI355X dense MFMA, TFLO
 # FP32 accumulation and FP64 combination); the 8-bit digit path is measured
 # and reported beside them.
 HEADLINE_FORMS = ("fp64", "mixed")
-# MFMA products issued per algorithmic term: ten BF16 slice products, thirteen
-# 8-bit digit products
-NPROD = {"mixed": 10, "mixed_i8": 13}
+# MFMA products issued per algorithmic term: eleven BF16 slice products,
+# thirteen 8-bit digit products
+NPROD = {"mixed": 11, "mixed_i8": 13}
 DTYPE = {"fp64": "f64", "mixed": "bf16x4-split/f32-acc/f64-sum", "mixed_i8": "i8x4-split/i32-acc/f64-sum"}
+# MFMA type (peak) of each kernel class per path
+KERNEL_PEAK = {"assemble": {"fp64": "fp64", "mixed": "bf16", "mixed_i8": "int8"},
+               "contract": {"fp64": "fp64", "mixed": "fp64", "mixed_i8": "fp64"}}
+KERNEL_NAME = {"assemble": "(ac|bd) batch assembly", "contract": "S/A contraction + unpack"}
 HBM_PEAK = 8000.0  # GB/s
-# Bytes one assembly launch moves between L2 and the memory fabric, from
-# rocprofv3 FETCH_SIZE + WRITE_SIZE per dispatch (scaled x2.0 and x1.0 by a
-# plain 256 MiB device copy), averaged over the T2 and Lambda launches of a
-# step; per (workload, path), for the kernels as committed (profiles/).  The
-# vvvv density and partial-contraction entries are the launch of their GEMM
-# kernel, counted the same way.
-TRAFFIC = {("d2h_medium", "mixed"): 3.528e9, ("d2h_medium", "fp64"): 2.046e9, ("d2h_medium", "mixed_i8"): 1.345e9,
-           ("d2h_large", "fp64"): 11.333e9, ("d2h_large", "mixed"): 10.771e9, ("d2h_large", "mixed_i8"): 6.690e9,
-           ("vvvv_d2h_medium", "fp64"): 3.800e9,
-           ("pm_d2h_medium", "fp64"): 0.277e9, ("pm_d2h_large", "fp64"): 7.494e9}
+GATE = {"fp64": 1e-12, "mixed": 1e-7, "mixed_i8": 1e-7}
+PAIR_GATE = 1e-8   # Eh, split paths (FP64: 1e-12 relative to max |e_ij|)
+# Bytes one launch of a kernel class moves between L2 and the memory fabric,
+# from rocprofv3 FETCH_SIZE + WRITE_SIZE per dispatch (scaled x2.0 and x1.0 by
+# a plain 256 MiB device copy), per (workload, path, kernel), for the kernels
+# as committed (profiles/).  The vvvv density and partial-contraction entries
+# are the launch of their GEMM kernel, counted the same way.
+TRAFFIC = {("d2h_medium", "mixed", "assemble"): 3.528e9, ("d2h_medium", "fp64", "assemble"): 2.046e9,
+           ("d2h_medium", "mixed_i8", "assemble"): 1.345e9,
+           ("d2h_large", "fp64", "assemble"): 11.333e9, ("d2h_large", "mixed", "assemble"): 10.771e9,
+           ("d2h_large", "mixed_i8", "assemble"): 6.690e9,
+           ("d2h_large", "fp64", "contract"): 10.011e9, ("d2h_large", "mixed", "contract"): 10.011e9,
+           ("d2h_large", "mixed_i8", "contract"): 10.011e9,
+           ("vvvv_d2h_medium", "fp64", "gemm"): 3.800e9,
+           ("pm_d2h_medium", "fp64", "gemm"): 0.277e9, ("pm_d2h_large", "fp64", "gemm"): 7.494e9}
+# A single system is checked on every element when the plain oracle costs at
+# most this many flops; in a batched call, systems up to SYSTEM_FULL_FLOPS
+# are checked in full and the others on sampled elements.
+FULL_ORACLE_FLOPS = 5e12
+SYSTEM_FULL_FLOPS = 2e10
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def blas_threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count()))
+    except Exception:  # pragma: no cover
+        return int(os.cpu_count() or 1)
 
 
 def workload(name):
@@ -96,45 +138,88 @@ def step(cdcc, dev, precision):
         fn(ds, precision=precision, tile_policy=TILE_POLICY)
 
 
-def _oracle_flops(p):
+def _plain_flops(p):
     from oracle.layout import OracleLayout
     lay = OracleLayout(p["sym"])
     return sum(2.0 * lay.n_oo[G] * lay.n_vv[G] ** 2 for G in range(lay.h))
 
 
-def accuracy(cdcc, dev, precision, samples=300):
-    """Errors against the FP64 oracle: full comparison (normwise, pair
-    energies) when the oracle is cheap, else sampled elements computed one by
-    one (max error relative to max|R|)."""
+def _alg_flops(kind, p):
+    from paper_2512_21909_amd import Layout
+    return sum(Layout(p["sym"]).flops(0 if kind == "t2" else 2))
+
+
+def _oracle(kind, p):
+    import oracle as O
+    if kind == "t2":
+        return O.t2_ladder_blocks(p["sym"], p["B"], p["X"])
+    return O.lambda_ladder_blocks(p["sym"], p["B"], p["Bvo"], p["t1"], p["X"])
+
+
+def reference(entries):
+    """Oracle results (R, R/D, pair energies) of every problem the oracle
+    affords in full (None for the others), and the host time and algorithmic
+    flops of those oracle evaluations (a CPU-baseline sample)."""
+    import oracle as O
+    refs, secs, flops, n = [], 0.0, 0.0, 0
+    for kind, probs in entries:
+        single = len(probs) == 1
+        row = []
+        for p in probs:
+            if _plain_flops(p) > (FULL_ORACLE_FLOPS if single else SYSTEM_FULL_FLOPS):
+                row.append(None)
+                continue
+            t0 = time.perf_counter()
+            r = _oracle(kind, p)
+            secs += time.perf_counter() - t0
+            flops += _alg_flops(kind, p)
+            n += 1
+            sym = p["sym"]
+            row.append({"R": r, "e": O.pair_energies_blocks(sym, p["X"], r),
+                        "delta": O.denominator_update_blocks(sym, r, p["eps_occ"], p["eps_vir"])})
+        refs.append(row)
+    return refs, {"seconds": secs, "flops": flops, "evaluations": n}
+
+
+def accuracy(cdcc, dev, refs, precision, e_fp64=None, samples=40):
+    """Errors of one evaluation against the oracle.  Problems with a full
+    reference: normwise max and Frobenius errors of R and R/D, pair energies.
+    The others: ``samples`` elements each computed one by one by the oracle
+    (max error relative to max|R|), and, when the FP64 path's pair energies
+    are given, the pair energies against them.  Metrics that were not
+    computed are None.  Returns (per-kind errors, pair energies per call)."""
     import torch
     import oracle as O
-    from oracle.layout import OracleLayout
     step(cdcc, dev, precision)
     torch.cuda.synchronize()
-    out = {}
+    out, energies = {}, []
     rng = np.random.default_rng(2024)
-    for kind, probs, ds in dev:
-        worst = {"max_rel": 0.0, "fro_rel": 0.0, "pair_energy_abs": 0.0}
-        sampled = sum(_oracle_flops(p) for p in probs) > 2e11
-        for p, d in zip(probs, ds):
+    for ci, (kind, probs, ds) in enumerate(dev):
+        acc = {"max_rel": 0.0, "fro_rel": None, "delta_max_rel": None, "pair_energy_abs": None,
+               "pair_energy_abs_vs_fp64": None, "full_systems": 0, "sampled_systems": 0, "sampled_elements": 0}
+        e_call = []
+        for pi, (p, d) in enumerate(zip(probs, ds)):
             lay = d["layout"]
             got = lay.unpack_amp(d["R"].cpu().numpy())
-            if not sampled:
-                ref = (O.t2_ladder_blocks(p["sym"], p["B"], p["X"]) if kind == "t2"
-                       else O.lambda_ladder_blocks(p["sym"], p["B"], p["Bvo"], p["t1"], p["X"]))
-                mx, fro = O.rel_errors(got, ref)
-                ol = OracleLayout(p["sym"])
-                e_ref = O.pair_energies_full(ol.full_amp(p["X"]), ol.full_amp(ref))
-                e_got = d["pair_energy"].cpu().numpy().reshape(e_ref.shape)
-                worst["max_rel"] = max(worst["max_rel"], mx)
-                worst["fro_rel"] = max(worst["fro_rel"], fro)
-                worst["pair_energy_abs"] = max(worst["pair_energy_abs"], float(np.max(np.abs(e_got - e_ref))))
+            e_got = d["pair_energy"].cpu().numpy()
+            e_call.append(e_got)
+            ref = refs[ci][pi] if refs is not None else None
+            if ref is not None:
+                mx, fro = O.rel_errors(got, ref["R"])
+                dmx, _ = O.rel_errors(lay.unpack_amp(d["delta"].cpu().numpy()), ref["delta"])
+                ee = float(np.max(np.abs(e_got.reshape(ref["e"].shape) - ref["e"]))) if ref["e"].size else 0.0
+                if precision == "fp64":
+                    ee /= max(1.0, float(np.max(np.abs(ref["e"])))) if ref["e"].size else 1.0
+                acc["max_rel"] = max(acc["max_rel"], mx)
+                acc["fro_rel"] = max(acc["fro_rel"] or 0.0, fro)
+                acc["delta_max_rel"] = max(acc["delta_max_rel"] or 0.0, dmx)
+                acc["pair_energy_abs"] = max(acc["pair_energy_abs"] or 0.0, ee)
+                acc["full_systems"] += 1
                 continue
             sym, h = p["sym"], p["sym"]["h"]
             no, nv = sym["nocc"], sym["nvir"]
             scale = max(float(np.max(np.abs(b))) for b in got.values() if b.size)
-            n = max(8, samples // len(probs))
-            for _ in range(n):
+            for _ in range(samples):
                 G, gi, ga = (int(x) for x in rng.integers(0, h, 3))
                 gj, gb = gi ^ G, ga ^ G
                 if not (no[gi] and no[gj] and nv[ga] and nv[gb]):
@@ -142,12 +227,37 @@ def accuracy(cdcc, dev, precision, samples=300):
                 i, j = int(rng.integers(no[gi])), int(rng.integers(no[gj]))
                 a, b = int(rng.integers(nv[ga])), int(rng.integers(nv[gb]))
                 args = (lay.occ_off[gi] + i, lay.occ_off[gj] + j, lay.vir_off[ga] + a, lay.vir_off[gb] + b)
-                ref = (O.element_t2(sym, p["B"], p["X"], *args) if kind == "t2"
-                       else O.element_lambda(sym, p["B"], p["Bvo"], p["t1"], p["X"], *args))
-                worst["max_rel"] = max(worst["max_rel"], abs(got[(G, gi, ga)][i, j, a, b] - ref) / scale)
-            worst["sampled_elements"] = True
-        out[kind] = worst
-    return out
+                r = (O.element_t2(sym, p["B"], p["X"], *args) if kind == "t2"
+                     else O.element_lambda(sym, p["B"], p["Bvo"], p["t1"], p["X"], *args))
+                acc["max_rel"] = max(acc["max_rel"], abs(got[(G, gi, ga)][i, j, a, b] - r) / scale)
+                acc["sampled_elements"] += 1
+            acc["sampled_systems"] += 1
+            if e_fp64 is not None:
+                ee = float(np.max(np.abs(e_got - e_fp64[ci][pi]))) if e_got.size else 0.0
+                acc["pair_energy_abs_vs_fp64"] = max(acc["pair_energy_abs_vs_fp64"] or 0.0, ee)
+        out[kind] = acc
+        energies.append(e_call)
+    return out, energies
+
+
+def gate_ok(acc, precision):
+    """Every metric that was computed is within its gate (None = not
+    computed, left out)."""
+    if acc is None:
+        return True
+    g = GATE[precision]
+    for a in acc.values():
+        if a["max_rel"] > g:
+            return False
+        for k in ("fro_rel", "delta_max_rel"):
+            if a[k] is not None and a[k] > g:
+                return False
+        pe = 1e-12 if precision == "fp64" else PAIR_GATE
+        if a["pair_energy_abs"] is not None and a["pair_energy_abs"] > pe:
+            return False
+        if a["pair_energy_abs_vs_fp64"] is not None and a["pair_energy_abs_vs_fp64"] > PAIR_GATE:
+            return False
+    return True
 
 
 def timed(cdcc, dev, precision, steps, warmup):
@@ -170,7 +280,8 @@ def timed(cdcc, dev, precision, steps, warmup):
 
 
 def kernel_times(cdcc, dev, precision, steps):
-    """Per-class kernel durations from HIP events on the library's stream."""
+    """Per-class kernel durations from HIP events recorded by the library on
+    the stream it launches on."""
     import torch
     torch.cuda.synchronize()
     cdcc.timing_read()
@@ -182,53 +293,210 @@ def kernel_times(cdcc, dev, precision, steps):
     return cdcc.timing_read()
 
 
-def cpu_baseline(entries, flops_step, budget_s=12.0, budget_1t=6.0):
-    """The FP64 oracle (NumPy + host BLAS) on the same workload, repeated for
-    a bounded time on the host cores (whole steps while they fit the budget,
-    else the first problems of the first call); then the same with the host
-    BLAS held to one thread, on a shorter budget."""
-    import oracle as O
-    try:
-        from threadpoolctl import threadpool_info, threadpool_limits
-        cores = max((d.get("num_threads", 1) for d in threadpool_info()), default=os.cpu_count())
-    except Exception:  # pragma: no cover
-        threadpool_limits = None
-        cores = os.cpu_count()
+def kernel_rooflines(name, precision, kt, flops_cls, steps):
+    """Roofline object of the assembly and of the contraction of one path:
+    algorithmic flops per launch / average launch time."""
+    out = {}
+    for cls, fidx in (("assemble", 0), ("contract", 1)):
+        ms, n = kt.get(cls, (0.0, 0))
+        if not n or not ms:
+            continue
+        per_launch = flops_cls[fidx] * steps / n
+        avg_ms = ms / n
+        ach = per_launch / (avg_ms * 1e-3) / 1e12
+        pk = KERNEL_PEAK[cls][precision]
+        o = {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK[pk],
+             "unit": "TOP/s" if pk == "int8" else "TFLOP/s", "frac": round(ach / PEAK[pk], 4),
+             "traffic": TRAFFIC.get((name, precision, cls)), "kernel": KERNEL_NAME[cls], "launches": n,
+             "avg_launch_ms": avg_ms, "flops_per_launch": per_launch, "ms_per_step": ms / steps}
+        if pk != "fp64" and precision in NPROD:
+            o["issued_" + ("bf16_tflops" if pk == "bf16" else "int8_tops")] = round(ach * NPROD[precision], 3)
+            o["issued_frac"] = round(ach * NPROD[precision] / PEAK[pk], 4)
+        out[cls] = o
+    return out
 
-    def run_one(kind, p):
-        if kind == "t2":
-            O.t2_ladder_blocks(p["sym"], p["B"], p["X"])
-        else:
-            O.lambda_ladder_blocks(p["sym"], p["B"], p["Bvo"], p["t1"], p["X"])
 
-    from paper_2512_21909_amd import Layout
-
-    def timed(budget):
+def measure_ladder(cdcc, name, args, paths):
+    """Every path on one workload: accuracy gate, timing, per-kernel
+    rooflines; plus the oracle's own timing from the gate (CPU sample)."""
+    desc, entries = workload(name)
+    dev = build_inputs(cdcc, entries)
+    flops_step, flops_cls = 0.0, [0.0, 0.0, 0.0]
+    for kind, _, ds in dev:
+        for d in ds:
+            f = d["layout"].flops(0 if kind == "t2" else 2)
+            flops_step += sum(f)
+            flops_cls = [a + b for a, b in zip(flops_cls, f)]
+    log(f"{desc}; F_alg per step {flops_step:.4e} (assembly {flops_cls[0]:.4e}, contraction {flops_cls[1]:.4e})")
+    refs, oracle_t = (None, None)
+    if not args.no_check:
         t0 = time.perf_counter()
-        done_flops, reps, items = 0.0, 0, 0
-        while time.perf_counter() - t0 < budget and reps < 50:
+        refs, oracle_t = reference(entries)
+        log(f"{name}: oracle references in {time.perf_counter() - t0:.1f} s "
+            f"({oracle_t['evaluations']} full evaluations)")
+    results, e_fp64 = {}, None
+    for prec in paths:
+        try:
+            acc = None
+            if refs is not None:
+                acc, energies = accuracy(cdcc, dev, refs, prec, e_fp64=e_fp64 if prec != "fp64" else None)
+                if prec == "fp64":
+                    e_fp64 = energies
+        except cdcc.CdccError as e:
+            log(f"{prec}: unavailable ({e})")
+            continue
+        sec, per_step = timed(cdcc, dev, prec, args.steps, args.warmup)
+        kt = kernel_times(cdcc, dev, prec, args.steps)
+        ok = gate_ok(acc, prec)
+        roofs = kernel_rooflines(name, prec, kt, flops_cls, args.steps)
+        dom = max(roofs, key=lambda c: roofs[c]["ms_per_step"]) if roofs else None
+        results[prec] = {"ms_per_step": sec * 1e3, "tflops": flops_step / sec / 1e12, "accuracy": acc,
+                         "passes_gate": ok, "step_ms_median": float(np.median(per_step)),
+                         "step_ms_min": float(np.min(per_step)), "dominant_kernel": dom, "rooflines": roofs,
+                         "kernels_ms": kt}
+        log(f"{name} {prec}: {sec * 1e3:.3f} ms/step, {flops_step / sec / 1e12:.2f} TFLOP/s, gate ok={ok}, "
+            f"kernels={kt}")
+    good = [p for p in results if results[p]["passes_gate"] and (p in HEADLINE_FORMS or len(results) == 1)]
+    best = max(good, key=lambda p: results[p]["tflops"]) if good else None
+    out = {"workload": desc, "flops_per_step": flops_step, "flops_assembly": flops_cls[0],
+           "flops_contraction": flops_cls[1], "paths": results, "best": best,
+           "value": round(results[best]["tflops"], 4) if best else None,
+           "ms_per_step": round(results[best]["ms_per_step"], 4) if best else None,
+           "passes_gate": best is not None}
+    if best:
+        r = results[best]
+        out["roofline"] = r["rooflines"].get(r["dominant_kernel"])
+    if "fp64" in results and "mixed" in results:
+        out["mixed_speedup_vs_fp64"] = results["mixed"]["tflops"] / results["fp64"]["tflops"]
+    if "fp64" in results and "mixed_i8" in results:
+        out["mixed_i8_speedup_vs_fp64"] = results["mixed_i8"]["tflops"] / results["fp64"]["tflops"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(entries, oracle_t, budget_1t=args.cpu_budget_1t if name != "d2h_large" else 0)
+    return out
+
+
+def cpu_baseline(entries, oracle_t, budget_s=12.0, budget_1t=0.0):
+    """The FP64 oracle (NumPy + host BLAS) on the same workload: the gate's
+    own oracle evaluations when there were any (else whole evaluations
+    repeated for a bounded time), and optionally a run with the host BLAS
+    held to one thread."""
+    cores = blas_threads()
+
+    def run_for(budget):
+        t0 = time.perf_counter()
+        done_flops, items = 0.0, 0
+        while items == 0 or time.perf_counter() - t0 < budget:
             for kind, probs in entries:
                 for p in probs:
-                    run_one(kind, p)
-                    done_flops += sum(Layout(p["sym"]).flops(0 if kind == "t2" else 2))
+                    _oracle(kind, p)
+                    done_flops += _alg_flops(kind, p)
                     items += 1
                     if time.perf_counter() - t0 >= budget:
-                        break
-                if time.perf_counter() - t0 >= budget:
-                    break
-            reps += 1
+                        return done_flops, time.perf_counter() - t0, items
         return done_flops, time.perf_counter() - t0, items
 
-    done_flops, dt, items = timed(budget_s)
-    out = {"value": done_flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-           "sample": f"{items} ladder evaluations of this workload (symmetry-blocked plain FP64 contraction, "
-                     f"NumPy + host BLAS) in {dt:.1f} s; rate = their algorithmic flops / time"}
-    if threadpool_limits is not None and budget_1t > 0:
-        with threadpool_limits(limits=1):
-            f1, d1, n1 = timed(budget_1t)
-        out["value_1_thread"] = f1 / d1 / 1e12
-        out["sample_1_thread"] = f"{n1} evaluations in {d1:.1f} s with the host BLAS on one thread"
+    if oracle_t and oracle_t["evaluations"] and oracle_t["seconds"] >= 2.0:
+        f, dt, n = oracle_t["flops"], oracle_t["seconds"], oracle_t["evaluations"]
+        how = "the accuracy gate's own oracle runs"
+    else:
+        f, dt, n = run_for(budget_s)
+        how = "oracle runs repeated for a bounded time"
+    out = {"value": f / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{n} ladder evaluation(s) of this workload in {dt:.1f} s ({how}; symmetry-blocked plain "
+                     f"FP64 contraction, NumPy + host BLAS); rate = their algorithmic flops / time"}
+    if budget_1t > 0:
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                f1, d1, n1 = run_for(budget_1t)
+            out["value_1_thread"] = f1 / d1 / 1e12
+            out["sample_1_thread"] = f"{n1} evaluations in {d1:.1f} s with the host BLAS on one thread"
+        except Exception:  # pragma: no cover
+            pass
     return out
+
+
+def serving_pool(seed=5, n_shapes=12):
+    """Device-resident inputs of the serving mix: twelve shapes drawn like the
+    uneven batch, plus the large request (o=30, v=300, 2500 vectors, 8
+    irreps)."""
+    import torch
+    import synth as S
+    from paper_2512_21909_amd import Layout
+
+    def dev(x):
+        return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+    syms = S.batch_syms(n_shapes, seed=seed) + [S.sym_serving_large()]
+    pool = []
+    for k, sym in enumerate(syms):
+        p = S.make_problem(sym, seed=100 + k, kind="t2")
+        lay = Layout(sym)
+        pool.append({"layout": lay, "B": dev(lay.pack_B(p["B"])), "X": dev(lay.pack_amp(p["X"])),
+                     "flops": sum(lay.flops(0)), "large": k == len(syms) - 1})
+    return pool
+
+
+def compact(m):
+    """An extra workload's summary for the bench line."""
+    keep = ("workload", "value", "ms_per_step", "passes_gate", "best", "flops_per_step", "roofline",
+            "mixed_speedup_vs_fp64", "mixed_i8_speedup_vs_fp64", "cpu_baseline")
+    out = {k: m[k] for k in keep if k in m}
+    out["paths"] = {p: {k: v for k, v in r.items() if k != "kernels_ms"} for p, r in m["paths"].items()}
+    return out
+
+
+def ladder_main(args, cdcc):
+    paths = ["fp64", "mixed", "mixed_i8"] if args.precision == "all" else [args.precision]
+    m = measure_ladder(cdcc, args.workload, args, paths)
+    if m["best"] is None:
+        log("no path passed its accuracy gate")
+        print(json.dumps({"metric": METRIC, "value": None, "error": "no path passed its accuracy gate",
+                          "paths": m["paths"]}, default=str), flush=True)
+        sys.exit(1)
+    best = m["best"]
+    line = {
+        "metric": METRIC, "value": m["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[best], "data": "synthetic",
+        "config": {"workload": m["workload"], "flops_per_step": m["flops_per_step"], "path": best},
+        "roofline": m["roofline"],
+        "paths": m["paths"],
+    }
+    for k in ("mixed_speedup_vs_fp64", "mixed_i8_speedup_vs_fp64"):
+        if k in m:
+            line[k] = m[k]
+    extras = [] if args.extras in ("", "none") else args.extras.split(",")
+    if extras:
+        line["workloads"] = {}
+        for name in extras:
+            line["workloads"][name] = compact(measure_ladder(cdcc, name, args, paths))
+    if args.serving:
+        from paper_2512_21909_amd import serve
+        pool = serving_pool()
+        line["serving"] = {}
+        for prec in args.serving_precisions.split(","):
+            line["serving"][prec] = serve.measure(pool, prec, n_requests=args.serving, warmup=args.serving_warmup,
+                                                  load=args.serving_load)
+            s = line["serving"][prec]
+            log(f"serving {prec}: saturation {s['saturation'].get('requests_per_s', 0):.1f} req/s, "
+                f"load {args.serving_load}: p50 {s['stream'].get('p50_ms', 0):.2f} ms, "
+                f"p99 {s['stream'].get('p99_ms', 0):.2f} ms")
+    if "cpu_baseline" in m:
+        line["cpu_baseline"] = m["cpu_baseline"]
+    print(json.dumps(line, default=str), flush=True)
+
+
+def serving_sweep_main(args, cdcc):
+    """Saturation once, then one Poisson stream per load, per precision."""
+    from paper_2512_21909_amd import serve
+    pool = serving_pool()
+    loads = [float(x) for x in args.serving_sweep.split(",")]
+    out = {}
+    for prec in args.serving_precisions.split(","):
+        out[prec] = serve.measure_sweep(pool, prec, n_requests=args.serving, loads=loads,
+                                        warmup=args.serving_warmup, log=log)
+    print(json.dumps(out), flush=True)
 
 
 DENSITY_METRIC = "vvvv two-body-density contraction with Cholesky vectors, TFLOP/s (FP64)"
@@ -299,7 +567,7 @@ def density_main(args, cdcc):
         "config": {"workload": desc, "flops_per_step": flops, "path": "fp64"},
         "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
                      "frac": round(ach / PEAK["fp64"], 4),
-                     "traffic": TRAFFIC.get((args.workload, "fp64")),
+                     "traffic": TRAFFIC.get((args.workload, "fp64", "gemm")),
                      "kernel": "contraction of the (ab|cd) batch with L", "launches": g_n,
                      "avg_launch_ms": g_ms / max(g_n, 1), "flops_per_launch": fl * args.steps / max(g_n, 1)},
         "stage_ab_cd": {"ms_per_step": w_ms / args.steps, "tflops": fv * args.steps / (w_ms * 1e-3) / 1e12 if w_ms else 0},
@@ -319,7 +587,7 @@ def density_main(args, cdcc):
             reps += 1
         dt = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": flops * reps / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores),
-                                "kind": "oracle",
+                                "kind": "oracle", "cpu_model": cpu_model(),
                                 "sample": f"the whole workload, {reps} oracle runs in {dt:.1f} s"}
     print(json.dumps(line), flush=True)
     if not ok:
@@ -400,7 +668,7 @@ def partial_main(args, cdcc):
         roof = {"bound": "hbm", "achieved": round(gemm_bytes / g_s / 1e9, 1) if g_ms else 0.0, "peak": HBM_PEAK,
                 "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof.update({"traffic": TRAFFIC.get((args.workload, "fp64")), "kernel": "pm_gemm (S and A, both orders of M)",
+    roof.update({"traffic": TRAFFIC.get((args.workload, "fp64", "gemm")), "kernel": "pm_gemm (S and A, both orders of M)",
                  "launches": g_n, "avg_launch_ms": g_ms / max(g_n, 1), "flops_per_launch": flops,
                  "algorithmic_bytes_per_launch": gemm_bytes, "intensity_flop_per_byte": round(intensity, 2)})
     line = {
@@ -424,7 +692,7 @@ def partial_main(args, cdcc):
             reps += 1
         dt = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": flops * reps / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores),
-                                "kind": "oracle",
+                                "kind": "oracle", "cpu_model": cpu_model(),
                                 "sample": f"the whole workload, {reps} oracle runs (plain definition, "
                                           f"{plain:.3e} flops each) in {dt:.1f} s; rate in the partial "
                                           f"algorithm's flops"}
@@ -528,7 +796,7 @@ def cd_main(args, cdcc):
             O.cd_vectors(V, rp)
             reps += 1
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": dt / reps * 1e3, "unit": "ms", "cores": int(cores), "kind": "oracle",
+        line["cpu_baseline"] = {"value": dt / reps * 1e3, "unit": "ms", "cores": int(cores), "kind": "oracle", "cpu_model": cpu_model(),
                                 "sample": f"the whole workload, {reps} oracle runs in {dt:.1f} s"}
     print(json.dumps(line), flush=True)
     if not ok:
@@ -540,20 +808,32 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="d2h_medium")
+    ap.add_argument("--workload", default="d2h_large")
+    ap.add_argument("--extras", default=None,
+                    help="comma-separated extra ladder workloads measured beside the headline one "
+                         "(default with d2h_large: d2h_medium,batch64; 'none' to skip)")
     ap.add_argument("--precision", default="all", choices=["all", "fp64", "mixed", "mixed_i8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-1t", type=float, default=6.0,
+                    help="seconds of the one-thread CPU baseline of the extra workloads (0 = skip)")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle accuracy gate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--tile-policy", type=int, default=0, help="0 = tile table, 1..3 force a tile class")
-    ap.add_argument("--serving", type=int, default=200,
-                    help="requests of the serving run reported beside the step (0 = skip)")
+    ap.add_argument("--tile-policy", type=int, default=0, help="0 = tile table, 1..4 force a tile class")
+    ap.add_argument("--serving", type=int, default=2000,
+                    help="requests of each measured serving run (0 = skip the serving runs)")
+    ap.add_argument("--serving-warmup", type=int, default=200, help="warm-up requests before the serving runs")
+    ap.add_argument("--serving-load", type=float, default=0.7, help="Poisson rate as a fraction of saturation")
+    ap.add_argument("--serving-precisions", default="fp64,mixed")
+    ap.add_argument("--serving-sweep", default=None,
+                    help="comma-separated loads: only the serving sweep (saturation, one stream per load)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ladder library runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.extras is None:
+        args.extras = "d2h_medium,batch64" if args.workload == "d2h_large" else ""
 
     import torch
     import paper_2512_21909_amd as cdcc
@@ -567,6 +847,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.serving_sweep:
+        serving_sweep_main(args, cdcc)
+        return
     if args.workload.startswith("vvvv_"):
         density_main(args, cdcc)
         return
@@ -576,98 +859,7 @@ def main():
     if args.workload.startswith("cd_"):
         cd_main(args, cdcc)
         return
-    wdesc, entries = workload(args.workload)
-    dev = build_inputs(cdcc, entries)
-    flops_step = flops_assemble = 0.0
-    for kind, _, ds in dev:
-        for d in ds:
-            f = d["layout"].flops(0 if kind == "t2" else 2)
-            flops_step += sum(f)
-            flops_assemble += f[0]
-    print(f"[bench] {wdesc}; F_alg per step {flops_step:.4e} (assembly {flops_assemble:.4e})", file=sys.stderr,
-          flush=True)
-
-    paths = ["fp64", "mixed", "mixed_i8"] if args.precision == "all" else [args.precision]
-    results = {}
-    for prec in paths:
-        try:
-            acc = None if args.no_check else accuracy(cdcc, dev, prec)
-        except cdcc.CdccError as e:
-            print(f"[bench] {prec}: unavailable ({e})", file=sys.stderr, flush=True)
-            continue
-        sec, per_step = timed(cdcc, dev, prec, args.steps, args.warmup)
-        kt = kernel_times(cdcc, dev, prec, args.steps)
-        gate = 1e-12 if prec == "fp64" else 1e-7
-        ok = acc is None or all(a["max_rel"] <= gate and a["fro_rel"] <= gate and
-                                (prec == "fp64" or a["pair_energy_abs"] <= 1e-8) for a in acc.values())
-        results[prec] = {"ms_per_step": sec * 1e3, "tflops": flops_step / sec / 1e12, "accuracy": acc,
-                         "passes_gate": ok, "kernels": kt,
-                         "step_ms_median": float(np.median(per_step)), "step_ms_min": float(np.min(per_step))}
-        print(f"[bench] {prec}: {sec * 1e3:.3f} ms/step, {flops_step / sec / 1e12:.2f} TFLOP/s, gate ok={ok}, "
-              f"kernels={kt}", file=sys.stderr, flush=True)
-
-    good = [p for p in results if results[p]["passes_gate"] and (p in HEADLINE_FORMS or len(results) == 1)]
-    if not good:
-        print("[bench] no path passed its accuracy gate", file=sys.stderr)
-        sys.exit(1)
-    best = max(good, key=lambda p: results[p]["tflops"])
-    r = results[best]
-    asm_ms, asm_n = r["kernels"].get("assemble", (0.0, 0))
-    per_launch_flops = flops_assemble * args.steps / max(asm_n, 1)
-    avg_ms = asm_ms / max(asm_n, 1)
-    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    peak = PEAK[{"fp64": "fp64", "mixed": "bf16", "mixed_i8": "int8"}[best]]
-    line = {
-        "metric": METRIC,
-        "value": round(r["tflops"], 4),
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(r["ms_per_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": DTYPE[best],
-        "data": "synthetic",
-        "config": {"workload": wdesc, "flops_per_step": flops_step, "path": best},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get((args.workload, best)),
-                     "kernel": "assemble (ac|bd) batch", "launches": asm_n, "avg_launch_ms": avg_ms,
-                     "flops_per_launch": per_launch_flops},
-        "paths": {p: {k: v for k, v in results[p].items() if k != "kernels"} | {"kernels_ms": results[p]["kernels"]}
-                  for p in results},
-    }
-    if best != "fp64":
-        line["roofline"]["issued_bf16_tflops" if best == "mixed" else "issued_int8_tops"] = round(achieved * NPROD[best], 3)
-        line["roofline"]["issued_frac"] = round(achieved * NPROD[best] / peak, 4)
-    if "fp64" in results:
-        f = results["fp64"]
-        fa_ms, fa_n = f["kernels"].get("assemble", (0.0, 0))
-        fa = flops_assemble * args.steps / max(fa_n, 1) / (fa_ms / max(fa_n, 1) * 1e-3) / 1e12 if fa_ms else 0.0
-        line["roofline_fp64"] = {"bound": "mfma", "achieved": round(fa, 3), "peak": PEAK["fp64"],
-                                 "unit": "TFLOP/s", "frac": round(fa / PEAK["fp64"], 4),
-                                 "traffic": TRAFFIC.get((args.workload, "fp64"))}
-    if "fp64" in results and "mixed" in results:
-        line["mixed_speedup_vs_fp64"] = results["mixed"]["tflops"] / results["fp64"]["tflops"]
-    if "mixed_i8" in results and best != "mixed_i8":
-        # the 8-bit digit path: same algorithmic flops, int8 MFMA (thirteen digit products per term)
-        q = results["mixed_i8"]
-        qa_ms, qa_n = q["kernels"].get("assemble", (0.0, 0))
-        qa = flops_assemble * args.steps / max(qa_n, 1) / (qa_ms / max(qa_n, 1) * 1e-3) / 1e12 if qa_ms else 0.0
-        line["roofline_mixed_i8"] = {"bound": "mfma", "achieved": round(qa, 3), "peak": PEAK["int8"],
-                                     "unit": "TOP/s", "frac": round(qa / PEAK["int8"], 4),
-                                     "issued_int8_tops": round(qa * NPROD["mixed_i8"], 3),
-                                     "issued_frac": round(qa * NPROD["mixed_i8"] / PEAK["int8"], 4),
-                                     "traffic": TRAFFIC.get((args.workload, "mixed_i8")), "passes_gate": q["passes_gate"]}
-        if "fp64" in results:
-            line["mixed_i8_speedup_vs_fp64"] = q["tflops"] / results["fp64"]["tflops"]
-    if args.serving:
-        from paper_2512_21909_amd import serve
-        line["serving"] = serve.measure(best, n_requests=args.serving)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(entries, flops_step)
-    print(json.dumps(line), flush=True)
+    ladder_main(args, cdcc)
 
 
 if __name__ == "__main__":

@@ -28,6 +28,7 @@ __all__ = [
     "t2_ladder_loops", "t2_ladder_full", "t2_ladder_blocks", "t1_dressing_full",
     "lambda_w_full", "lambda_ladder_full", "lambda_ladder_blocks",
     "t2_ladder_symantisym_full", "pair_energies_full", "denominator_update_full",
+    "pair_energies_blocks", "denominator_update_blocks",
     "element_t2", "element_lambda", "rel_errors",
 ]
 
@@ -194,6 +195,42 @@ def denominator_update_full(R: np.ndarray, eps_occ: np.ndarray, eps_vir: np.ndar
     D = (eps_occ[:, None, None, None] + eps_occ[None, :, None, None]
          - eps_vir[None, None, :, None] - eps_vir[None, None, None, :])
     return R / D
+
+
+def pair_energies_blocks(sym: dict, X: dict, R: dict) -> np.ndarray:
+    """The pair functional of ``pair_energies_full`` on symmetry blocks
+    (no full tensor is formed): for the block (G, gi, ga) the exchange
+    partner X_ij^ba sits in block (G, gi, gb), gb = ga^G, with its last two
+    axes swapped.  Returns the (o_tot, o_tot) matrix e[I, J] with global
+    occupied indices."""
+    h, no = sym["h"], sym["nocc"]
+    off = np.concatenate([[0], np.cumsum(no)]).astype(int)
+    e = np.zeros((off[-1], off[-1]))
+    for G in range(h):
+        for gi in range(h):
+            gj = gi ^ G
+            for ga in range(h):
+                gb = ga ^ G
+                r = R[(G, gi, ga)]
+                if r.size == 0:
+                    continue
+                xt = 2.0 * X[(G, gi, ga)] - X[(G, gi, gb)].transpose(0, 1, 3, 2)
+                e[off[gi]:off[gi + 1], off[gj]:off[gj + 1]] += np.einsum("ijab,ijab->ij", xt, r)
+    return e
+
+
+def denominator_update_blocks(sym: dict, R: dict, eps_occ: list, eps_vir: list) -> dict:
+    """``denominator_update_full`` on symmetry blocks: R / (e_i + e_j - e_a -
+    e_b) with eps_occ[g], eps_vir[g] the orbital energies of irrep g."""
+    h = sym["h"]
+    out = {}
+    for (G, gi, ga), r in R.items():
+        gj, gb = gi ^ G, ga ^ G
+        D = (eps_occ[gi][:, None, None, None] + eps_occ[gj][None, :, None, None]
+             - eps_vir[ga][None, None, :, None] - eps_vir[gb][None, None, None, :])
+        out[(G, gi, ga)] = r / D if r.size else r.copy()
+    assert len(out) == h ** 3
+    return out
 
 
 # --------------------------------------------------------------------------

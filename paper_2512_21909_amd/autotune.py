@@ -4,7 +4,7 @@ tile_table.txt next to libcdcc.so (the library reads it when it builds a plan;
 the key is the exact symmetry shape, so a system's tile shape never depends on
 what else is in its batch).
 
-Usage (on the GPU): python -m paper_2512_21909_amd.autotune [--workloads ...]
+Usage (on the GPU): python -m paper_2512_21909_amd.autotune shapes.json
 """
 from __future__ import annotations
 
@@ -64,16 +64,32 @@ def time_classes(cdcc, dev_problem: dict, kind: str, precision: str, reps: int =
     return out
 
 
+def random_problem(cdcc, sym: dict, kind: str, seed: int = 0) -> dict:
+    """Device buffers of one ladder call with random values of a realistic
+    scale (timing does not depend on the values; the tile class never changes
+    an element's arithmetic)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    lay = cdcc.Layout(sym)
+
+    def rnd(n, scale):
+        return torch.randn(max(n, 1), generator=g, dtype=torch.float64, device="cuda")[:n] * scale
+
+    d = {"layout": lay, "B": rnd(lay.b_size, 1.0), "X": rnd(lay.amp_size, 1e-3),
+         "R": torch.empty(lay.amp_size, dtype=torch.float64, device="cuda")}
+    if kind == "lambda":
+        d["Bvo"], d["t1"] = rnd(lay.bvo_size, 1.0), rnd(lay.t1_size, 1e-3)
+    return d
+
+
 def tune(syms: list[dict], kinds=("t2", "lambda"), precisions=("fp64", "mixed", "mixed_i8"), seed: int = 0,
          table: dict | None = None, log=print) -> dict:
-    import synth as S
     import paper_2512_21909_amd as cdcc
-    from tests.gpu_support import device_problem
     table = dict(table or {})
     for sym in syms:
         for kind in kinds:
-            p = S.make_problem(sym, seed=seed, kind=kind)
-            d = device_problem(cdcc, p, nan_fill=False)
+            d = random_problem(cdcc, sym, kind, seed)
             for prec in precisions:
                 t = time_classes(cdcc, d, kind, prec)
                 best = min(range(len(t)), key=lambda c: t[c])
@@ -85,37 +101,20 @@ def tune(syms: list[dict], kinds=("t2", "lambda"), precisions=("fp64", "mixed", 
 
 
 def main():
-    import synth as S
+    """Tune the shapes listed in a JSON file: a list of {"nocc": [...],
+    "nvir": [...], "ncd": [...], "kinds": ["t2", "lambda"]} objects."""
+    import json
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--workloads", default="c1_small,d2h_medium,d2h_medium_B,serving_large,batch64")
+    ap.add_argument("shapes", help="JSON file with the shapes to tune")
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--precisions", default="fp64,mixed,mixed_i8", help="paths to tune (the others keep their entries)")
     args = ap.parse_args()
     precs = tuple(p for p in args.precisions.split(",") if p)
-    syms, kinds = [], {}
-    for w in args.workloads.split(","):
-        if w == "c1_small":
-            syms.append((S.sym_c1_small(), ("t2", "lambda")))
-        elif w == "d2h_medium":
-            syms.append((S.sym_d2h_medium("A"), ("t2", "lambda")))
-        elif w == "d2h_medium_B":
-            syms.append((S.sym_d2h_medium("B"), ("t2", "lambda")))
-        elif w == "d2h_large":
-            syms.append((S.sym_d2h_large(), ("t2", "lambda")))
-        elif w == "serving_large":
-            syms.append((S.sym_serving_large(), ("t2",)))
-        elif w == "batch64":
-            syms += [(s, ("t2",)) for s in S.batch_syms(64, seed=0)]
-        else:
-            raise SystemExit(f"unknown workload {w}")
     t0 = time.time()
     table = load_table(args.out)
-    for sym, ks in syms:
-        table = tune([sym], kinds=ks, precisions=precs, table=table)
+    for e in json.load(open(args.shapes)):
+        sym = {"h": len(e["nocc"]), "nocc": list(e["nocc"]), "nvir": list(e["nvir"]), "ncd": list(e["ncd"])}
+        table = tune([sym], kinds=tuple(e.get("kinds", ("t2",))), precisions=precs, table=table)
     write_table(table, args.out)
     _lib.load().cdcc_release()
     print(f"[autotune] {len(table)} entries -> {args.out} in {time.time() - t0:.1f} s")
-
-
-if __name__ == "__main__":
-    main()

@@ -133,6 +133,57 @@ struct SysPlan {
   int p1cls = 0;
 };
 
+// Completion marker of a plan's last enqueued work: recorded after every
+// call that uses the plan, waited for before the plan's device tables and
+// graphs are freed, so that evicting a plan never frees memory a queued
+// launch still reads.
+struct PlanFence {
+  hipEvent_t ev = nullptr;
+  bool recorded = false;
+  void mark(hipStream_t s) {
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      ev = nullptr;
+      (void)hipStreamSynchronize(s);  // no event: make the work complete now instead
+      return;
+    }
+    recorded = hipEventRecord(ev, s) == hipSuccess;
+  }
+  void wait() {
+    if (ev && recorded) (void)hipEventSynchronize(ev);
+    recorded = false;
+  }
+  ~PlanFence() {
+    wait();
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+// Plans by key, evicting the least recently used one beyond `cap` entries.
+template <class P>
+struct PlanCache {
+  explicit PlanCache(size_t c) : cap(c) {}
+  size_t cap;
+  uint64_t tick = 0;
+  std::map<std::string, std::pair<std::shared_ptr<P>, uint64_t>> m;
+  std::shared_ptr<P> find(const std::string &k) {
+    auto it = m.find(k);
+    if (it == m.end()) return nullptr;
+    it->second.second = ++tick;
+    return it->second.first;
+  }
+  void put(const std::string &k, std::shared_ptr<P> p) {
+    while (m.size() >= cap) {
+      auto lru = m.begin();
+      for (auto it = m.begin(); it != m.end(); ++it)
+        if (it->second.second < lru->second.second) lru = it;
+      m.erase(lru);  // the plan's destructor waits for its fence
+    }
+    m[k] = {std::move(p), ++tick};
+  }
+  void clear() { m.clear(); }
+  size_t size() const { return m.size(); }
+};
+
 struct Plan {
   int nsys = 0;
   int lambda = 0, dressed = 0, precision = 0;
@@ -166,7 +217,9 @@ struct Plan {
   int64_t xbuf_elems = 0;
   // captured launch sequences, keyed by the workspace base they were built for
   std::map<void *, hipGraphExec_t> graphs;
+  PlanFence fence;
   ~Plan() {
+    fence.wait();
     for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
     if (dtab) (void)hipFree(dtab);
   }
@@ -232,7 +285,7 @@ struct Span {
     g_spans.push_back({cls, n, a, b});
   }
 };
-std::map<std::string, std::shared_ptr<Plan>> g_plans;                 // key includes device
+PlanCache<Plan> g_plans(256);  // key includes device
 std::map<std::pair<int, void *>, std::unique_ptr<Workspace>> g_ws;  // (device, stream)
 
 int64_t env_i64(const char *name, int64_t dflt) {
@@ -901,9 +954,8 @@ int get_plan(int dev, int32_t nsys, const cdcc_problem_t *probs, int lambda, int
              std::shared_ptr<Plan> &out) {
   const int64_t cap = batch_cap(opts);
   const std::string key = plan_key(dev, nsys, probs, lambda, dressed, opts, cap);
-  auto it = g_plans.find(key);
-  if (it != g_plans.end()) {
-    out = it->second;
+  if (auto hit = g_plans.find(key)) {
+    out = hit;
     return CDCC_OK;
   }
   auto P = std::make_shared<Plan>();
@@ -911,8 +963,7 @@ int get_plan(int dev, int32_t nsys, const cdcc_problem_t *probs, int lambda, int
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) g_num_cu = ncu;
   const int rc = build_plan(nsys, probs, lambda, dressed, opts, cap, *P);
   if (rc != CDCC_OK) return rc;
-  if (g_plans.size() > 256) g_plans.clear();
-  g_plans[key] = P;
+  g_plans.put(key, P);
   out = P;
   return CDCC_OK;
 }
@@ -1065,7 +1116,11 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
   double *xbuf = reinterpret_cast<double *>(base + W.xbuf);
   double *part = reinterpret_cast<double *>(base + W.part);
   const bool use_graph = !g_timing && env_i64("CDCC_GRAPH", 1) != 0;
-  if (!use_graph) return enqueue_sequence(*P, dsp, counters, xbuf, part, stream);
+  if (!use_graph) {
+    rc = enqueue_sequence(*P, dsp, counters, xbuf, part, stream);
+    P->fence.mark(stream);
+    return rc;
+  }
   auto it = P->graphs.find(ws->dev);
   if (it == P->graphs.end()) {
     // capture the kernel sequence once per (plan, workspace) on a private stream
@@ -1086,6 +1141,7 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
     it = P->graphs.emplace(ws->dev, exec).first;
   }
   HIPCHK(hipGraphLaunch(it->second, stream));
+  P->fence.mark(stream);
   return CDCC_OK;
 }
 
@@ -1124,11 +1180,13 @@ struct DensPlan {
   int ncounters = 0;
   int64_t xbuf_elems = 0, part_elems = 0;
   std::vector<int64_t> t_elems;
+  PlanFence fence;
   ~DensPlan() {
+    fence.wait();
     if (dtab) (void)hipFree(dtab);
   }
 };
-std::map<std::string, std::shared_ptr<DensPlan>> g_dplans;
+PlanCache<DensPlan> g_dplans(64);
 
 int64_t vv_count(const cdcc_layout_t &L, int G) { return L.n_vv[G]; }
 
@@ -1392,16 +1450,12 @@ int run_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_op
     for (int g = 0; g < y.nirrep; ++g)
       key += "," + std::to_string(y.nocc[g]) + "," + std::to_string(y.nvir[g]) + "," + std::to_string(y.ncd[g]);
   }
-  std::shared_ptr<DensPlan> P;
-  auto it = g_dplans.find(key);
-  if (it != g_dplans.end()) {
-    P = it->second;
-  } else {
+  std::shared_ptr<DensPlan> P = g_dplans.find(key);
+  if (!P) {
     P = std::make_shared<DensPlan>();
     rc = build_density_plan(nsys, probs, cap, *P);
     if (rc != CDCC_OK) return rc;
-    if (g_dplans.size() > 64) g_dplans.clear();
-    g_dplans[key] = P;
+    g_dplans.put(key, P);
   }
   const DensWs W = dens_ws_layout(*P);
   Workspace *ws = nullptr;
@@ -1455,6 +1509,7 @@ int run_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_op
       HIPCHK(launch_density_reduce(B.rcount, P->gdesc, P->rjobs + B.rstart, ddp, part, stream));
     }
   }
+  P->fence.mark(stream);
   return CDCC_OK;
 }
 
@@ -1476,11 +1531,13 @@ struct PmPlan {
   PmChunk *lchunks = nullptr, *tchunks = nullptr;
   int nlchunks = 0, ntchunks = 0;
   std::vector<int64_t> ws_elems;
+  PlanFence fence;
   ~PmPlan() {
+    fence.wait();
     if (dtab) (void)hipFree(dtab);
   }
 };
-std::map<std::string, std::shared_ptr<PmPlan>> g_pmplans;
+PlanCache<PmPlan> g_pmplans(64);
 
 int build_pm_plan(int nsys, const cdcc_partial_problem_t *probs, PmPlan &P) {
   constexpr int BM = 64;
@@ -1602,16 +1659,12 @@ int run_partial(int32_t nsys, const cdcc_partial_problem_t *probs, const cdcc_op
     key += "|" + std::to_string(y.nirrep);
     for (int g = 0; g < y.nirrep; ++g) key += "," + std::to_string(y.nocc[g]) + "," + std::to_string(y.nvir[g]);
   }
-  std::shared_ptr<PmPlan> P;
-  auto it = g_pmplans.find(key);
-  if (it != g_pmplans.end()) {
-    P = it->second;
-  } else {
+  std::shared_ptr<PmPlan> P = g_pmplans.find(key);
+  if (!P) {
     P = std::make_shared<PmPlan>();
     rc = build_pm_plan(nsys, probs, *P);
     if (rc != CDCC_OK) return rc;
-    if (g_pmplans.size() > 64) g_pmplans.clear();
-    g_pmplans[key] = P;
+    g_pmplans.put(key, P);
   }
   int64_t total = align_up(int64_t(nsys) * int64_t(sizeof(PmPtrs)));
   std::vector<int64_t> wofs(nsys);
@@ -1645,6 +1698,7 @@ int run_partial(int32_t nsys, const cdcc_partial_problem_t *probs, const cdcc_op
     Span sp(10, P->ntiles > 0, stream);
     HIPCHK(launch_pm_gemm(P->descs, P->tiles, P->ntiles, P->sqs, dpp, stream));
   }
+  P->fence.mark(stream);
   return CDCC_OK;
 }
 
@@ -2115,11 +2169,11 @@ extern "C" int cdcc_vvvv_density(int32_t nsys, const cdcc_density_problem_t *pro
 
 extern "C" int cdcc_release(void) {
   std::lock_guard<std::mutex> lock(g_mu);
-  g_dplans.clear();
-  g_pmplans.clear();
   delete g_tile_table;  // re-read on the next plan
   g_tile_table = nullptr;
   if (hipDeviceSynchronize() != hipSuccess) return CDCC_EDEVICE;
+  g_dplans.clear();
+  g_pmplans.clear();
   g_ws.clear();
   g_plans.clear();
   for (auto &c : g_capture_streams) (void)hipStreamDestroy(c.second);

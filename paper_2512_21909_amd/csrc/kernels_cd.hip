@@ -8,7 +8,7 @@
 // The integral matrix is given per irrep as a dense symmetric matrix V (rows
 // and columns: the basis-function pairs of the irrep).
 //
-// First step, per macro iteration (host loop in cd.cpp):
+// First step, per macro iteration (host loop in cdcc.cpp, cdcc_cd_basis):
 //   gather     M[r][slot] = V[r][q_slot] for the qualified pairs q of an irrep
 //   gemm_nt    M -= L1 L1[Q]^T (the vectors of earlier macro iterations)
 //   micro      one launch per micro iteration: pivot = the first largest

@@ -6,12 +6,23 @@
 //
 // BF16 (CDCC_MIXED).  sigma >= max|x|, exponent-aligned BF16 slices
 //   y = x / sigma = s0 + s1 + s2 + s3 + r,   s_t = m_t 2^-8(t+1), |m_t| <= 256,
-// so that |r| <= 2^-33.  The ten slice products with t + u <= 3 are formed.
-// The leading product s0 * s0 has 16-bit integer
-// terms in units of 2^-16: accumulated in FP32 on MFMA it is exact for up to
-// 256 terms, so it is flushed into an FP64 total every 256 K.  The nine
-// lower-order products go to a second FP32 accumulator (their rounding is
-// 2^-32 relative to the result scale) and are flushed at the same points.
+// so that |r| <= 2^-33.  Eleven slice products are formed: the ten with
+// t + u <= 3 and s2 * s2.  The last one matters beyond its size: on the
+// diagonal of the product (both operand rows the same row, and its
+// transpose for symmetric vectors) a dropped s_t * s_t is a square, positive
+// in every term, and the pair energies weight those diagonal products
+// coherently; without s2 * s2 they came out 3-5e-9 too small relative to
+// their value (up to 1.1e-8 Eh at |e_ij| = 3.6), with it the bias is gone
+// and the first dropped square is s3 * s3, 2^-16 smaller.  The products go
+// to three FP32 accumulators, flushed into an FP64 total every 256 K:
+//   weight 0, s0 * s0: integer terms of at most 2^16 units of 2^-16, exact in
+//     FP32 for 256 K;
+//   weight 1, s0 * s1 and s1 * s0 (|m_1| <= 128): terms of at most 2^15 units
+//     of 2^-24, two per K, exact for 256 K as well;
+//   weights 2 to 4, the other eight: these alone are rounded, at 2^-24 of a
+//     sum that is itself about 2^-16 of the result scale (MFMA rounds each
+//     accumulation once; sums with bits below the accumulator's last place
+//     drift slightly toward zero, so the exact sums are kept apart).
 //
 // 8-bit digits (CDCC_MIXED_I8).  y = x / sigma = sum_t m_t 2^-(7+8t) + r with
 // signed digits m_0 in [-126, 127], m_t in [-128, 127] (t >= 1) and
@@ -319,8 +330,9 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
         lds_copy16(src[i] + int64_t(kb) * ROWB, st + (i * NW + wave) * 8 * ROWB);
     };
 
-    // BF16 state
-    f16v acc0[NJ], acc1[NJ];
+    // BF16 state: acc0 the leading product, acc1 the two products of weight
+    // one, acc2 the eight of weights two to four
+    f16v acc0[NJ], acc1[NJ], acc2[NJ];
     double tot[NJ][16];
     // I8 state: accumulator w holds the products of weight t + u = w
     i16v iacc[5][NJ];
@@ -328,9 +340,10 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) tot[j][r] += double(acc0[j][r]) + double(acc1[j][r]);
+        for (int r = 0; r < 16; ++r) tot[j][r] += double(acc0[j][r]) + (double(acc1[j][r]) + double(acc2[j][r]));
         acc0[j] = f16v{};
         acc1[j] = f16v{};
+        acc2[j] = f16v{};
       }
     };
     // fragment byte offsets inside a stage: slice s of row r is logical
@@ -351,7 +364,7 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
     // I8 step in two parts: every fragment of the block is read before the
     // next block's copies are issued (with the reads after the copies, the
     // compiler's LDS-DMA wait tracking falls back to waiting for every copy
-    // in flight, which drains the ring), then the ten products
+    // in flight, which drains the ring), then the thirteen products
     i4v fa[4], fb[NJ][4];
     auto read_i8 = [&](const unsigned char *L) {
 #pragma unroll
@@ -398,14 +411,15 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
             b[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + boff[j][s]) ^ flip);
           acc0[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], acc0[j], 0, 0, 0);
           acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], acc1[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc2[j], 0, 0, 0);
           acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[3], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[2], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[1], acc1[j], 0, 0, 0);
-          acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[0], acc1[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], acc2[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], acc2[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[3], acc2[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[2], acc2[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[1], acc2[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[3], b[0], acc2[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[2], acc2[j], 0, 0, 0);
         }
         if ((kb & 15) == 15 || kb == nkb - 1) flush();  // every 256 K: keep the leading accumulator exact
       }
@@ -437,6 +451,7 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
         } else {
           acc0[j] = f16v{};
           acc1[j] = f16v{};
+          acc2[j] = f16v{};
 #pragma unroll
           for (int r = 0; r < 16; ++r) tot[j][r] = 0.0;
         }

@@ -21,10 +21,8 @@ is bitwise the same alone and in a mix.
 """
 from __future__ import annotations
 
-import argparse
 import collections
 import dataclasses
-import json
 import time
 
 from . import _lib
@@ -225,29 +223,6 @@ def latency_stats(reqs: list[Request]) -> dict:
             "requests_per_s": len(done) / span if span > 0 else 0.0}
 
 
-def request_pool(n_shapes: int = 12, seed: int = 5, with_large: bool = True):
-    """Device-resident inputs for a pool of request shapes drawn like the
-    uneven batch, plus one large request (o=30, v=300, 2500 vectors)."""
-    import numpy as np
-    import torch
-
-    import synth as S
-
-    def dev(x):
-        return torch.from_numpy(np.ascontiguousarray(x)).cuda()
-
-    syms = S.batch_syms(n_shapes, seed=seed)
-    if with_large:
-        syms.append(S.sym_serving_large())
-    pool = []
-    for k, sym in enumerate(syms):
-        p = S.make_problem(sym, seed=100 + k, kind="t2")
-        lay = Layout(sym)
-        pool.append({"layout": lay, "B": dev(lay.pack_B(p["B"])), "X": dev(lay.pack_amp(p["X"])),
-                     "flops": sum(lay.flops(0)), "large": with_large and k == len(syms) - 1})
-    return pool
-
-
 def make_stream(pool, n: int, rate_hz: float, seed: int = 5, p_large: float = 0.1, want_energy=True):
     """Poisson arrivals; each request takes a pool shape (large with
     probability p_large, else a uniformly drawn small shape)."""
@@ -264,26 +239,20 @@ def make_stream(pool, n: int, rate_hz: float, seed: int = 5, p_large: float = 0.
     return reqs
 
 
-def measure(precision="fp64", n_requests=300, load=0.7, n_streams=3, max_batch=16, seed=5):
-    """Saturation throughput of the mix (all requests at t=0), then a Poisson
-    stream at ``load`` times that rate; returns both stats."""
-    import torch
-    free, total = torch.cuda.mem_get_info()
-    budget = int(free * 0.6)
-    pool = request_pool(seed=seed)
-    # warm-up: plans and workspaces for every shape
-    LadderServer(budget, n_streams, precision, max_batch).serve(make_stream(pool, 2 * len(pool), 0, seed + 1))
-    sat_reqs = make_stream(pool, n_requests, 0.0, seed)
-    sat = latency_stats(LadderServer(budget, n_streams, precision, max_batch).serve(sat_reqs))
-    rate = load * sat["requests_per_s"]
-    reqs = make_stream(pool, n_requests, rate, seed)
-    st = latency_stats(LadderServer(budget, n_streams, precision, max_batch).serve(reqs))
-    return {"precision": precision, "saturation": sat, "rate_hz": rate, "load": load, "stream": st,
-            "n_streams": n_streams, "max_batch": max_batch, "hbm_budget_bytes": budget}
+def measure(pool, precision="fp64", n_requests=2000, warmup=200, load=0.7, n_streams=3, max_batch=16, seed=5):
+    """Warm-up (``warmup`` requests at t=0, at least two per pool shape, not
+    counted), saturation throughput of the mix (``n_requests`` at t=0), then a
+    Poisson stream of ``n_requests`` at ``load`` times that rate.  ``pool``:
+    device-resident request inputs (dicts with layout, B, X, flops, large)."""
+    out = measure_sweep(pool, precision, n_requests, (load,), n_streams, max_batch, seed, warmup)
+    st = out.pop("streams")[0]
+    out["load"], out["rate_hz"] = st.pop("load"), st.pop("rate_hz")
+    out["stream"] = st
+    return out
 
 
-def measure_sweep(precision="fp64", n_requests=2000, loads=(0.3, 0.5, 0.7, 0.9), n_streams=3, max_batch=16,
-                  seed=5, warmup=200, log=None):
+def measure_sweep(pool, precision="fp64", n_requests=2000, loads=(0.3, 0.5, 0.7, 0.9), n_streams=3,
+                  max_batch=16, seed=5, warmup=200, log=None):
     """Warm-up (``warmup`` requests at t=0, at least two per pool shape, not
     counted), saturation throughput of the mix, then one Poisson stream of
     ``n_requests`` per entry of ``loads`` (a fraction of the saturation
@@ -291,7 +260,6 @@ def measure_sweep(precision="fp64", n_requests=2000, loads=(0.3, 0.5, 0.7, 0.9),
     import torch
     free, total = torch.cuda.mem_get_info()
     budget = int(free * 0.6)
-    pool = request_pool(seed=seed)
 
     def server():
         return LadderServer(budget, n_streams, precision, max_batch)
@@ -309,27 +277,3 @@ def measure_sweep(precision="fp64", n_requests=2000, loads=(0.3, 0.5, 0.7, 0.9),
         if log:
             log(f"{precision} load {load}: p50 {st.get('p50_ms', 0):.2f} ms, p99 {st.get('p99_ms', 0):.2f} ms")
     return out
-
-
-def main():
-    import sys
-    ap = argparse.ArgumentParser(description="serving loop of the ladder library")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_i8"])
-    ap.add_argument("--requests", type=int, default=300)
-    ap.add_argument("--load", type=float, default=0.7)
-    ap.add_argument("--loads", default=None,
-                    help="comma-separated loads: saturation once, then one Poisson stream per load")
-    ap.add_argument("--warmup", type=int, default=200, help="warm-up requests of a --loads sweep")
-    ap.add_argument("--streams", type=int, default=3)
-    args = ap.parse_args()
-    if args.loads:
-        loads = [float(x) for x in args.loads.split(",")]
-        res = measure_sweep(args.precision, args.requests, loads, args.streams, warmup=args.warmup,
-                            log=lambda m: print(m, file=sys.stderr, flush=True))
-    else:
-        res = measure(args.precision, args.requests, args.load, args.streams)
-    print(json.dumps(res))
-
-
-if __name__ == "__main__":
-    main()

@@ -1,4 +1,5 @@
-"""Serving loop: results identical alone and in the mix, admission by HBM
+"""Serving loop: results identical alone and in the mix (the large
+o=30/v=300 request included) and equal to the oracle, admission by HBM
 footprint, and clean failure of one request without failing the others."""
 import os
 
@@ -11,13 +12,17 @@ from tests.gpu_support import to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _pool(cdcc, syms, seed=0):
+def _pool(cdcc, syms, seed=0, large=None, keep=False):
+    """Device-resident request inputs; ``large`` marks the last shape as the
+    large request; ``keep`` also returns the generator problems."""
     pool = []
     for k, sym in enumerate(syms):
         p = S.make_problem(sym, seed=seed + k, kind="t2")
         lay = cdcc.Layout(sym)
         pool.append({"layout": lay, "B": to_dev(lay.pack_B(p["B"])), "X": to_dev(lay.pack_amp(p["X"])),
-                     "flops": sum(lay.flops(0)), "large": False})
+                     "flops": sum(lay.flops(0)), "large": bool(large) and k == len(syms) - 1})
+        if keep:
+            pool[-1]["prob"] = p
     return pool
 
 
@@ -95,10 +100,52 @@ def test_load_sweep_reports_every_load(gpu_lib):
     """The sweep measures saturation once and one Poisson stream per load;
     every request of every run completes."""
     from paper_2512_21909_amd import serve
-    out = serve.measure_sweep("mixed", n_requests=24, loads=(0.3, 0.9), warmup=4, max_batch=4)
+    pool = _pool(gpu_lib, S.batch_syms(4, seed=9))
+    out = serve.measure_sweep(pool, "mixed", n_requests=24, loads=(0.3, 0.9), warmup=4, max_batch=4)
     assert out["saturation"]["done"] == 24 and out["saturation"]["requests_per_s"] > 0
     assert [s["load"] for s in out["streams"]] == [0.3, 0.9]
     for s in out["streams"]:
         assert s["done"] == 24 and s["rejected"] == 0 and s["failed"] == 0
         assert s["rate_hz"] == pytest.approx(s["load"] * out["saturation"]["requests_per_s"])
         assert 0 < s["p50_ms"] <= s["p99_ms"]
+
+
+_MIX_REF = {}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mix_with_the_large_request_matches_alone_and_oracle(gpu_lib, precision):
+    """The serving mix with the large request (o=30, v=300, 2500 vectors, 8
+    irreps, drawn with probability 0.3 here so that it lands in batches with
+    small ones): every request completes, equals its standalone result
+    bitwise, and every distinct shape matches the oracle (R normwise, pair
+    energies) within the path's tolerance."""
+    import torch
+    import oracle as O
+    from paper_2512_21909_amd import serve
+    pool = _pool(gpu_lib, S.batch_syms(5, seed=11) + [S.sym_serving_large()], seed=40, large=True, keep=True)
+    reqs = serve.make_stream(pool, 30, 0.0, seed=3, p_large=0.3)
+    assert 3 <= sum(r.layout is pool[-1]["layout"] for r in reqs) < 30
+    srv = serve.LadderServer(int(torch.cuda.mem_get_info()[0] * 0.5), n_streams=3, precision=precision, max_batch=6)
+    done = srv.serve(reqs)
+    assert sorted(r.rid for r in done) == list(range(30)) and all(r.status == "done" for r in done)
+    tol = 1e-12 if precision == "fp64" else 1e-7
+    checked = set()
+    for r in done:
+        Ra, Ea = _alone(gpu_lib, r, precision)
+        assert np.array_equal(r.R.cpu().numpy(), Ra), r.rid
+        assert np.array_equal(r.pair_energy.cpu().numpy(), Ea), r.rid
+        k = next(i for i, p in enumerate(pool) if p["layout"] is r.layout)
+        if k in checked:
+            continue
+        checked.add(k)
+        p = pool[k]["prob"]
+        if k not in _MIX_REF:
+            ref = O.t2_ladder_blocks(p["sym"], p["B"], p["X"])
+            _MIX_REF[k] = (ref, O.pair_energies_blocks(p["sym"], p["X"], ref))
+        ref, e_ref = _MIX_REF[k]
+        mx, fro = O.rel_errors(r.layout.unpack_amp(Ra), ref)
+        assert mx <= tol and fro <= tol, (k, mx, fro)
+        err_e = float(np.max(np.abs(Ea.reshape(e_ref.shape) - e_ref)))
+        assert err_e <= (1e-12 * max(1.0, float(np.max(np.abs(e_ref)))) if precision == "fp64" else 1e-8), (k, err_e)
+    assert len(pool) - 1 in checked
