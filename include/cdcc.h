@@ -48,6 +48,8 @@ extern "C" {
 #define CDCC_ENOMEM       -2  /* device workspace could not be allocated        */
 #define CDCC_EUNSUPPORTED -3  /* e.g. irrep count not in {1,2,4,8}              */
 #define CDCC_EDEVICE      -4  /* HIP runtime error, or no gfx950 device         */
+#define CDCC_ESCRATCH     -5  /* needs more than the static scratch of         */
+                              /* cdcc_ladder_t2_noalloc                          */
 
 #define CDCC_FP64  0  /* FP64 MFMA throughout                                     */
 #define CDCC_MIXED 1  /* split-BF16 MFMA, FP32 accumulation, FP64 combination     */
@@ -344,6 +346,25 @@ int cdcc_workspace_bytes(int32_t nsys, const cdcc_problem_t *probs,
 #define CDCC_TIMING_CLASSES 14
 int cdcc_timing_enable(int32_t on);
 int cdcc_timing_read(double ms[CDCC_TIMING_CLASSES], int64_t launches[CDCC_TIMING_CLASSES]);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the T2
+ * ladder of cdcc_ladder_t2, same arguments, results and errors, computed
+ * without any device or pinned-host allocation.  Plan tables and workspace
+ * live in a static device array of CDCC_NOALLOC_SCRATCH_BYTES that every GPU
+ * the library runs on holds until the process ends; the (ac|bd) batch is
+ * sized to what is left of it.  A call whose tables and workspace do not fit
+ * returns CDCC_ESCRATCH before anything is enqueued.  The launches are
+ * enqueued directly (no graph); plans are cached on the host.  All calls on
+ * one GPU share the array: calls that overlap in time on one GPU (other
+ * streams, or unordered host threads) race and must be serialised by the
+ * caller; consecutive calls on one stream are ordered and each call writes
+ * every byte it reads.
+ */
+#define CDCC_NOALLOC_SCRATCH_BYTES (256ll << 20)
+int cdcc_ladder_t2_noalloc(int32_t nsys, const cdcc_problem_t *probs,
+                           const cdcc_opts_t *opts, void *stream);
 
 /* Static, human-readable text for a status code. */
 const char *cdcc_status_string(int status);

@@ -8,7 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcdcc.so")
 
 MAX_IRREP = 8
-OK, EINVAL, ENOMEM, EUNSUPPORTED, EDEVICE = 0, -1, -2, -3, -4
+OK, EINVAL, ENOMEM, EUNSUPPORTED, EDEVICE, ESCRATCH = 0, -1, -2, -3, -4, -5
 FP64, MIXED, MIXED_I8 = 0, 1, 2
 
 _i32, _i64 = ctypes.c_int32, ctypes.c_int64
@@ -77,7 +77,8 @@ class Opts(ctypes.Structure):
 EXPORTS = ["cdcc_irrep_layout", "cdcc_ladder_t2", "cdcc_ladder_lambda", "cdcc_ladder_flops",
            "cdcc_workspace_bytes", "cdcc_timing_enable", "cdcc_timing_read", "cdcc_status_string",
            "cdcc_release", "cdcc_vvvv_density", "cdcc_density_flops", "cdcc_vo_layout",
-           "cdcc_partial_contract", "cdcc_partial_flops", "cdcc_cd_basis", "cdcc_cd_vectors"]
+           "cdcc_partial_contract", "cdcc_partial_flops", "cdcc_cd_basis", "cdcc_cd_vectors",
+           "cdcc_ladder_t2_noalloc"]
 
 _lib = None
 
@@ -92,7 +93,7 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     lib.cdcc_irrep_layout.argtypes = [ctypes.POINTER(Sym), ctypes.POINTER(LayoutC)]
     lib.cdcc_irrep_layout.restype = ctypes.c_int
-    for name in ("cdcc_ladder_t2", "cdcc_ladder_lambda"):
+    for name in ("cdcc_ladder_t2", "cdcc_ladder_lambda", "cdcc_ladder_t2_noalloc"):
         f = getattr(lib, name)
         f.argtypes = [_i32, ctypes.POINTER(Problem), ctypes.POINTER(Opts), ctypes.c_void_p]
         f.restype = ctypes.c_int

@@ -17,7 +17,7 @@ OUT = os.path.join(PKG, "libcdcc.so")
 BUILD = os.path.join(PKG, "_build")
 
 HIP_SOURCES = ["kernels_f64.hip", "kernels_mixed.hip", "kernels_density.hip", "kernels_partial.hip",
-               "kernels_cd.hip"]
+               "kernels_cd.hip", "noalloc.hip"]
 CXX_SOURCES = ["layout.cpp", "cdcc.cpp"]
 
 ARCH = "gfx950"

@@ -217,6 +217,9 @@ struct Plan {
   int64_t xbuf_elems = 0;
   // captured launch sequences, keyed by the workspace base they were built for
   std::map<void *, hipGraphExec_t> graphs;
+  // plans for a caller-provided table region (allocation-free entry point):
+  // the tables are kept on the host and copied to that region on every call
+  std::vector<char> host_tables;
   PlanFence fence;
   ~Plan() {
     fence.wait();
@@ -428,8 +431,11 @@ void pair_table(const int32_t *n, int h, int G, const int64_t off[CDCC_MAX_IRREP
   }
 }
 
+// table_base: NULL = the plan allocates and fills its device tables; else the
+// tables are laid out for that device address and kept on the host
+// (P.host_tables), and the caller copies them there before every use.
 int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, const cdcc_opts_t &opts, int64_t cap,
-               Plan &P) {
+               Plan &P, void *table_base = nullptr) {
   P.nsys = nsys;
   P.lambda = lambda;
   P.dressed = dressed;
@@ -855,9 +861,15 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
   const int64_t o_kt = T.add(ktab), o_ij = T.add(ijtab), o_vv = T.add(vvtab), o_vf = T.add(vvfull);
   const int64_t o_ej = T.add(ejobs), o_sj = T.add(slicejobs), o_sr = T.add(slicerows);
   const int64_t o_rj = T.add(redjobs);
-  if (hipMalloc(&P.dtab, std::max<size_t>(T.bytes.size(), 256)) != hipSuccess) return CDCC_ENOMEM;
-  if (hipMemcpy(P.dtab, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return CDCC_EDEVICE;
-  char *b = static_cast<char *>(P.dtab);
+  char *b = nullptr;
+  if (table_base) {
+    P.host_tables = std::move(T.bytes);
+    b = static_cast<char *>(table_base);
+  } else {
+    if (hipMalloc(&P.dtab, std::max<size_t>(T.bytes.size(), 256)) != hipSuccess) return CDCC_ENOMEM;
+    if (hipMemcpy(P.dtab, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return CDCC_EDEVICE;
+    b = static_cast<char *>(P.dtab);
+  }
   P.packjobs = reinterpret_cast<PackJob *>(b + o_pj);
   P.packrows = reinterpret_cast<int2 *>(b + o_pr);
   P.npackrows = int(packrows.size());
@@ -2110,6 +2122,113 @@ extern "C" int cdcc_partial_contract(int32_t nsys, const cdcc_partial_problem_t 
   return run_partial(nsys, probs, opts, stream);
 }
 
+// ===========================================================================
+// The T2 ladder on a caller-provided device region (the allocation-free entry
+// point in noalloc.hip passes the library's static scratch array).  Region
+// layout: [0, kScratchTables) the plan's tables, then the workspace of the
+// call (counters, pointer table, (ac|bd) batch, split-K partials, packed
+// amplitudes, slices).  The batch cap is lowered until the workspace fits.
+// Nothing is allocated: plans keep their tables on the host and copy them
+// into the region, with the pointer table, by ordinary asynchronous copies;
+// the launches are enqueued directly (no graph).  Every byte the kernels read
+// is written in the same call before it is read (the queue counters are
+// cleared by a fill kernel), so a region holding an earlier call's data gives
+// the same result.
+// ===========================================================================
+namespace {
+constexpr int64_t kScratchTables = int64_t(16) << 20;
+PlanCache<Plan> g_scratch_plans(64);
+
+struct ScratchHost {
+  std::vector<SysPtrs> sysptrs;  // host source of the pointer table copy
+  hipEvent_t ev = nullptr;       // the previous copy out of sysptrs has completed
+  bool recorded = false;
+};
+std::map<int, ScratchHost> g_scratch_host;
+}  // namespace
+
+int run_ladder_in_region(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *popts, void *vstream,
+                         void *region, int64_t region_bytes) {
+  cdcc_opts_t opts{};
+  if (popts) opts = *popts;
+  if (opts.precision != CDCC_FP64 && !is_split(opts.precision)) return CDCC_EINVAL;
+  if (opts.tile_policy < 0 || opts.tile_policy > 4) return CDCC_EINVAL;
+  if (opts.tile_policy == 4 && !is_split(opts.precision)) return CDCC_EINVAL;
+  if (!region || region_bytes <= kScratchTables) return CDCC_EINVAL;
+  int dressed = 0;
+  int rc = validate(nsys, probs, 0, &dressed);
+  if (rc != CDCC_OK) return rc;
+  hipStream_t stream = static_cast<hipStream_t>(vstream);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_mu);
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) g_num_cu = ncu;
+  }
+  char *tables = static_cast<char *>(region);
+  const int64_t avail = region_bytes - kScratchTables;
+  const std::string key = "region|" + std::to_string(reinterpret_cast<uintptr_t>(region)) + "|" +
+                          std::to_string(region_bytes) + "|" + plan_key(dev, nsys, probs, 0, 0, opts, batch_cap(opts));
+  std::shared_ptr<Plan> P = g_scratch_plans.find(key);
+  if (!P) {
+    // the batch cap: the caller's (or the default), lowered until the whole
+    // workspace fits the region
+    int64_t cap = std::min<int64_t>(batch_cap(opts), avail);
+    for (int tries = 0;; ++tries) {
+      auto Q = std::make_shared<Plan>();
+      rc = build_plan(nsys, probs, 0, 0, opts, cap, *Q, tables);
+      if (rc != CDCC_OK) return rc;
+      if (int64_t(Q->host_tables.size()) > kScratchTables) return CDCC_ESCRATCH;
+      const int64_t total = ws_layout(*Q).total;
+      if (total <= avail) {
+        P = Q;
+        break;
+      }
+      const int64_t rest = total - Q->xbuf_elems * 8;  // everything but the batch buffer
+      if (rest >= avail || tries >= 8 || cap <= (1 << 16)) return CDCC_ESCRATCH;
+      cap = std::max<int64_t>(1 << 16, std::min(cap / 2, avail - rest));
+    }
+    g_scratch_plans.put(key, P);
+  }
+  const WsLayout W = ws_layout(*P);
+  char *base = tables + kScratchTables;
+  ScratchHost &H = g_scratch_host[dev];
+  if (!H.ev && hipEventCreateWithFlags(&H.ev, hipEventDisableTiming) != hipSuccess) {
+    H.ev = nullptr;
+    return CDCC_EDEVICE;
+  }
+  if (H.recorded) HIPCHK(hipEventSynchronize(H.ev));
+  H.sysptrs.resize(size_t(nsys));
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_problem_t &p = probs[s];
+    SysPtrs q{};
+    q.opnd = p.B;
+    q.X = p.X;
+    q.R = p.R;
+    q.delta = p.delta;
+    q.eps_occ = p.eps_occ;
+    q.eps_vir = p.eps_vir;
+    q.epair = p.pair_energy;
+    q.tauhat = reinterpret_cast<double *>(base + W.th[s]);
+    q.B = p.B;
+    q.slices = reinterpret_cast<unsigned char *>(base + W.sl[s]);
+    q.rowscale = reinterpret_cast<double *>(base + W.sc[s]);
+    H.sysptrs[size_t(s)] = q;
+  }
+  SysPtrs *dsp = reinterpret_cast<SysPtrs *>(base + W.sysptrs);
+  HIPCHK(hipMemcpyAsync(tables, P->host_tables.data(), P->host_tables.size(), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(dsp, H.sysptrs.data(), size_t(nsys) * sizeof(SysPtrs), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(H.ev, stream));
+  H.recorded = true;
+  int *counters = reinterpret_cast<int *>(base + W.counters);
+  double *xbuf = reinterpret_cast<double *>(base + W.xbuf);
+  double *part = reinterpret_cast<double *>(base + W.part);
+  rc = enqueue_sequence(*P, dsp, counters, xbuf, part, stream);
+  P->fence.mark(stream);
+  return rc;
+}
+
 extern "C" int cdcc_ladder_t2(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *opts, void *stream) {
   return run_ladder(nsys, probs, opts, stream, 0);
 }
@@ -2176,6 +2295,10 @@ extern "C" int cdcc_release(void) {
   g_pmplans.clear();
   g_ws.clear();
   g_plans.clear();
+  g_scratch_plans.clear();
+  for (auto &h : g_scratch_host)
+    if (h.second.ev) (void)hipEventDestroy(h.second.ev);
+  g_scratch_host.clear();
   for (auto &c : g_capture_streams) (void)hipStreamDestroy(c.second);
   g_capture_streams.clear();
   for (const TimedSpan &t : g_spans) {

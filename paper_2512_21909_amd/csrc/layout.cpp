@@ -230,6 +230,7 @@ extern "C" const char *cdcc_status_string(int status) {
     case CDCC_ENOMEM: return "device workspace allocation failed";
     case CDCC_EUNSUPPORTED: return "unsupported (irrep count must be 1, 2, 4 or 8)";
     case CDCC_EDEVICE: return "HIP runtime error or no gfx950 device";
+    case CDCC_ESCRATCH: return "problem needs more device memory than the static scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

@@ -91,6 +91,19 @@ def ladder_t2(problems, precision="fp64", stream=None, tile_policy=0, batch_byte
     _lib.check(st, "cdcc_ladder_t2")
 
 
+def ladder_t2_noalloc(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0) -> None:
+    """The T2 ladder of ``ladder_t2`` without any device allocation: plan
+    tables and workspace in the library's static scratch array (calls that
+    overlap on one GPU race).  Raises CdccError with status ESCRATCH when the
+    problem does not fit it."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr, keep = make_problems(problems, False)
+    o = _opts(precision, tile_policy, batch_bytes)
+    st = _lib.load().cdcc_ladder_t2_noalloc(len(problems), arr, ctypes.byref(o), _stream(stream))
+    _lib.check(st, "cdcc_ladder_t2_noalloc")
+
+
 def ladder_lambda(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0) -> None:
     """Lambda ladder Z_ij^ab = sum_ef lambda_ij^ef W_efab (Appendix-A W)."""
     if isinstance(problems, dict):
