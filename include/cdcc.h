@@ -119,6 +119,9 @@ typedef struct {
   const double *eps_vir;     /* device, lay->nvir_tot, or NULL                  */
   double *delta;             /* device out, lay->amp_size, or NULL              */
   double *pair_energy;       /* device out, nocc_tot*nocc_tot, or NULL          */
+  const double *U;           /* Lambda only: device, 2*lay->b_size, the dressed */
+                             /* stack of cdcc_lambda_dress (Bvo, t1 unused), or */
+                             /* NULL; must be NULL for the T2 ladder            */
 } cdcc_problem_t;
 
 typedef struct {
@@ -127,6 +130,10 @@ typedef struct {
                              /* 1..3 (FP64), 1..4 (the two split precisions)   */
   int64_t batch_bytes;       /* cap of the (ac|bd) batch buffer, 0 = default    */
                              /* (4 GiB, or CDCC_BATCH_MB megabytes)             */
+  int32_t contract_kseg;     /* K-table entries per contraction segment (split */
+                             /* K), 0 = tile table, else the built-in rule;    */
+                             /* changes the rounding order of S and A only     */
+  int32_t pad0;
 } cdcc_opts_t;
 
 /*
@@ -151,10 +158,44 @@ int cdcc_ladder_t2(int32_t nsys, const cdcc_problem_t *probs,
 /*
  * Lambda ladder Z_ij^ab = sum_ef lambda_ij^ef W_efab with the Appendix-A
  * W_efab (X = lambda, R = Z).  Same conventions and errors as cdcc_ladder_t2;
- * Bvo and t1 must be both set or both NULL.
+ * Bvo and t1 must be both set or both NULL.  With U set (the stack of
+ * cdcc_lambda_dress for these B, Bvo and t1) the dressing is not rebuilt:
+ * the result is the dressed ladder, bitwise the same as with Bvo and t1 in
+ * FP64.  All problems of one call use the same kind of dressing (none,
+ * Bvo/t1, or U).
  */
 int cdcc_ladder_lambda(int32_t nsys, const cdcc_problem_t *probs,
                        const cdcc_opts_t *opts, void *stream);
+
+/*
+ * The T1-dressed operand of the Lambda ladder (Appendix A, the
+ * lambda-independent intermediates t^P_ab = sum_m t_m^a L^P_bm and the
+ * W_AbEf they enter; the paper computes them once per Lambda solve).  For
+ * every (GP, Ga) block, rows (a, e) with e in Ge = Ga ^ GP (e fastest), each
+ * row of 2 N_GP doubles:
+ *
+ *   U[a][e][P]        = B^P_ea - t^P_ea,   U[a][e][N_GP + P] = t^P_ea,
+ *   t^P_ea = sum_m t_m^e L^P_am            (m in Ge),
+ *
+ * block (GP, Ga) at element 2 * b_off[GP][Ga], so that
+ * W_efab = sum_P [U^P_(a,e) U^P_(b,f)] - sum_P [U^(N+P)_(a,e) U^(N+P)_(b,f)]
+ * is the ladder's operand product (the second half subtracted).  Blocks with
+ * N_GP = 0 or an empty irrep are not written.  B, Bvo, t1 as in
+ * cdcc_problem_t (device, read only); U is a caller-owned device buffer of
+ * 2 * lay->b_size doubles, written asynchronously on `stream`.  Pass it as
+ * cdcc_problem_t.U to every cdcc_ladder_lambda call of the solve (valid
+ * while B, Bvo and t1 are unchanged).  CDCC_EINVAL for nsys < 0, a NULL
+ * pointer or a bad layout; CDCC_ENOMEM, CDCC_EDEVICE as for the ladder.
+ */
+typedef struct {
+  const cdcc_layout_t *lay;  /* host pointer, read during the call only        */
+  const double *B;           /* device, lay->b_size                             */
+  const double *Bvo;         /* device, lay->bvo_size                           */
+  const double *t1;          /* device, lay->t1_size                            */
+  double *U;                 /* device out, 2 * lay->b_size                     */
+} cdcc_dress_problem_t;
+
+int cdcc_lambda_dress(int32_t nsys, const cdcc_dress_problem_t *probs, void *stream);
 
 /*
  * One vvvv two-body-density contraction (Appendix "CCSD two-body density
@@ -312,6 +353,23 @@ int cdcc_cd_basis(const cdcc_cd_matrix_t *mat, const cdcc_cd_params_t *params,
 int cdcc_cd_vectors(const cdcc_cd_matrix_t *mat, const int64_t *const piv[CDCC_MAX_IRREP],
                     const int64_t npiv[CDCC_MAX_IRREP], double *const L[CDCC_MAX_IRREP],
                     void *stream);
+
+/*
+ * Tile choice (host only).  cdcc_tile_key writes the size class of a shape
+ * ("<precision> <t2|lambda> b<h> <T> <K> <M>": the half-octave buckets of
+ * its 64 x 64 assembly tile count, their mean Cholesky length and its
+ * largest packed occupied pair count) into buf (len bytes); the tile table
+ * (tile_table.txt next to the library, or $CDCC_TILE_TABLE) maps exact shapes
+ * and size classes to "<assembly class>[:<contraction segment>]", exact
+ * entries first, and the autotuner writes it.  cdcc_tile_table_reload makes
+ * plans built afterwards read the table again, from path (NULL: the default
+ * location).  Tile choices never change an element's arithmetic in the
+ * assembly; the contraction segment fixes the order in which S and A are
+ * summed.  CDCC_EINVAL for a NULL pointer, a short buffer or a bad
+ * precision, CDCC_EUNSUPPORTED for an irrep count other than 1, 2, 4, 8.
+ */
+int cdcc_tile_key(const cdcc_sym_t *sym, int32_t precision, int32_t lambda, char *buf, int32_t len);
+int cdcc_tile_table_reload(const char *path);
 
 /*
  * Algorithmic flop count of one evaluation (host only): flops[0] = (ac|bd)

@@ -9,6 +9,6 @@ The computation lives in ``libcdcc.so`` (HIP, gfx950) behind the C ABI of
 """
 from ._lib import CdccError, LIB_PATH  # noqa: F401
 from .layout import Layout  # noqa: F401
-from .ladder import (cd_basis, cd_vectors, ladder_lambda, ladder_t2, ladder_t2_noalloc,  # noqa: F401
+from .ladder import (cd_basis, cd_vectors, ladder_lambda, ladder_t2, ladder_t2_noalloc, lambda_dress,  # noqa: F401
                      partial_contract, release, require_gpu, timing_enable, timing_read, vvvv_density,
                      workspace_bytes)

@@ -40,6 +40,14 @@ class Problem(ctypes.Structure):
         ("Bvo", ctypes.c_void_p), ("t1", ctypes.c_void_p),
         ("eps_occ", ctypes.c_void_p), ("eps_vir", ctypes.c_void_p),
         ("delta", ctypes.c_void_p), ("pair_energy", ctypes.c_void_p),
+        ("U", ctypes.c_void_p),
+    ]
+
+
+class DressProblem(ctypes.Structure):
+    _fields_ = [
+        ("lay", ctypes.POINTER(LayoutC)),
+        ("B", ctypes.c_void_p), ("Bvo", ctypes.c_void_p), ("t1", ctypes.c_void_p), ("U", ctypes.c_void_p),
     ]
 
 
@@ -71,14 +79,15 @@ class CdParams(ctypes.Structure):
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("precision", _i32), ("tile_policy", _i32), ("batch_bytes", _i64)]
+    _fields_ = [("precision", _i32), ("tile_policy", _i32), ("batch_bytes", _i64), ("contract_kseg", _i32),
+                ("pad0", _i32)]
 
 
 EXPORTS = ["cdcc_irrep_layout", "cdcc_ladder_t2", "cdcc_ladder_lambda", "cdcc_ladder_flops",
            "cdcc_workspace_bytes", "cdcc_timing_enable", "cdcc_timing_read", "cdcc_status_string",
            "cdcc_release", "cdcc_vvvv_density", "cdcc_density_flops", "cdcc_vo_layout",
            "cdcc_partial_contract", "cdcc_partial_flops", "cdcc_cd_basis", "cdcc_cd_vectors",
-           "cdcc_ladder_t2_noalloc"]
+           "cdcc_ladder_t2_noalloc", "cdcc_lambda_dress", "cdcc_tile_key", "cdcc_tile_table_reload"]
 
 _lib = None
 
@@ -97,6 +106,12 @@ def load() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.argtypes = [_i32, ctypes.POINTER(Problem), ctypes.POINTER(Opts), ctypes.c_void_p]
         f.restype = ctypes.c_int
+    lib.cdcc_lambda_dress.argtypes = [_i32, ctypes.POINTER(DressProblem), ctypes.c_void_p]
+    lib.cdcc_lambda_dress.restype = ctypes.c_int
+    lib.cdcc_tile_key.argtypes = [ctypes.POINTER(Sym), _i32, _i32, ctypes.c_char_p, _i32]
+    lib.cdcc_tile_key.restype = ctypes.c_int
+    lib.cdcc_tile_table_reload.argtypes = [ctypes.c_char_p]
+    lib.cdcc_tile_table_reload.restype = ctypes.c_int
     lib.cdcc_ladder_flops.argtypes = [ctypes.POINTER(LayoutC), _i32, ctypes.POINTER(ctypes.c_double)]
     lib.cdcc_ladder_flops.restype = ctypes.c_int
     lib.cdcc_workspace_bytes.argtypes = [_i32, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _i32,

@@ -131,6 +131,7 @@ struct SysPlan {
   int64_t slice_bytes = 0;   // split paths: sliced operand
   int64_t scale_rows = 0;    // split paths: row scales
   int p1cls = 0;
+  int kseg = 0;              // contraction K-segment length (0: the rule)
 };
 
 // Completion marker of a plan's last enqueued work: recorded after every
@@ -328,6 +329,7 @@ std::string plan_key(int dev, int nsys, const cdcc_problem_t *p, int lambda, int
   put(dressed);
   put(o.precision);
   put(o.tile_policy);
+  put(o.contract_kseg);
   put(cap);
   put(nsys);
   for (int s = 0; s < nsys; ++s) {
@@ -344,32 +346,81 @@ std::string plan_key(int dev, int nsys, const cdcc_problem_t *p, int lambda, int
 }
 
 // Tile table written by the autotuner (paper_2512_21909_amd/autotune.py):
-// lines "<fp64|mixed|mixed_i8> <t2|lambda> h nocc[h] nvir[h] ncd[h] class", looked up by
-// the exact shape of each system.  Read once from $CDCC_TILE_TABLE or from
-// tile_table.txt next to this library.
-std::map<std::string, int> *g_tile_table = nullptr;
+// lines "<key> <class>[:<kseg>]" with <class> the assembly tile class and
+// <kseg> the contraction's K-segment length (0 or absent: the rule below).
+// Keys are either the exact shape, "<fp64|mixed|mixed_i8> <t2|lambda> h
+// nocc[h] nvir[h] ncd[h]", or a shape bucket (shape_bucket), so that shapes
+// never tuned themselves take the choice of tuned shapes of the same size
+// class.  Read from $CDCC_TILE_TABLE or from tile_table.txt next to this
+// library, once (and again after cdcc_tile_table_reload).
+struct TileChoice {
+  int cls = -1;
+  int kseg = 0;
+};
+std::map<std::string, TileChoice> *g_tile_table = nullptr;
+std::string g_tile_table_path;  // set by cdcc_tile_table_reload ("" = default)
+
+const char *prec_name(int precision) {
+  return precision == CDCC_MIXED_I8 ? "mixed_i8" : precision == CDCC_MIXED ? "mixed" : "fp64";
+}
 
 std::string shape_key(const cdcc_sym_t &y, int precision, int lambda) {
   std::ostringstream k;
-  k << (precision == CDCC_MIXED_I8 ? "mixed_i8" : precision == CDCC_MIXED ? "mixed" : "fp64") << ' '
-    << (lambda ? "lambda" : "t2") << ' ' << y.nirrep;
+  k << prec_name(precision) << ' ' << (lambda ? "lambda" : "t2") << ' ' << y.nirrep;
   for (const int32_t *a : {y.nocc, y.nvir, y.ncd})
     for (int g = 0; g < y.nirrep; ++g) k << ' ' << a[g];
   return k.str();
 }
 
-const std::map<std::string, int> &tile_table() {
+// Size class of a shape: "<prec> <kind> b<h> <T> <K> <M>" with T the number of
+// 64 x 64 assembly tiles, K their mean Cholesky length (x2 for the Lambda
+// stack) and M the largest packed occupied pair count (contraction rows), each
+// as round(2 log2(x)) (half-octave buckets; -1 for zero).
+std::string shape_bucket(const cdcc_sym_t &y, int precision, int lambda) {
+  const int h = y.nirrep;
+  const int32_t *no = y.nocc, *nv = y.nvir, *nc = y.ncd;
+  const int kmul = lambda ? 2 : 1;
+  double tiles = 0, kw = 0, mrows = 0;
+  for (int ga = 0; ga < h; ++ga)
+    for (int gb = 0; gb <= ga; ++gb) {
+      const int G = ga ^ gb;
+      for (int gc = 0; gc < h; ++gc) {
+        const int gP = ga ^ gc, gd = gb ^ gP;
+        if (nc[gP] == 0) continue;
+        const double M = double(nv[ga]) * nv[gc], N = double(nv[gb]) * nv[gd] * (ga == gb ? 0.5 : 1.0);
+        const double t = std::ceil(M / 64) * std::ceil(N / 64);
+        tiles += t;
+        kw += t * double(kmul) * nc[gP];
+      }
+      double pk = 0;
+      for (int gi = 0; gi < h; ++gi) {
+        const int gj = gi ^ G;
+        if (gi > gj) pk += double(no[gi]) * no[gj];
+        if (gi == gj) pk += double(no[gi]) * (no[gi] + 1) / 2;
+      }
+      mrows = std::max(mrows, pk);
+    }
+  auto b = [](double x) { return x > 0 ? long(std::lround(2.0 * std::log2(x))) : -1L; };
+  std::ostringstream k;
+  k << prec_name(precision) << ' ' << (lambda ? "lambda" : "t2") << " b" << h << ' ' << b(tiles) << ' '
+    << b(tiles > 0 ? kw / tiles : 0) << ' ' << b(mrows);
+  return k.str();
+}
+
+const std::map<std::string, TileChoice> &tile_table() {
   if (g_tile_table) return *g_tile_table;
-  g_tile_table = new std::map<std::string, int>();
-  std::string path;
-  if (const char *e = std::getenv("CDCC_TILE_TABLE")) {
-    path = e;
-  } else {
-    Dl_info info;
-    if (dladdr(reinterpret_cast<void *>(&cdcc_irrep_layout), &info) && info.dli_fname) {
-      path = info.dli_fname;
-      const size_t cut = path.find_last_of('/');
-      path = (cut == std::string::npos ? std::string(".") : path.substr(0, cut)) + "/tile_table.txt";
+  g_tile_table = new std::map<std::string, TileChoice>();
+  std::string path = g_tile_table_path;
+  if (path.empty()) {
+    if (const char *e = std::getenv("CDCC_TILE_TABLE")) {
+      path = e;
+    } else {
+      Dl_info info;
+      if (dladdr(reinterpret_cast<void *>(&cdcc_irrep_layout), &info) && info.dli_fname) {
+        path = info.dli_fname;
+        const size_t cut = path.find_last_of('/');
+        path = (cut == std::string::npos ? std::string(".") : path.substr(0, cut)) + "/tile_table.txt";
+      }
     }
   }
   std::ifstream in(path);
@@ -378,17 +429,28 @@ const std::map<std::string, int> &tile_table() {
     if (line.empty() || line[0] == '#') continue;
     const size_t cut = line.find_last_of(' ');
     if (cut == std::string::npos) continue;
-    (*g_tile_table)[line.substr(0, cut)] = std::atoi(line.c_str() + cut + 1);
+    TileChoice c;
+    const char *v = line.c_str() + cut + 1;
+    c.cls = std::atoi(v);
+    if (const char *colon = std::strchr(v, ':')) c.kseg = std::atoi(colon + 1);
+    (*g_tile_table)[line.substr(0, cut)] = c;
   }
   return *g_tile_table;
+}
+
+// The table's choice for a shape: its exact entry, else its size class's.
+TileChoice table_choice(const cdcc_sym_t &y, int precision, int lambda) {
+  const auto &T = tile_table();
+  auto it = T.find(shape_key(y, precision, lambda));
+  if (it == T.end()) it = T.find(shape_bucket(y, precision, lambda));
+  return it == T.end() ? TileChoice{} : it->second;
 }
 
 int choose_p1_class(const cdcc_layout_t &L, int policy, int precision, int lambda) {
   const bool mixed = is_split(precision);
   if (policy >= 1 && policy <= (mixed ? 4 : 3)) return policy - 1;
-  const auto &T = tile_table();
-  const auto it = T.find(shape_key(L.sym, precision, lambda));
-  if (it != T.end() && it->second >= 0 && it->second <= (mixed ? 3 : 2)) return it->second;
+  const TileChoice c = table_choice(L.sym, precision, lambda);
+  if (c.cls >= 0 && c.cls <= (mixed ? 3 : 2)) return c.cls;
   // untuned shapes: 128 x 64 for split-BF16; 64 x 64 for the 8-bit digits
   // (thirteen accumulators per 32 x 32 block: the 64-wide waves of the other
   // classes run at one wave per SIMD)
@@ -470,7 +532,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
       for (int g = 0; g < probs[s].lay->sym.nirrep; ++g) mxrow = std::max<int64_t>(mxrow, int64_t(km) * probs[s].lay->sym.ncd[g] * 8);
     const bool fits = mxrow <= kSliceStageMax;
     P.slice_stage = fits ? int(std::max<int64_t>(mxrow, 8)) : 0;
-    P.fuse_dress = fits && lambda && is_split(opts.precision);
+    P.fuse_dress = fits && lambda && dressed != 2 && is_split(opts.precision);
   }
   for (int s = 0; s < nsys; ++s) {
     SysPlan &SP = P.sys[s];
@@ -482,7 +544,9 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     const bool mixed = is_split(opts.precision);
     const int kblk = split_kblock(opts.precision), ebytes = split_elem_bytes(opts.precision);
     SP.p1cls = choose_p1_class(L, opts.tile_policy, opts.precision, lambda);
-    if (lambda && !P.fuse_dress) SP.u_elems = kmul * L.b_size;
+    // contraction K segment: forced, else tuned, else the rule (0)
+    SP.kseg = opts.contract_kseg > 0 ? opts.contract_kseg : std::max(0, table_choice(L.sym, opts.precision, lambda).kseg);
+    if (lambda && !P.fuse_dress && dressed != 2) SP.u_elems = kmul * L.b_size;
     // mixed path: slice every operand block once per call
     int64_t blk_s[CDCC_MAX_IRREP][CDCC_MAX_IRREP], blk_sc[CDCC_MAX_IRREP][CDCC_MAX_IRREP];
     int blk_kp[CDCC_MAX_IRREP];
@@ -571,8 +635,9 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
             }
         }
     }
-    // Lambda operand stack (in the mixed path the slice launch builds it)
-    if (lambda && !P.fuse_dress)
+    // Lambda operand stack (in the mixed path the slice launch builds it;
+    // with a caller's stack there is nothing to build)
+    if (lambda && !P.fuse_dress && dressed != 2)
       for (int gP = 0; gP < h; ++gP)
         for (int ga = 0; ga < h; ++ga) {
           const int ge = ga ^ gP;
@@ -657,7 +722,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           g.fm = contract_fm(int(n_ij));
           // groups with more than four row tiles have tiles enough to fill
           // the chip with segments twice as long (half the split-K partials)
-          const int kseg_len = n_ij > 4 * 16 * g.fm ? 2 * kKSeg : kKSeg;
+          const int kseg_len = SP.kseg > 0 ? (SP.kseg + 15) / 16 * 16 : (n_ij > 4 * 16 * g.fm ? 2 * kKSeg : kKSeg);
           g.nsplit = std::max(1, (kt_len + kseg_len / 2) / kseg_len);
           g.kseg = ((kt_len + g.nsplit - 1) / g.nsplit + 15) / 16 * 16;
           if (g.nsplit > 1) g.nsplit = (kt_len + g.kseg - 1) / g.kseg;
@@ -941,15 +1006,18 @@ int validate(int32_t nsys, const cdcc_problem_t *probs, int lambda, int *dressed
     if (p.delta && (!p.eps_occ || !p.eps_vir)) return CDCC_EINVAL;
     if (lambda) {
       if ((p.Bvo == nullptr) != (p.t1 == nullptr)) return CDCC_EINVAL;
-      const int d = p.t1 ? 1 : 0;
-      if (dr >= 0 && dr != d) return CDCC_EINVAL;  // one batch: all dressed or all undressed
+      // 0 undressed, 1 dressed here from B, L and t1, 2 dressed stack given (U)
+      const int d = p.U ? 2 : (p.t1 ? 1 : 0);
+      if (dr >= 0 && dr != d) return CDCC_EINVAL;  // one batch: one kind of dressing
       dr = d;
+    } else if (p.U) {
+      return CDCC_EINVAL;  // the stack is a Lambda operand
     }
     // the amplitude tables use 32-bit indices
     for (int G = 0; G < p.lay->sym.nirrep; ++G)
       if (p.lay->n_vv[G] >= (int64_t(1) << 31) || p.lay->n_oo[G] >= (int64_t(1) << 31)) return CDCC_EUNSUPPORTED;
   }
-  *dressed = dr > 0 ? 1 : 0;
+  *dressed = dr > 0 ? dr : 0;
   return CDCC_OK;
 }
 
@@ -1023,7 +1091,7 @@ int get_workspace(int dev, hipStream_t stream, int64_t bytes, int64_t staging, W
 int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, double *part, hipStream_t stream) {
   const Plan *P = &Pl;
   HIPCHK(launch_fill_int(counters, P->ncounters, 0, stream));
-  if (P->lambda && !P->fuse_dress) {
+  if (P->lambda && !P->fuse_dress && P->ndressrows > 0) {
     Span sp(0, P->ndressrows > 0, stream);
     HIPCHK(launch_dress(P->dressjobs, P->dressrows, P->ndressrows, dsp, stream));
   }
@@ -1081,6 +1149,7 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
   if (opts.precision != CDCC_FP64 && !is_split(opts.precision)) return CDCC_EINVAL;
   if (opts.tile_policy < 0 || opts.tile_policy > 4) return CDCC_EINVAL;
   if (opts.tile_policy == 4 && !is_split(opts.precision)) return CDCC_EINVAL;
+  if (opts.contract_kseg < 0 || opts.contract_kseg > (1 << 20)) return CDCC_EINVAL;
   int dressed = 0;
   int rc = validate(nsys, probs, lambda, &dressed);
   if (rc != CDCC_OK) return rc;
@@ -1104,7 +1173,7 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
   for (int s = 0; s < nsys; ++s) {
     const cdcc_problem_t &p = probs[s];
     SysPtrs q{};
-    q.opnd = lambda ? reinterpret_cast<const double *>(base + W.u[s]) : p.B;
+    q.opnd = !lambda ? p.B : (dressed == 2 ? p.U : reinterpret_cast<const double *>(base + W.u[s]));
     q.X = p.X;
     q.R = p.R;
     q.delta = p.delta;
@@ -2154,6 +2223,7 @@ int run_ladder_in_region(int32_t nsys, const cdcc_problem_t *probs, const cdcc_o
   if (opts.precision != CDCC_FP64 && !is_split(opts.precision)) return CDCC_EINVAL;
   if (opts.tile_policy < 0 || opts.tile_policy > 4) return CDCC_EINVAL;
   if (opts.tile_policy == 4 && !is_split(opts.precision)) return CDCC_EINVAL;
+  if (opts.contract_kseg < 0 || opts.contract_kseg > (1 << 20)) return CDCC_EINVAL;
   if (!region || region_bytes <= kScratchTables) return CDCC_EINVAL;
   int dressed = 0;
   int rc = validate(nsys, probs, 0, &dressed);
@@ -2229,8 +2299,144 @@ int run_ladder_in_region(int32_t nsys, const cdcc_problem_t *probs, const cdcc_o
   return rc;
 }
 
+extern "C" int cdcc_tile_key(const cdcc_sym_t *sym, int32_t precision, int32_t lambda, char *buf, int32_t len) {
+  if (!sym || !buf || len <= 0) return CDCC_EINVAL;
+  if (!valid_sym(*sym)) return sym->nirrep >= 1 && sym->nirrep <= 8 ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+  if (precision != CDCC_FP64 && !is_split(precision)) return CDCC_EINVAL;
+  const std::string k = shape_bucket(*sym, precision, lambda ? 1 : 0);
+  if (int64_t(k.size()) + 1 > len) return CDCC_EINVAL;
+  std::memcpy(buf, k.c_str(), k.size() + 1);
+  return CDCC_OK;
+}
+
+extern "C" int cdcc_tile_table_reload(const char *path) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  delete g_tile_table;
+  g_tile_table = nullptr;
+  g_tile_table_path = path ? path : "";
+  return CDCC_OK;
+}
+
 extern "C" int cdcc_ladder_t2(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *opts, void *stream) {
   return run_ladder(nsys, probs, opts, stream, 0);
+}
+
+// ===========================================================================
+// Dressed operand of the Lambda ladder, built once per Lambda solve
+// (Appendix A: t^P_ab = sum_m t_m^a L^P_bm and W_AbEf depend on t1 and the
+// Cholesky vectors only, not on lambda).  One dress job per (system, GP, Ga)
+// block; the stack has the layout the ladder's FP64 path builds for itself.
+// ===========================================================================
+namespace {
+struct DressPlan {
+  void *dtab = nullptr;
+  DressJob *jobs = nullptr;
+  int2 *rows = nullptr;
+  int nrows = 0;
+  PlanFence fence;
+  ~DressPlan() {
+    fence.wait();
+    if (dtab) (void)hipFree(dtab);
+  }
+};
+PlanCache<DressPlan> g_dressplans(64);
+
+int build_dress_plan(int nsys, const cdcc_dress_problem_t *probs, DressPlan &P) {
+  std::vector<DressJob> jobs;
+  std::vector<int2> rows;
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_layout_t &L = *probs[s].lay;
+    const int h = L.sym.nirrep;
+    const int32_t *no = L.sym.nocc, *nv = L.sym.nvir, *nc = L.sym.ncd;
+    for (int gP = 0; gP < h; ++gP)
+      for (int ga = 0; ga < h; ++ga) {
+        const int ge = ga ^ gP;
+        if (nc[gP] == 0 || nv[ga] == 0 || nv[ge] == 0) continue;
+        DressJob D{};
+        D.sys = s;
+        D.va = nv[ga];
+        D.ve = nv[ge];
+        D.np = nc[gP];
+        D.om = no[ge];
+        D.u_off = 2 * L.b_off[gP][ga];
+        D.b_off = L.b_off[gP][ge];
+        D.bvo_off = L.bvo_off[gP][ga];
+        D.t1_off = L.t1_off[ge];
+        const int jid = int(jobs.size());
+        jobs.push_back(D);
+        for (int ae = 0; ae < nv[ga] * nv[ge]; ++ae) rows.push_back(int2{jid, ae});
+      }
+  }
+  TableBuilder T;
+  const int64_t o_j = T.add(jobs), o_r = T.add(rows);
+  if (hipMalloc(&P.dtab, std::max<size_t>(T.bytes.size(), 256)) != hipSuccess) return CDCC_ENOMEM;
+  if (hipMemcpy(P.dtab, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) return CDCC_EDEVICE;
+  char *b = static_cast<char *>(P.dtab);
+  P.jobs = reinterpret_cast<DressJob *>(b + o_j);
+  P.rows = reinterpret_cast<int2 *>(b + o_r);
+  P.nrows = int(rows.size());
+  return CDCC_OK;
+}
+
+int run_dress(int32_t nsys, const cdcc_dress_problem_t *probs, void *vstream) {
+  if (nsys < 0 || (nsys > 0 && !probs)) return CDCC_EINVAL;
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_dress_problem_t &p = probs[s];
+    if (!p.lay || !p.B || !p.Bvo || !p.t1 || !p.U) return CDCC_EINVAL;
+    if (!valid_sym(p.lay->sym)) return p.lay->sym.nirrep >= 1 && p.lay->sym.nirrep <= 8 ? CDCC_EUNSUPPORTED : CDCC_EINVAL;
+    cdcc_layout_t chk;
+    if (cdcc_irrep_layout(&p.lay->sym, &chk) != CDCC_OK) return CDCC_EINVAL;
+    if (chk.b_size != p.lay->b_size || chk.bvo_size != p.lay->bvo_size || chk.t1_size != p.lay->t1_size)
+      return CDCC_EINVAL;
+  }
+  if (nsys == 0) return CDCC_OK;
+  hipStream_t stream = static_cast<hipStream_t>(vstream);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_mu);
+  std::string key = "dress|" + std::to_string(dev) + "|" + std::to_string(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    const cdcc_sym_t &y = probs[s].lay->sym;
+    key += "|" + std::to_string(y.nirrep);
+    for (int g = 0; g < y.nirrep; ++g)
+      key += "," + std::to_string(y.nocc[g]) + "," + std::to_string(y.nvir[g]) + "," + std::to_string(y.ncd[g]);
+  }
+  std::shared_ptr<DressPlan> P = g_dressplans.find(key);
+  if (!P) {
+    P = std::make_shared<DressPlan>();
+    const int rc = build_dress_plan(nsys, probs, *P);
+    if (rc != CDCC_OK) return rc;
+    g_dressplans.put(key, P);
+  }
+  Workspace *ws = nullptr;
+  const int64_t bytes = align_up(int64_t(nsys) * int64_t(sizeof(SysPtrs)));
+  int rc = get_workspace(dev, stream, bytes, int64_t(nsys) * int64_t(sizeof(SysPtrs)), ws);
+  if (rc != CDCC_OK) return rc;
+  if (ws->ev_recorded) HIPCHK(hipEventSynchronize(ws->ev));
+  SysPtrs *hs = static_cast<SysPtrs *>(ws->staging);
+  for (int s = 0; s < nsys; ++s) {
+    SysPtrs q{};
+    q.opnd = probs[s].U;  // written by the dress kernel
+    q.B = probs[s].B;
+    q.Bvo = probs[s].Bvo;
+    q.t1 = probs[s].t1;
+    hs[s] = q;
+  }
+  SysPtrs *dsp = static_cast<SysPtrs *>(ws->dev);
+  HIPCHK(hipMemcpyAsync(dsp, hs, size_t(nsys) * sizeof(SysPtrs), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(ws->ev, stream));
+  ws->ev_recorded = true;
+  {
+    Span sp(0, P->nrows > 0, stream);
+    HIPCHK(launch_dress(P->jobs, P->rows, P->nrows, dsp, stream));
+  }
+  P->fence.mark(stream);
+  return CDCC_OK;
+}
+}  // namespace
+
+extern "C" int cdcc_lambda_dress(int32_t nsys, const cdcc_dress_problem_t *probs, void *stream) {
+  return run_dress(nsys, probs, stream);
 }
 
 extern "C" int cdcc_ladder_lambda(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *opts, void *stream) {
@@ -2295,6 +2501,7 @@ extern "C" int cdcc_release(void) {
   g_pmplans.clear();
   g_ws.clear();
   g_plans.clear();
+  g_dressplans.clear();
   g_scratch_plans.clear();
   for (auto &h : g_scratch_host)
     if (h.second.ev) (void)hipEventDestroy(h.second.ev);

@@ -126,8 +126,8 @@ __global__ __launch_bounds__(256) void dress_kernel(const DressJob *__restrict__
 // ---------------------------------------------------------------------------
 // assemble (FP64): X[(c,d),(a,b)] = 1/2 sum_K U[(a,c),K] s_K U[(b,d),K]
 // Tile BM x BN of the (a,c) x (d,b) product, BK = 16, 4 waves in 2x2, each
-// wave (BM/2) x (BN/2) as 16x16 MFMA f64 blocks.  LDS holds [k][row] (padded
-// by 2 doubles, double-buffered, one barrier per K step).  Out-of-range rows
+// wave (BM/2) x (BN/2) as 16x16 MFMA f64 blocks.  LDS holds [row][k] (rows
+// of BK + 1 doubles, double-buffered, one barrier per K step).  Out-of-range rows
 // and K are read from a clamped address and zeroed by a select, so the loads
 // are straight-line code.
 // ---------------------------------------------------------------------------
@@ -144,12 +144,18 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
                                                            const SysPtrs *__restrict__ sp,
                                                            double *__restrict__ xbuf) {
   constexpr int BK = 16;
-  constexpr int LA = BM + 2, LB = BN + 2;
+  // LDS tiles row-major like the operands ([row][k]) with a row stride of
+  // BK + 1 doubles (34 banks): a thread's four consecutive k of one row go to
+  // consecutive words, and the four threads of one k slot in a 16-lane group
+  // (rows lr .. lr+3, k slots 0/4/8/12) land on 16 different bank pairs; a
+  // fragment read (16 consecutive rows, one k) steps 34 words per lane, so
+  // its 16 lanes cover the 32 banks once.  Both are free of bank conflicts.
+  constexpr int LK = BK + 1;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int RA = BM / 64, RB = BN / 64;  // row slots per thread
-  __shared__ double As[2][BK][LA];
-  __shared__ double Bs[2][BK][LB];
+  __shared__ double As[2][BM][LK];
+  __shared__ double Bs[2][BN][LK];
   __shared__ int s_tile;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -256,11 +262,11 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
 #pragma unroll
       for (int q = 0; q < RA; ++q)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) As[buf][lk + e][lr + 64 * q] = ra[q][e];
+        for (int e = 0; e < 4; ++e) As[buf][lr + 64 * q][lk + e] = ra[q][e];
 #pragma unroll
       for (int q = 0; q < RB; ++q)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) Bs[buf][lk + e][lr + 64 * q] = rb[q][e];
+        for (int e = 0; e < 4; ++e) Bs[buf][lr + 64 * q][lk + e] = rb[q][e];
     };
 
     const int nfull = K / BK, nk = (K + BK - 1) / BK;
@@ -277,9 +283,9 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
         const int kr = ks * 4 + (lane >> 4);
         double fa[FM], fb[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) fa[i] = As[cur][kr][wm * WM + i * 16 + (lane & 15)];
+        for (int i = 0; i < FM; ++i) fa[i] = As[cur][wm * WM + i * 16 + (lane & 15)][kr];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) fb[j] = Bs[cur][kr][wn * WN + j * 16 + (lane & 15)];
+        for (int j = 0; j < FN; ++j) fb[j] = Bs[cur][wn * WN + j * 16 + (lane & 15)][kr];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -290,7 +296,25 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
       __syncthreads();
     }
 
-    // epilogue: permuted store into the column group's X region
+    // epilogue: permuted store into the column group's X region.  The
+    // quotients of a lane's rows (by vc) and columns (by nb or vd) are formed
+    // once per row and per column, not once per element.
+    int rq[FM][4], rrem[FM][4], cq[FN], crem[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * WM + i * 16 + (lane >> 4) + 4 * r;
+        rq[i][r] = m / D.vc;
+        rrem[i][r] = m - rq[i][r] * D.vc;
+      }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + wn * WN + j * 16 + (lane & 15);
+      const int dv = MODE == 1 ? D.vd : D.nb;
+      cq[j] = n / dv;
+      crem[j] = n - cq[j] * dv;
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -301,15 +325,14 @@ __global__ __launch_bounds__(256) void assemble_f64_kernel(const P1Desc *__restr
           const int n = n0 + wn * WN + j * 16 + (lane & 15);
           if (m >= D.M || n >= D.N) continue;
           if constexpr (MODE == 1) {
-            const int am = m / D.vc, b = m - am * D.vc;
-            const int c = n / D.vd, d = n - c * D.vd;
+            const int am = rq[i][r], b = rrem[i][r];
+            const int c = cq[j], d = crem[j];
             const int64_t wrow = int64_t(D.a_first + am - D.ga0) * D.nb + c;
             xbuf[D.xoff + wrow * D.ldx + D.xrow0 + int64_t(b) * D.vd + d] = acc[i][j][r];
             continue;
           }
-          const int am = m / D.vc, c = m - am * D.vc;
-          const int a = D.a_first + am;
-          const int dd = n / D.nb, b = n - dd * D.nb;
+          const int a = D.a_first + rq[i][r], c = rrem[i][r];
+          const int dd = cq[j], b = crem[j];
           if (D.tri && b > a) continue;
           const int64_t xcol = D.tri ? (int64_t(a) * (a + 1) / 2 - int64_t(D.ga0) * (D.ga0 + 1) / 2 + b)
                                      : (int64_t(a - D.ga0) * D.vb + b);

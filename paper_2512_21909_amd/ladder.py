@@ -4,6 +4,7 @@ library.  There is no CPU fallback: a missing library or GPU raises."""
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
@@ -44,7 +45,7 @@ def _ptr(t, n, name, optional=False):
 def make_problems(problems: list[dict], lambda_: bool):
     """Marshal a list of problem dicts into a ctypes array of cdcc_problem_t.
     Keys: layout (Layout), B, X, R; optional eps_occ, eps_vir, delta,
-    pair_energy; Lambda: Bvo, t1."""
+    pair_energy; Lambda: Bvo, t1, or U (the stack of lambda_dress)."""
     arr = (_lib.Problem * len(problems))()
     keep = []
     for k, p in enumerate(problems):
@@ -62,14 +63,37 @@ def make_problems(problems: list[dict], lambda_: bool):
         if lambda_:
             q.Bvo = _ptr(p.get("Bvo"), lay.bvo_size, "Bvo", True)
             q.t1 = _ptr(p.get("t1"), lay.t1_size, "t1", True)
+            q.U = _ptr(p.get("U"), 2 * lay.b_size, "U", True)
     return arr, keep
 
 
-def _opts(precision, tile_policy, batch_bytes):
+def lambda_dress(problems, stream=None) -> None:
+    """Build the T1-dressed Lambda stack U (2 * b_size doubles, caller-owned)
+    from B, Bvo and t1, once per Lambda solve; pass it as the problem's "U"
+    to ladder_lambda.  Keys: layout, B, Bvo, t1, U (out)."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr = (_lib.DressProblem * len(problems))()
+    keep = []
+    for k, p in enumerate(problems):
+        lay: Layout = p["layout"]
+        keep.append(lay)
+        q = arr[k]
+        q.lay = ctypes.pointer(lay.c)
+        q.B = _ptr(p["B"], lay.b_size, "B")
+        q.Bvo = _ptr(p["Bvo"], lay.bvo_size, "Bvo")
+        q.t1 = _ptr(p["t1"], lay.t1_size, "t1")
+        q.U = _ptr(p["U"], 2 * lay.b_size, "U")
+    st = _lib.load().cdcc_lambda_dress(len(problems), arr, _stream(stream))
+    _lib.check(st, "cdcc_lambda_dress")
+
+
+def _opts(precision, tile_policy, batch_bytes, contract_kseg=0):
     o = _lib.Opts()
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
     o.tile_policy = int(tile_policy)
     o.batch_bytes = int(batch_bytes)
+    o.contract_kseg = int(contract_kseg)
     return o
 
 
@@ -80,18 +104,29 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def ladder_t2(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0) -> None:
+def _maybe_tune(problems, kind, precision, tile_policy):
+    """With CDCC_AUTOTUNE=1, shapes whose size class has no tile-table entry
+    are tuned first (autotune.ensure); a forced tile class needs no table."""
+    if tile_policy or os.environ.get("CDCC_AUTOTUNE") != "1":
+        return
+    from .autotune import ensure
+    prec = precision if isinstance(precision, str) else {v: k for k, v in _PREC.items()}[int(precision)]
+    ensure([p["layout"].sym for p in problems], kind, prec)
+
+
+def ladder_t2(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0, contract_kseg=0) -> None:
     """T2 ladder R_ij^ab = sum_cd tau_ij^cd (ac|bd) for one problem dict or a
     list of them (one batched launch sequence).  Asynchronous on ``stream``."""
     if isinstance(problems, dict):
         problems = [problems]
+    _maybe_tune(problems, "t2", precision, tile_policy)
     arr, keep = make_problems(problems, False)
-    o = _opts(precision, tile_policy, batch_bytes)
+    o = _opts(precision, tile_policy, batch_bytes, contract_kseg)
     st = _lib.load().cdcc_ladder_t2(len(problems), arr, ctypes.byref(o), _stream(stream))
     _lib.check(st, "cdcc_ladder_t2")
 
 
-def ladder_t2_noalloc(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0) -> None:
+def ladder_t2_noalloc(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0, contract_kseg=0) -> None:
     """The T2 ladder of ``ladder_t2`` without any device allocation: plan
     tables and workspace in the library's static scratch array (calls that
     overlap on one GPU race).  Raises CdccError with status ESCRATCH when the
@@ -99,17 +134,18 @@ def ladder_t2_noalloc(problems, precision="fp64", stream=None, tile_policy=0, ba
     if isinstance(problems, dict):
         problems = [problems]
     arr, keep = make_problems(problems, False)
-    o = _opts(precision, tile_policy, batch_bytes)
+    o = _opts(precision, tile_policy, batch_bytes, contract_kseg)
     st = _lib.load().cdcc_ladder_t2_noalloc(len(problems), arr, ctypes.byref(o), _stream(stream))
     _lib.check(st, "cdcc_ladder_t2_noalloc")
 
 
-def ladder_lambda(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0) -> None:
+def ladder_lambda(problems, precision="fp64", stream=None, tile_policy=0, batch_bytes=0, contract_kseg=0) -> None:
     """Lambda ladder Z_ij^ab = sum_ef lambda_ij^ef W_efab (Appendix-A W)."""
     if isinstance(problems, dict):
         problems = [problems]
+    _maybe_tune(problems, "lambda", precision, tile_policy)
     arr, keep = make_problems(problems, True)
-    o = _opts(precision, tile_policy, batch_bytes)
+    o = _opts(precision, tile_policy, batch_bytes, contract_kseg)
     st = _lib.load().cdcc_ladder_lambda(len(problems), arr, ctypes.byref(o), _stream(stream))
     _lib.check(st, "cdcc_ladder_lambda")
 
@@ -208,15 +244,31 @@ def cd_vectors(V, piv, L, stream=None) -> None:
     _lib.check(st, "cdcc_cd_vectors")
 
 
-def workspace_bytes(problems, lambda_=False, precision="fp64", tile_policy=0, batch_bytes=0) -> int:
+def workspace_bytes(problems, lambda_=False, precision="fp64", tile_policy=0, batch_bytes=0, contract_kseg=0) -> int:
     if isinstance(problems, dict):
         problems = [problems]
     arr, keep = make_problems(problems, lambda_)
-    o = _opts(precision, tile_policy, batch_bytes)
+    o = _opts(precision, tile_policy, batch_bytes, contract_kseg)
     out = ctypes.c_int64(0)
     _lib.check(_lib.load().cdcc_workspace_bytes(len(problems), arr, ctypes.byref(o), int(bool(lambda_)),
                                                 ctypes.byref(out)), "cdcc_workspace_bytes")
     return int(out.value)
+
+
+def tile_key(sym: dict, precision="fp64", kind="t2") -> str:
+    """The size-class key of the tile table for a shape (cdcc_tile_key)."""
+    buf = ctypes.create_string_buffer(256)
+    c = Layout(sym).c.sym
+    st = _lib.load().cdcc_tile_key(ctypes.byref(c), _PREC[precision], int(kind == "lambda"), buf, 256)
+    _lib.check(st, "cdcc_tile_key")
+    return buf.value.decode()
+
+
+def tile_table_reload(path=None) -> None:
+    """Plans built from now on read the tile table again (from ``path``, or
+    the default location)."""
+    st = _lib.load().cdcc_tile_table_reload(path.encode() if path else None)
+    _lib.check(st, "cdcc_tile_table_reload")
 
 
 def release() -> None:

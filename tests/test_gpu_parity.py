@@ -460,3 +460,66 @@ def test_uneven_batch_of_64_systems(gpu_lib, precision):
             ref = O.element_t2(sym, p["B"], p["X"], lay.occ_off[gi] + i, lay.occ_off[gj] + j,
                                lay.vir_off[ga] + a, lay.vir_off[gb] + b)
             assert abs(Rb[(G, gi, ga)][i, j, a, b] - ref) <= tol * scale, (k, G, gi, ga)
+
+
+# ------------------------------------------------------------ dressing once
+def _oracle_stack(sym, prob):
+    """U of cdcc_lambda_dress from the oracle's t^P_ea (Appendix A): per
+    (GP, Ga) block, rows (a, e), [B^P_ea - t^P_ea | t^P_ea], flattened like
+    the library's layout."""
+    import oracle as O
+    lay = OracleLayout(sym)
+    Bf, Bvof, t1f = lay.full_B(prob["B"]), lay.full_Bvo(prob["Bvo"]), lay.full_t1(prob["t1"])
+    tP = O.t1_dressing_full(Bvof, t1f)                 # [P, e, a] = sum_m t_m^e L^P_am
+    h, nv, nc = sym["h"], sym["nvir"], sym["ncd"]
+    vo = np.concatenate([[0], np.cumsum(nv)]).astype(int)
+    po = np.concatenate([[0], np.cumsum(nc)]).astype(int)
+    out = []
+    for gP in range(h):
+        for ga in range(h):
+            ge = ga ^ gP
+            a_sl, e_sl, p_sl = slice(vo[ga], vo[ga + 1]), slice(vo[ge], vo[ge + 1]), slice(po[gP], po[gP + 1])
+            b = Bf[p_sl, e_sl, a_sl].transpose(2, 1, 0)    # [a, e, P] = B^P_ea
+            t = tP[p_sl, e_sl, a_sl].transpose(2, 1, 0)    # [a, e, P] = t^P_ea
+            out.append(np.concatenate([b - t, t], axis=2).ravel())
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
+def test_lambda_with_stack_built_once(gpu_lib, precision):
+    """cdcc_lambda_dress builds the dressed stack once (checked element by
+    element against the oracle's t^P_ea); Lambda calls that pass it match the
+    oracle and, in FP64, the call that dresses from Bvo and t1 bitwise; two
+    systems in one batched call."""
+    import torch
+    cdcc = gpu_lib
+    specs = [([2, 1, 1, 1], [9, 5, 7, 4], [30, 11, 6, 7]), ([3, 2], [21, 14], [50, 31])]
+    probs = [problem(S.sym_custom(*sp), seed=60 + k, kind="lambda", symmetric_B=False) for k, sp in enumerate(specs)]
+    ds, with_u = [], []
+    for p in probs:
+        d = device_problem(cdcc, p, want_energy=True)
+        lay = d["layout"]
+        u = torch.full((2 * lay.b_size,), float("nan"), dtype=torch.float64, device="cuda")
+        cdcc.lambda_dress({"layout": lay, "B": d["B"], "Bvo": d["Bvo"], "t1": d["t1"], "U": u})
+        torch.cuda.synchronize()
+        ref_u = _oracle_stack(p["sym"], p)
+        got_u = u.cpu().numpy()
+        mask = np.isfinite(got_u)
+        assert mask.sum() == ref_u.size or np.all(ref_u[~mask] == 0)  # only empty blocks stay unwritten
+        np.testing.assert_allclose(got_u[mask], ref_u[mask], rtol=0, atol=1e-14 * np.abs(ref_u).max())
+        e = device_problem(cdcc, p, want_energy=True)
+        e_u = dict(e)
+        e_u.pop("Bvo"), e_u.pop("t1")
+        e_u["U"] = u
+        ds.append(d)
+        with_u.append(e_u)
+    run(cdcc, ds, kind="lambda", precision=precision)           # dressed from Bvo and t1
+    run(cdcc, with_u, kind="lambda", precision=precision)       # the prebuilt stack
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    for p, d, e in zip(probs, ds, with_u):
+        ref = oracle_result(p)
+        _check(blocks(e), ref, tol, "stack")
+        if precision == "fp64":
+            assert np.array_equal(e["R"].cpu().numpy(), d["R"].cpu().numpy())
+        else:
+            assert _pair_energy_err(e, p, ref) <= PAIR_TOL

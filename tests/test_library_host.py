@@ -35,8 +35,9 @@ def test_struct_sizes_match_header(lib):
     # 4 + 3*8*4 = 100 -> padded to 104 by the following int64 arrays
     assert ctypes.sizeof(lib.Sym) == 100
     assert ctypes.sizeof(lib.LayoutC) == 104 + 8 * (5 * 8 + 4 * 64 + 4 * 8 + 7)
-    assert ctypes.sizeof(lib.Problem) == 10 * 8
-    assert ctypes.sizeof(lib.Opts) == 16
+    assert ctypes.sizeof(lib.Problem) == 11 * 8
+    assert ctypes.sizeof(lib.DressProblem) == 5 * 8
+    assert ctypes.sizeof(lib.Opts) == 24
 
 
 SPECS = [
@@ -311,3 +312,29 @@ def test_cd_argument_errors_before_device_work(lib):
     assert L.cdcc_cd_vectors(ctypes.byref(m), pp, npv, outs, None) == lib.EINVAL
     npv[0] = 5
     assert L.cdcc_cd_vectors(ctypes.byref(m), pp, npv, outs, None) == lib.EINVAL
+
+
+def test_tile_size_class_keys():
+    """The tile table's size-class key: a function of the shape's size (the
+    same for a permutation of irreps that keeps every count), different for a
+    shape of another size, and per precision and kind."""
+    import paper_2512_21909_amd as cdcc
+    import synth as S
+    k = cdcc.ladder.tile_key
+    a = S.sym_custom([3, 2], [21, 14], [50, 31])
+    assert k(a, "mixed", "t2").startswith("mixed t2 b2 ")
+    assert k(a, "mixed", "t2") != k(a, "fp64", "t2") and k(a, "mixed", "t2") != k(a, "mixed", "lambda")
+    assert k(S.sym_custom([3, 2], [21, 14], [50, 32]), "mixed", "t2") == k(a, "mixed", "t2")   # same bucket
+    assert k(S.sym_d2h_large(), "mixed", "t2") != k(S.sym_d2h_medium("B"), "mixed", "t2")
+    parts = k(S.sym_d2h_large(), "fp64", "t2").split()
+    assert parts[2] == "b8" and all(p.lstrip("-").isdigit() for p in parts[3:])
+
+
+def test_tile_table_reader_round_trip(tmp_path):
+    """The autotuner's table writer and reader agree (exact and size-class
+    keys, class with and without a contraction segment)."""
+    from paper_2512_21909_amd import autotune
+    t = {"fp64 t2 1 8 40 300": "1", "mixed t2 b8 37 17 14": "2:2048"}
+    path = str(tmp_path / "tile_table.txt")
+    autotune.write_table(t, path)
+    assert autotune.load_table(path) == t
