@@ -120,9 +120,14 @@ struct BatchPlan {
   Launch red;  // split-K reduce + unpack jobs (count 0: none)
 };
 
-// Split-K segment of the contraction: fixed per group shape (never per
-// batch), so a system's result is the same alone and in any batch.
-constexpr int kKSeg = 1024;
+// Split-K segment of the contraction (default; the tile table or the
+// options can set another per shape): fixed per group shape, never per
+// batch, so a system's result is the same alone and in any batch.  4096
+// entries: at o=40/v=400 the contraction took 8.6 ms per call with 1024,
+// 8.1 with 2048 and 8.0 with 4096 to 65536 (the tiles of one launch fill the
+// chip without splitting, and the partials cost traffic); at o=20/v=200 the
+// lengths measured the same.
+constexpr int kKSeg = 4096;
 
 struct SysPlan {
   cdcc_layout_t lay{};
@@ -720,9 +725,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
           g.th_rs = int(align_up(n_ij, 16));
           g.r_off = L.amp_off[G];
           g.fm = contract_fm(int(n_ij));
-          // groups with more than four row tiles have tiles enough to fill
-          // the chip with segments twice as long (half the split-K partials)
-          const int kseg_len = SP.kseg > 0 ? (SP.kseg + 15) / 16 * 16 : (n_ij > 4 * 16 * g.fm ? 2 * kKSeg : kKSeg);
+          const int kseg_len = SP.kseg > 0 ? (SP.kseg + 15) / 16 * 16 : kKSeg;
           g.nsplit = std::max(1, (kt_len + kseg_len / 2) / kseg_len);
           g.kseg = ((kt_len + g.nsplit - 1) / g.nsplit + 15) / 16 * 16;
           if (g.nsplit > 1) g.nsplit = (kt_len + g.kseg - 1) / g.kseg;
