@@ -16,8 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libcdcc.so")
 BUILD = os.path.join(PKG, "_build")
 
-HIP_SOURCES = ["kernels_f64.hip", "kernels_mixed.hip", "kernels_density.hip", "kernels_partial.hip",
-               "kernels_cd.hip", "noalloc.hip"]
+HIP_SOURCES = ["kernels_f64.hip", "kernels_mixed.hip", "kernels_bf16.hip", "kernels_density.hip",
+               "kernels_partial.hip", "kernels_cd.hip", "noalloc.hip"]
 CXX_SOURCES = ["layout.cpp", "cdcc.cpp"]
 
 ARCH = "gfx950"
@@ -26,7 +26,8 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-munsafe-fp-atomics", "-ffp-contract=fast",
                 # keep MFMA accumulators in VGPRs: avoids an AGPR<->VGPR copy of
-                # every accumulator on each K step of the main loops
+                # every accumulator on each K step of the main loops (the AGPRs
+                # then hold MFMA operands and values that are seldom touched)
                 "-mllvm", "-amdgpu-mfma-vgpr-form"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 

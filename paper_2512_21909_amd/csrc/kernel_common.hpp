@@ -16,6 +16,18 @@ __device__ __forceinline__ const CDCC_GLOBAL T *as_global(const T *p) {
   return (const CDCC_GLOBAL T *)(p);
 }
 
+// s_waitcnt immediate (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8): wait for vmcnt <= v and lgkmcnt <= l.
+constexpr int waitcnt_imm(int v, int l) { return (v & 15) | ((v >> 4) << 14) | (7 << 4) | (l << 8); }
+
+// One 16-byte chunk per lane from global memory straight into LDS: lane l
+// writes bytes [16 l, 16 l + 16) after the wave-uniform LDS pointer dst.
+// The copies are counted on vmcnt; the caller waits for them with explicit
+// s_waitcnt vmcnt and a barrier.
+__device__ __forceinline__ void lds_copy16(const CDCC_GLOBAL unsigned char *src, unsigned char *dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst), 16, 0, 0);
+}
+
 // Claim the next tile; called by every lane of wave 0, the result is valid in
 // all of them (-1 when every queue is empty).  `dead` is per-workgroup state
 // (bit l: queue (xcd + l) % 8 known to be empty, in the XCD's stealing order).

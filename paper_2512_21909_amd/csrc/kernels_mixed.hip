@@ -60,18 +60,6 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // read with the same K order, so the order inside a 16-byte chunk never
 // matters.
 
-// s_waitcnt immediate (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
-// 6:4, lgkmcnt in 11:8): wait for vmcnt <= v and lgkmcnt <= l.
-constexpr int waitcnt_imm(int v, int l) { return (v & 15) | ((v >> 4) << 14) | (7 << 4) | (l << 8); }
-
-// One 16-byte chunk per lane from global memory straight into LDS: lane l
-// writes bytes [16 l, 16 l + 16) after the wave-uniform LDS pointer dst.
-// The copies are counted on vmcnt; the caller waits for them with explicit
-// s_waitcnt vmcnt and a barrier.
-__device__ __forceinline__ void lds_copy16(const CDCC_GLOBAL unsigned char *src, unsigned char *dst) {
-  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(dst), 16, 0, 0);
-}
-
 __device__ __forceinline__ uint16_t bf16_bits_exact(double v) {
   // v is a small integer times a power of two: exact in float and in BF16
   return uint16_t(__float_as_uint(float(v)) >> 16);
@@ -270,8 +258,10 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
 // 16 rows a 16-lane group of a fragment read touches then fall on 16
 // different 16-byte bank groups of the 256-byte bank width.  Rows past the
 // tile edge are read clamped: they only reach results that are never stored.
-// BF16: the sign of the subtracted part of the Lambda stack is applied to the
-// B fragments.  I8: the accumulators are negated at that part's first block.
+// The subtracted part of the Lambda stack negates the accumulators (and the
+// BF16 running total) at that part's first block, exactly, and the epilogue
+// negates the total back.  (Negating the B fragments instead would not give
+// bitwise the same sums: the MFMA's rounding is not symmetric in the sign.)
 // ---------------------------------------------------------------------------
 template <int BM, int BN, int WN, bool I8, bool LONGK>
 __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_kernel(
@@ -399,7 +389,6 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
     };
     auto step = [&](const unsigned char *L, int kb) {
       {
-        const unsigned flip = kb >= D.kneg_blk ? 0x80008000u : 0u;
         bf8 a[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) a[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + aoff[s]));
@@ -408,7 +397,7 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
           bf8 b[4];
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            b[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + boff[j][s]) ^ flip);
+            b[s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + boff[j][s]));
           acc0[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], acc0[j], 0, 0, 0);
           acc1[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], acc1[j], 0, 0, 0);
           acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc2[j], 0, 0, 0);
@@ -471,15 +460,25 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
             __builtin_amdgcn_s_waitcnt(waitcnt_imm(NI, 0));
             __builtin_amdgcn_s_barrier();
             __asm__ volatile("" ::: "memory");  // no LDS access moves above the barrier
-            if constexpr (I8) {
-              // first block of the subtracted half: acc <- -acc (here, not
-              // between the copies and the fragment reads, so that the reads
-              // can still be scheduled ahead of the copies)
-              if (kb + q == D.kneg_blk) {
+            // first block of the subtracted half: acc <- -acc and, BF16,
+            // tot <- -tot (exact; the total is negated back in the epilogue).
+            // Here, not between the copies and the fragment reads, so that
+            // the reads can still be scheduled ahead of the copies.
+            if (kb + q == D.kneg_blk) {
+              if constexpr (I8) {
 #pragma unroll
                 for (int w = 0; w < 5; ++w)
 #pragma unroll
                   for (int j = 0; j < NJ; ++j) iacc[w][j] = -iacc[w][j];
+              } else {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                  acc0[j] = -acc0[j];
+                  acc1[j] = -acc1[j];
+                  acc2[j] = -acc2[j];
+#pragma unroll
+                  for (int r = 0; r < 16; ++r) tot[j][r] = -tot[j][r];
+                }
               }
             }
             if constexpr (I8) {
@@ -500,8 +499,8 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
 
       // scale and permuted store (same numbering as the FP64 path); later
       // segments add to what the earlier ones stored (same lane, same element)
-      const double sgn = (I8 && kb1 > D.kneg_blk) ? -1.0 : 1.0;
-      const double unit = I8 ? 0.5 * sgn * (1.0 / 16384.0) : 0.5;  // digit products are in units of 2^-14
+      const double sgn = kb1 > D.kneg_blk ? -1.0 : 1.0;
+      const double unit = I8 ? 0.5 * sgn * (1.0 / 16384.0) : 0.5 * sgn;  // digit products are in units of 2^-14
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int n = n0 + wn * WN + j * 32 + (lane & 31);
@@ -565,6 +564,11 @@ static void launch_assemble_fmt(int cls, int grid, const P1Desc *descs, const Ti
   }
 }
 
+// the 128 x 128 split-BF16 class (kernels_bf16.hip)
+hipError_t launch_assemble_bf16(int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
+                                const SysPtrs *sp, double *xbuf, hipStream_t s);
+int occupancy_bf16();
+
 // longk: some tile of the launch has K > 32736 (8-bit path only)
 hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int grid, const P1Desc *descs, const Tile *tiles,
                                  const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s) {
@@ -573,6 +577,8 @@ hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int grid, const P1
     launch_assemble_fmt<true, true>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
   else if (fmt == 1)
     launch_assemble_fmt<true, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+  else if (cls == 2)
+    return launch_assemble_bf16(grid, descs, tiles, Q, cnt, sp, xbuf, s);
   else
     launch_assemble_fmt<false, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
   return hipGetLastError();
@@ -593,6 +599,9 @@ static int occupancy_fmt(int cls) {
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-int occupancy_mixed(int fmt, int cls) { return fmt == 1 ? occupancy_fmt<true>(cls) : occupancy_fmt<false>(cls); }
+int occupancy_mixed(int fmt, int cls) {
+  if (fmt == 0 && cls == 2) return occupancy_bf16();
+  return fmt == 1 ? occupancy_fmt<true>(cls) : occupancy_fmt<false>(cls);
+}
 
 }  // namespace cdcc
