@@ -45,8 +45,9 @@ hipError_t launch_energy(const EnergyJob *jobs, int njobs, const SysPtrs *sp, co
 // split paths (kernels_mixed.hip); fmt 0 = BF16 slices, 1 = 8-bit digits
 hipError_t launch_slice(int fmt, const SliceJob *jobs, const int2 *rows, int nrows, const SysPtrs *sp,
                         int stage_bytes, hipStream_t s);
-hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int grid, const P1Desc *descs, const Tile *tiles,
-                                 const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
+hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int neg, int grid, const P1Desc *descs,
+                                 const Tile *tiles, const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf,
+                                 hipStream_t s);
 int occupancy_mixed(int fmt, int cls);
 // vvvv density (kernels_f64.hip, kernels_density.hip)
 hipError_t launch_assemble_density(int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
@@ -1113,8 +1114,8 @@ int enqueue_sequence(const Plan &Pl, SysPtrs *dsp, int *counters, double *xbuf, 
       for (const Launch &l : B.p1) {
         int *cnt = counters + 8 * kQueueStride * ci++;
         if (is_split(P->precision))
-          HIPCHK(launch_assemble_mixed(split_fmt(P->precision), l.cls, l.longk, l.grid, P->p1, P->p1tiles + l.start,
-                                       l.q, cnt, dsp, xbuf, stream));
+          HIPCHK(launch_assemble_mixed(split_fmt(P->precision), l.cls, l.longk, P->lambda && P->dressed, l.grid,
+                                       P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
         else
           HIPCHK(launch_assemble_f64(l.cls, l.grid, P->p1, P->p1tiles + l.start, l.q, cnt, dsp, xbuf, stream));
       }

@@ -70,6 +70,8 @@ __device__ __forceinline__ unsigned lds_addr(const unsigned char *p) {
 // LDS row layout (as in kernels_mixed.hip): one K block of all four slices of
 // an operand row, eight 16-byte chunks; physical chunk c of row r holds
 // logical chunk c ^ ((r / 2) % 8), slice s being logical chunks 2s and 2s + 1.
+// NEG: the launch assembles a T1-dressed Lambda stack (with a subtracted half).
+template <bool NEG>
 __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__restrict__ descs,
                                                             const Tile *__restrict__ tiles, Queues Q,
                                                             int *__restrict__ cnt, const SysPtrs *__restrict__ sp,
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
           __builtin_amdgcn_s_barrier();
           __asm__ volatile("" ::: "memory");  // no LDS access moves above the barrier
           if (k + 3 < nkb) issue(q == 0 ? st3 : q == 1 ? st0 : q == 2 ? st1 : st2, k + 3);
-          if (k == kneg) {
+          if (NEG && k == kneg) {
             // first block of the subtracted half: negate (exact), and the
             // total is negated back in the epilogue
 #pragma unroll
@@ -333,16 +335,19 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
   }
 }
 
-hipError_t launch_assemble_bf16(int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
+hipError_t launch_assemble_bf16(int neg, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
                                 const SysPtrs *sp, double *xbuf, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  assemble_bf16_kernel<<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf);
+  if (neg)
+    assemble_bf16_kernel<true><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf);
+  else
+    assemble_bf16_kernel<false><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf);
   return hipGetLastError();
 }
 
 int occupancy_bf16() {
   int n = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_bf16_kernel, 256, 0);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_bf16_kernel<false>, 256, 0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 

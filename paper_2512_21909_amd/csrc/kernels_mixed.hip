@@ -260,10 +260,11 @@ __global__ __launch_bounds__(256) void slice_kernel(const SliceJob *__restrict__
 // tile edge are read clamped: they only reach results that are never stored.
 // The subtracted part of the Lambda stack negates the accumulators (and the
 // BF16 running total) at that part's first block, exactly, and the epilogue
-// negates the total back.  (Negating the B fragments instead would not give
+// negates the total back; NEG instantiations (launches of a T1-dressed Lambda
+// stack) hold that code, the others do not.  (Negating the B fragments instead would not give
 // bitwise the same sums: the MFMA's rounding is not symmetric in the sign.)
 // ---------------------------------------------------------------------------
-template <int BM, int BN, int WN, bool I8, bool LONGK>
+template <int BM, int BN, int WN, bool I8, bool LONGK, bool NEG>
 __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_kernel(
     const P1Desc *__restrict__ descs, const Tile *__restrict__ tiles, Queues Q, int *__restrict__ cnt,
     const SysPtrs *__restrict__ sp, double *__restrict__ xbuf) {
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(64 * (BM / 32) * (BN / WN)) void assemble_mixed_ker
             // tot <- -tot (exact; the total is negated back in the epilogue).
             // Here, not between the copies and the fragment reads, so that
             // the reads can still be scheduled ahead of the copies.
-            if (kb + q == D.kneg_blk) {
+            if (NEG && kb + q == D.kneg_blk) {
               if constexpr (I8) {
 #pragma unroll
                 for (int w = 0; w < 5; ++w)
@@ -553,34 +554,44 @@ hipError_t launch_slice(int fmt, const SliceJob *jobs, const int2 *rows, int nro
   return hipGetLastError();
 }
 
-template <bool I8, bool LONGK>
-static void launch_assemble_fmt(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
-                                const SysPtrs *sp, double *xbuf, hipStream_t s) {
-  switch (cls) {
-    case 0: assemble_mixed_kernel<64, 128, 64, I8, LONGK><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
-    case 1: assemble_mixed_kernel<128, 64, 64, I8, LONGK><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
-    case 2: assemble_mixed_kernel<128, 128, 64, I8, LONGK><<<grid, 512, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
-    default: assemble_mixed_kernel<64, 64, 32, I8, LONGK><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
-  }
-}
-
 // the 128 x 128 split-BF16 class (kernels_bf16.hip)
-hipError_t launch_assemble_bf16(int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
+hipError_t launch_assemble_bf16(int neg, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
                                 const SysPtrs *sp, double *xbuf, hipStream_t s);
 int occupancy_bf16();
 
-// longk: some tile of the launch has K > 32736 (8-bit path only)
-hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int grid, const P1Desc *descs, const Tile *tiles,
-                                 const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s) {
+template <bool I8, bool LONGK, bool NEG>
+static void launch_assemble_fmt(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
+                                const SysPtrs *sp, double *xbuf, hipStream_t s) {
+  switch (cls) {
+    case 0: assemble_mixed_kernel<64, 128, 64, I8, LONGK, NEG><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    case 1: assemble_mixed_kernel<128, 64, 64, I8, LONGK, NEG><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    case 2: assemble_mixed_kernel<128, 128, 64, I8, LONGK, NEG><<<grid, 512, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+    default: assemble_mixed_kernel<64, 64, 32, I8, LONGK, NEG><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf); break;
+  }
+}
+
+// longk: some tile of the launch has K > 32736 (8-bit path only); neg: the
+// launch assembles a T1-dressed Lambda stack (a subtracted half)
+hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int neg, int grid, const P1Desc *descs,
+                                 const Tile *tiles, const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf,
+                                 hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (fmt == 1 && longk)
-    launch_assemble_fmt<true, true>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
-  else if (fmt == 1)
-    launch_assemble_fmt<true, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
-  else if (cls == 2)
-    return launch_assemble_bf16(grid, descs, tiles, Q, cnt, sp, xbuf, s);
-  else
-    launch_assemble_fmt<false, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+  if (fmt == 1) {
+    if (longk && neg)
+      launch_assemble_fmt<true, true, true>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+    else if (longk)
+      launch_assemble_fmt<true, true, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+    else if (neg)
+      launch_assemble_fmt<true, false, true>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+    else
+      launch_assemble_fmt<true, false, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+  } else if (cls == 2) {
+    return launch_assemble_bf16(neg, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+  } else if (neg) {
+    launch_assemble_fmt<false, false, true>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+  } else {
+    launch_assemble_fmt<false, false, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
+  }
   return hipGetLastError();
 }
 
@@ -589,13 +600,13 @@ static int occupancy_fmt(int cls) {
   int n = 0;
   hipError_t e;
   if (cls == 0)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 128, 64, I8, false>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 128, 64, I8, false, false>, 256, 0);
   else if (cls == 1)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 64, 64, I8, false>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 64, 64, I8, false, false>, 256, 0);
   else if (cls == 2)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 128, 64, I8, false>, 512, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<128, 128, 64, I8, false, false>, 512, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 64, 32, I8, false>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_mixed_kernel<64, 64, 32, I8, false, false>, 256, 0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
