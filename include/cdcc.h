@@ -104,7 +104,9 @@ typedef struct {
  * i >= j are read.  R receives the full result (every stored element is
  * written).  Optional outputs (NULL = skip): delta = R / D with
  * D_ij^ab = eps_i + eps_j - eps_a - eps_b (needs eps_occ, eps_vir), and
- * pair_energy e_IJ = sum_ab (2 X_ij^ab - X_ij^ba) R_ij^ab.  Lambda only:
+ * pair_energy e_IJ = sum_ab (2 T_ij^ab - T_ij^ba) R_ij^ab with T = X, or
+ * T = energy_amps when that is given (for instance the T2 amplitudes with
+ * the Lambda residual).  Lambda only:
  * Bvo and t1 enable the T1 dressing of Appendix A; both NULL gives the
  * undressed W_efab = (ea|fb).  Input buffers must not overlap R/delta.
  */
@@ -122,6 +124,8 @@ typedef struct {
   const double *U;           /* Lambda only: device, 2*lay->b_size, the dressed */
                              /* stack of cdcc_lambda_dress (Bvo, t1 unused), or */
                              /* NULL; must be NULL for the T2 ladder            */
+  const double *energy_amps; /* device, lay->amp_size, pair-symmetric, or NULL */
+                             /* (= X): the T of the pair energies              */
 } cdcc_problem_t;
 
 typedef struct {

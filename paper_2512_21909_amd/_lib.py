@@ -40,7 +40,7 @@ class Problem(ctypes.Structure):
         ("Bvo", ctypes.c_void_p), ("t1", ctypes.c_void_p),
         ("eps_occ", ctypes.c_void_p), ("eps_vir", ctypes.c_void_p),
         ("delta", ctypes.c_void_p), ("pair_energy", ctypes.c_void_p),
-        ("U", ctypes.c_void_p),
+        ("U", ctypes.c_void_p), ("energy_amps", ctypes.c_void_p),
     ]
 
 

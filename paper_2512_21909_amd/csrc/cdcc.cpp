@@ -340,6 +340,7 @@ std::string plan_key(int dev, int nsys, const cdcc_problem_t *p, int lambda, int
   put(nsys);
   for (int s = 0; s < nsys; ++s) {
     const cdcc_sym_t &y = p[s].lay->sym;
+    put(p[s].pair_energy != nullptr);  // the plan holds the pair-energy jobs only when asked for
     put(y.nirrep);
     for (int g = 0; g < y.nirrep; ++g) {
       put(y.nocc[g]);
@@ -1184,6 +1185,7 @@ int run_ladder(int32_t nsys, const cdcc_problem_t *probs, const cdcc_opts_t *pop
     q.eps_occ = p.eps_occ;
     q.eps_vir = p.eps_vir;
     q.epair = p.pair_energy;
+    q.eamp = p.energy_amps ? p.energy_amps : p.X;
     q.tauhat = reinterpret_cast<double *>(base + W.th[s]);
     q.B = p.B;
     q.Bvo = p.Bvo;
@@ -2284,6 +2286,7 @@ int run_ladder_in_region(int32_t nsys, const cdcc_problem_t *probs, const cdcc_o
     q.eps_occ = p.eps_occ;
     q.eps_vir = p.eps_vir;
     q.epair = p.pair_energy;
+    q.eamp = p.energy_amps ? p.energy_amps : p.X;
     q.tauhat = reinterpret_cast<double *>(base + W.th[s]);
     q.B = p.B;
     q.slices = reinterpret_cast<unsigned char *>(base + W.sl[s]);

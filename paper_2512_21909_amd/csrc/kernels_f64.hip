@@ -650,7 +650,7 @@ __global__ __launch_bounds__(512) void energy_kernel(const EnergyJob *__restrict
   const EnergyJob J = jobs[blockIdx.x];
   const SysPtrs S = sp[J.sys];
   if (!S.epair) return;
-  const CDCC_GLOBAL double *xr = as_global(S.X) + J.r_off + int64_t(J.row) * J.ldr;
+  const CDCC_GLOBAL double *xr = as_global(S.eamp) + J.r_off + int64_t(J.row) * J.ldr;
   const CDCC_GLOBAL double *rr = as_global(S.R) + J.r_off + int64_t(J.row) * J.ldr;
   const CDCC_GLOBAL int *tc = as_global(vvfull) + J.vvfull_off;
   // U columns per thread per pass: all loads of a pass are issued before the

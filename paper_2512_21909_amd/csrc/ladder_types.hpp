@@ -21,6 +21,7 @@ struct SysPtrs {
   const double *t1;      // optional singles (Lambda)
   unsigned char *slices; // workspace: sliced assembly operand (split paths: BF16 or 8-bit digits)
   double *rowscale;      // workspace: per-row power-of-two scales of the operand (mixed path)
+  const double *eamp;    // amplitudes T of the pair energies (energy_amps, else X)
 };
 
 // Packing of X into the +/- halves for one (system, pair irrep G).

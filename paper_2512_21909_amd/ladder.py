@@ -45,7 +45,8 @@ def _ptr(t, n, name, optional=False):
 def make_problems(problems: list[dict], lambda_: bool):
     """Marshal a list of problem dicts into a ctypes array of cdcc_problem_t.
     Keys: layout (Layout), B, X, R; optional eps_occ, eps_vir, delta,
-    pair_energy; Lambda: Bvo, t1, or U (the stack of lambda_dress)."""
+    pair_energy, energy_amps (the T of the pair energies, default X);
+    Lambda: Bvo, t1, or U (the stack of lambda_dress)."""
     arr = (_lib.Problem * len(problems))()
     keep = []
     for k, p in enumerate(problems):
@@ -60,6 +61,7 @@ def make_problems(problems: list[dict], lambda_: bool):
         q.eps_vir = _ptr(p.get("eps_vir"), lay.nvir_tot, "eps_vir", True)
         q.delta = _ptr(p.get("delta"), lay.amp_size, "delta", True)
         q.pair_energy = _ptr(p.get("pair_energy"), lay.nocc_tot * lay.nocc_tot, "pair_energy", True)
+        q.energy_amps = _ptr(p.get("energy_amps"), lay.amp_size, "energy_amps", True)
         if lambda_:
             q.Bvo = _ptr(p.get("Bvo"), lay.bvo_size, "Bvo", True)
             q.t1 = _ptr(p.get("t1"), lay.t1_size, "t1", True)

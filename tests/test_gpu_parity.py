@@ -523,3 +523,39 @@ def test_lambda_with_stack_built_once(gpu_lib, precision):
             assert np.array_equal(e["R"].cpu().numpy(), d["R"].cpu().numpy())
         else:
             assert _pair_energy_err(e, p, ref) <= PAIR_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind", ["t2", "lambda"])
+def test_pair_energy_from_other_amplitudes(gpu_lib, kind, precision):
+    """energy_amps: the pair energies weight R with a caller-given
+    pair-symmetric tensor T (here the amplitudes of another seed) in place of
+    X; R itself is bitwise unchanged by the option, and without it X is used."""
+    from tests.gpu_support import to_dev
+    prob = problem(S.sym_custom([3, 2], [21, 14], [50, 31]), seed=8, kind=kind)
+    other = problem(prob["sym"], seed=9)["X"]
+    d0 = device_problem(gpu_lib, prob, want_energy=True)
+    run(gpu_lib, d0, kind=kind, precision=precision)
+    d = device_problem(gpu_lib, prob, want_energy=True)
+    d["energy_amps"] = to_dev(d["layout"].pack_amp(other))
+    run(gpu_lib, d, kind=kind, precision=precision)
+    assert np.array_equal(d["R"].cpu().numpy(), d0["R"].cpu().numpy())
+    ref = oracle_result(prob)
+    lay = OracleLayout(prob["sym"])
+    Rf = lay.full_amp(ref)
+    for dd, amps in ((d, other), (d0, prob["X"])):
+        e_ref = O.pair_energies_full(lay.full_amp(amps), Rf)
+        e_got = dd["pair_energy"].cpu().numpy().reshape(e_ref.shape)
+        tol = 1e-12 * max(1.0, np.max(np.abs(e_ref))) if precision == "fp64" else PAIR_TOL
+        assert np.max(np.abs(e_got - e_ref)) <= tol
+
+
+def test_pair_energy_after_a_call_without(gpu_lib):
+    """A call of the same shape without pair energies first: its cached plan
+    holds no pair-energy work, and the next call, which asks for them, must
+    not reuse it (regression test: the energies were left unwritten)."""
+    prob = problem(S.sym_custom([2, 2], [9, 7], [23, 19]), seed=4)
+    run(gpu_lib, device_problem(gpu_lib, prob))
+    d = device_problem(gpu_lib, prob, want_energy=True)
+    run(gpu_lib, d)
+    assert _pair_energy_err(d, prob, oracle_result(prob)) <= 1e-12

@@ -35,7 +35,7 @@ def test_struct_sizes_match_header(lib):
     # 4 + 3*8*4 = 100 -> padded to 104 by the following int64 arrays
     assert ctypes.sizeof(lib.Sym) == 100
     assert ctypes.sizeof(lib.LayoutC) == 104 + 8 * (5 * 8 + 4 * 64 + 4 * 8 + 7)
-    assert ctypes.sizeof(lib.Problem) == 11 * 8
+    assert ctypes.sizeof(lib.Problem) == 12 * 8
     assert ctypes.sizeof(lib.DressProblem) == 5 * 8
     assert ctypes.sizeof(lib.Opts) == 24
 
