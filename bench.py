@@ -491,6 +491,9 @@ def ladder_main(args, cdcc):
         "metric": METRIC, "value": m["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": DTYPE[best], "data": "synthetic",
+        # the S/A contraction (and everything after it) is FP64 in every path;
+        # the split forms apply to the (ac|bd) assembly
+        "dtype_contraction": "f64",
         "config": {"workload": m["workload"], "flops_per_step": m["flops_per_step"], "path": best},
         "roofline": m["roofline"],
         "paths": m["paths"],
