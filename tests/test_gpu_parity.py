@@ -559,3 +559,25 @@ def test_pair_energy_after_a_call_without(gpu_lib):
     d = device_problem(gpu_lib, prob, want_energy=True)
     run(gpu_lib, d)
     assert _pair_energy_err(d, prob, oracle_result(prob)) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", SPLIT)
+@pytest.mark.parametrize("kind", ["t2", "lambda"])
+@pytest.mark.parametrize("spec", [([2, 1], [9, 7], [5, 17]), ([1], [5], [16500])])
+def test_split_tile_classes_short_and_long_k(gpu_lib, spec, kind, precision):
+    """Every split tile class, forced, on K of one to three 16-wide blocks
+    (5 and 17 vectors: the K loops' tails) and on K far beyond the 256-wide
+    flush interval (16500 vectors; 33000 stacked for Lambda): bitwise equal
+    across classes and within the mixed tolerance of the oracle."""
+    prob = problem(S.sym_custom(*spec), seed=21, kind=kind)
+    ref = oracle_result(prob)
+    r0 = None
+    for cls in (1, 2, 3, 4):
+        d = device_problem(gpu_lib, prob)
+        run(gpu_lib, d, kind=kind, precision=precision, tile_policy=cls)
+        r = d["R"].cpu().numpy()
+        if r0 is None:
+            r0 = r
+            _check(blocks(d), ref, MIXED_TOL, f"{spec} {kind} class {cls}")
+        else:
+            assert np.array_equal(r, r0), cls
