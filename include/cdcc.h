@@ -132,8 +132,11 @@ typedef struct {
   int32_t precision;         /* CDCC_FP64, CDCC_MIXED or CDCC_MIXED_I8          */
   int32_t tile_policy;       /* 0 = tile table, k = force assembly class k-1:   */
                              /* 1..3 (FP64), 1..4 (the two split precisions)   */
-  int64_t batch_bytes;       /* cap of the (ac|bd) batch buffer, 0 = default    */
-                             /* (4 GiB, or CDCC_BATCH_MB megabytes)             */
+  int64_t batch_bytes;       /* cap of the (ac|bd) batch buffer, 0 = default:  */
+                             /* CDCC_BATCH_MB megabytes if set, else one batch */
+                             /* when the whole intermediate fits 16 GiB and    */
+                             /* batches of at most 4 GiB otherwise; the vvvv   */
+                             /* density's default is 4 GiB                     */
   int32_t contract_kseg;     /* K-table entries per contraction segment (split */
                              /* K), 0 = tile table, else the built-in rule;    */
                              /* changes the rounding order of S and A only     */

@@ -503,6 +503,9 @@ void pair_table(const int32_t *n, int h, int G, const int64_t off[CDCC_MAX_IRREP
 // table_base: NULL = the plan allocates and fills its device tables; else the
 // tables are laid out for that device address and kept on the host
 // (P.host_tables), and the caller copies them there before every use.
+// largest (ac|bd) region of one column group (the a range is split above it)
+constexpr int64_t kGroupRegionMaxBytes = int64_t(4) << 30;
+
 int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, const cdcc_opts_t &opts, int64_t cap,
                Plan &P, void *table_base = nullptr) {
   P.nsys = nsys;
@@ -527,7 +530,10 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     int sys = 0;
   };
   std::vector<GroupRec> groups;
+  // cap_elems bounds a batch; a column group's own region is further held to
+  // kGroupRegionMaxBytes
   const int64_t cap_elems = std::max<int64_t>(cap / 8, 1);
+  const int64_t group_cap_elems = std::max<int64_t>(std::min(cap, kGroupRegionMaxBytes) / 8, 1);
 
   // rows of up to kSliceStageMax bytes are staged in LDS by the slice launch;
   // the mixed Lambda stack is then built there and never stored
@@ -708,7 +714,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
         int a0 = 0;
         while (a0 < nv[ga]) {
           int a1 = a0 + 1;
-          while (a1 < nv[ga] && std::max<int64_t>(nrows, 1) * ncols_of(a0, a1 + 1) <= cap_elems) ++a1;
+          while (a1 < nv[ga] && std::max<int64_t>(nrows, 1) * ncols_of(a0, a1 + 1) <= group_cap_elems) ++a1;
           GroupRec R;
           R.sys = s;
           P2Group &g = R.g;
@@ -775,7 +781,17 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
     }
   }
 
-  // batches: consecutive groups whose regions fit the cap
+  // batches: consecutive groups whose regions fit the cap.  Under the
+  // library's default cap the call runs as one batch when all of its regions
+  // fit (no launch tails between batches), else in batches of at most
+  // kGroupRegionMaxBytes (larger ones measured slower at the o=135/v=543
+  // size).  A cap set by the caller or by CDCC_BATCH_MB is used as given.
+  int64_t batch_elems = cap_elems;
+  if (opts.batch_bytes <= 0 && std::getenv("CDCC_BATCH_MB") == nullptr) {
+    int64_t total = 0;
+    for (const GroupRec &R : groups) total += align_up(R.region, 32);
+    if (total > cap_elems) batch_elems = std::min(cap_elems, group_cap_elems);
+  }
   std::vector<P1Desc> p1;
   std::vector<Tile> p1tiles;
   std::vector<P2Group> p2;
@@ -785,7 +801,7 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
   while (gi < groups.size()) {
     int64_t used = 0;
     size_t gj = gi;
-    while (gj < groups.size() && (gj == gi || used + groups[gj].region <= cap_elems)) {
+    while (gj < groups.size() && (gj == gi || used + groups[gj].region <= batch_elems)) {
       used += align_up(groups[gj].region, 32);
       ++gj;
     }
@@ -1026,9 +1042,11 @@ int validate(int32_t nsys, const cdcc_problem_t *probs, int lambda, int *dressed
   return CDCC_OK;
 }
 
-// Default cap of the (ac|bd) batch buffer: 4 GiB, a small share of the 288 GB
-// of one MI355X; fewer, larger batches fill the chip better.
-constexpr int64_t kDefaultBatchMB = 4096;
+// Default cap of the (ac|bd) batch buffer: 16 GiB, a small share of the 288 GB
+// of one MI355X; fewer, larger batches fill the chip better (each launch ends
+// in a tail where CUs idle).  The vvvv density keeps 4 GiB batches.
+constexpr int64_t kDefaultBatchMB = 16384;
+constexpr int64_t kDefaultDensityBatchMB = 4096;
 
 int64_t batch_cap(const cdcc_opts_t &o) {
   int64_t cap = o.batch_bytes > 0 ? o.batch_bytes : env_i64("CDCC_BATCH_MB", kDefaultBatchMB) * (int64_t(1) << 20);
@@ -1529,7 +1547,7 @@ int run_density(int32_t nsys, const cdcc_density_problem_t *probs, const cdcc_op
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) g_num_cu = ncu;
   }
   const int64_t cap =
-      opts.batch_bytes > 0 ? opts.batch_bytes : env_i64("CDCC_BATCH_MB", kDefaultBatchMB) * (int64_t(1) << 20);
+      opts.batch_bytes > 0 ? opts.batch_bytes : env_i64("CDCC_BATCH_MB", kDefaultDensityBatchMB) * (int64_t(1) << 20);
   std::string key = "density|" + std::to_string(dev) + "|" + std::to_string(cap) + "|" + std::to_string(nsys);
   for (int s = 0; s < nsys; ++s) {
     const cdcc_sym_t &y = probs[s].lay->sym;
