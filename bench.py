@@ -53,15 +53,16 @@ PAIR_GATE = 1e-8   # Eh, split paths (FP64: 1e-12 relative to max |e_ij|)
 # a plain 256 MiB device copy), per (workload, path, kernel), for the kernels
 # as committed (profiles/).  A "launch" is what the library times as one: an
 # assembly launch (the T2 and the Lambda launch of a step averaged), or one
-# batch's contraction with its split-K reduction and unpack.  The vvvv density
+# batch's contraction with its split-K reduction and unpack (at o=40/v=400 a
+# call is one batch).  The vvvv density
 # and partial-contraction entries are the launch of their GEMM kernel,
 # counted the same way.
 TRAFFIC = {("d2h_medium", "mixed", "assemble"): 3.197e9, ("d2h_medium", "fp64", "assemble"): 2.266e9,
            ("d2h_medium", "mixed_i8", "assemble"): 1.392e9,
-           ("d2h_large", "fp64", "assemble"): 11.250e9, ("d2h_large", "mixed", "assemble"): 10.556e9,
-           ("d2h_large", "mixed_i8", "assemble"): 6.770e9,
-           ("d2h_large", "fp64", "contract"): 6.584e9, ("d2h_large", "mixed", "contract"): 6.584e9,
-           ("d2h_large", "mixed_i8", "contract"): 6.584e9,
+           ("d2h_large", "fp64", "assemble"): 45.980e9, ("d2h_large", "mixed", "assemble"): 41.673e9,
+           ("d2h_large", "mixed_i8", "assemble"): 26.958e9,
+           ("d2h_large", "fp64", "contract"): 35.871e9, ("d2h_large", "mixed", "contract"): 35.871e9,
+           ("d2h_large", "mixed_i8", "contract"): 35.871e9,
            ("vvvv_d2h_medium", "fp64", "gemm"): 3.800e9,
            ("pm_d2h_medium", "fp64", "gemm"): 0.277e9, ("pm_d2h_large", "fp64", "gemm"): 7.494e9}
 # A single system is checked on every element when the plain oracle costs at
