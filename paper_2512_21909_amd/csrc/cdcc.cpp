@@ -980,6 +980,8 @@ int build_plan(int nsys, const cdcc_problem_t *probs, int lambda, int dressed, c
 }
 
 // Workspace layout of one call.
+constexpr int64_t kEpilogueSinkBytes = 64 * 64 * 8;
+
 struct WsLayout {
   int64_t counters = 0, sysptrs = 0, xbuf = 0, part = 0, total = 0;
   std::vector<int64_t> th, u, sl, sc;
@@ -992,8 +994,11 @@ WsLayout ws_layout(const Plan &P) {
   o = align_up(o + int64_t(std::max(P.ncounters, 1)) * 4);
   W.sysptrs = o;
   o = align_up(o + int64_t(P.nsys) * int64_t(sizeof(SysPtrs)));
-  W.xbuf = o;
-  o = align_up(o + P.xbuf_elems * 8);
+  // 64 x 64 doubles just below the batch buffer take the split-BF16
+  // epilogue's stores of elements it does not keep (it issues a fixed number
+  // per tile)
+  W.xbuf = o + kEpilogueSinkBytes;
+  o = align_up(W.xbuf + P.xbuf_elems * 8);
   W.part = o;
   o = align_up(o + P.part_elems * 8);
   W.th.resize(P.nsys);

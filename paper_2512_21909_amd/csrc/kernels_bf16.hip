@@ -163,9 +163,21 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
     if (nkb > 2) issue(st2, 2);
   };
 
+  // every lane stores 64 elements per tile, those outside the stored
+  // triangle or the tile's edge into its slot of a 64 x 64 sink just below
+  // the batch buffer, so that each tile starts with exactly 64 stores in
+  // flight after its first copies (the first tile's are 64 stores to
+  // distinct sink slots here, which the compiler cannot merge)
+  double *const sink = xbuf - 64 * 64 + lane;
   int t = next_tile(cnt, Q, dead, &s_tile);
   int par = 0;
-  if (t >= 0) prepare(t);
+  if (t >= 0) {
+    prepare(t);
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int e = 0; e < 64; ++e) sink[64 * e] = 0.0;
+    __asm__ volatile("" ::: "memory");
+  }
 
   while (t >= 0) {
     // acc0: s0 s0; acc1: s0 s1 and s1 s0; acc2: the eight products of weights
@@ -228,11 +240,15 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
       __builtin_amdgcn_sched_barrier(0);
     };
 
-    // block 0: every copy of this wave has landed (the previous tile's
-    // stores included), then every wave's; its fragments go to registers.
-    // The epilogue table of this tile goes to slot par (the previous tile's
-    // epilogue, which other waves may still be in, reads the other slot).
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
+    // block 0: every copy of this wave has landed, then every wave's; its
+    // fragments go to registers.  The 64 stores of the previous epilogue
+    // (or of the sink) were issued after this tile's scale load and first
+    // copies, and vector memory operations complete in issue order, so at
+    // most 63 in flight leaves the load and the copies of blocks 0-2 done
+    // while the stores drain.  The epilogue table of this tile goes to slot
+    // par (the previous tile's epilogue, which other waves may still be in,
+    // reads the other slot).
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(63, 0));
     etab[par][tid] = pe;
     ekey[par][tid] = pk;
     __builtin_amdgcn_s_barrier();
@@ -248,13 +264,15 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
         const int k = k0 + q;
         if (k < nkb) {
           // this wave's copies of block k + 1 have landed once only those of
-          // block k + 2 may be in flight; after the barrier every wave's
-          // have, and every wave is done with block k - 1 (its stage is
-          // refilled below)
-          if (k + 2 < nkb)
-            __builtin_amdgcn_s_waitcnt(waitcnt_imm(kNI, 15));
-          else
-            __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
+          // block k + 2 may be in flight (blocks 1 and 2 have landed by the
+          // tile's first wait); after the barrier every wave's have, and
+          // every wave is done with block k - 1 (its stage is refilled below)
+          if (k >= 2) {
+            if (k + 2 < nkb)
+              __builtin_amdgcn_s_waitcnt(waitcnt_imm(kNI, 15));
+            else
+              __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 15));
+          }
           __builtin_amdgcn_s_barrier();
           __asm__ volatile("" ::: "memory");  // no LDS access moves above the barrier
           if (k + 3 < nkb) issue(q == 0 ? st3 : q == 1 ? st0 : q == 2 ? st1 : st2, k + 3);
@@ -327,7 +345,10 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
         const int rk = ekey[par][row];
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          if (ck[j] <= rk) xbuf[re.part + ce[j].part] = (unit * (re.s * ce[j].s)) * tot[i][j][r];
+        {
+          double *const dst = ck[j] <= rk ? xbuf + (re.part + ce[j].part) : sink;
+          *dst = (unit * (re.s * ce[j].s)) * tot[i][j][r];
+        }
       }
     __asm__ volatile("" ::: "memory");  // and before the next tile's table writes
     t = tn;
