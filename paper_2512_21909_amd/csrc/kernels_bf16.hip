@@ -19,7 +19,10 @@
 //    fragments of every block;
 //  * the next tile's first copies are issued before this tile's epilogue, and
 //    the epilogue takes each element's X offset and scale from row and column
-//    tables that were written to LDS when the tile was set up.
+//    tables that were written to LDS when the tile was set up;
+//  * the epilogue always issues 64 stores per lane (elements it does not keep
+//    go to a sink below the batch buffer), so the next tile's first wait can
+//    leave them in flight.
 #include <hip/hip_runtime.h>
 
 #include <climits>
