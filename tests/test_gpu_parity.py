@@ -186,6 +186,22 @@ def test_t2_d2h_large_full(gpu_lib, precision):
         assert err_e <= 1e-8
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_t2_d2h_large_one_batch_equals_four(gpu_lib, precision):
+    """The o=40/v=400 intermediate (about 14 GB) runs as one batch under the
+    default cap and as four under a 4 GiB cap; R and the pair energies are
+    bitwise the same."""
+    prob = _LARGE["prob"] if _LARGE else problem(S.sym_d2h_large(), seed=0)
+    out = []
+    for kw in ({}, {"batch_bytes": 4 << 30}):
+        d = device_problem(gpu_lib, prob, want_energy=True)
+        run(gpu_lib, d, precision=precision, **kw)
+        out.append((d["R"].cpu().numpy(), d["pair_energy"].cpu().numpy()))
+        del d
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 # ---------------------------------------------------------------- mixed path
 MIXED_TOL = 1e-7      # normwise relative
 PAIR_TOL = 1e-8       # Eh, absolute
