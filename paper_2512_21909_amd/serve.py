@@ -8,7 +8,9 @@ amplitudes) already resident in device memory.  The server
   requests; a request that can never fit is rejected at submission;
 * launches every batch of admitted requests as ONE batched library call
   (``cdcc_ladder_t2`` / ``cdcc_ladder_lambda`` with nsys = batch size) on a
-  free stream, so that batches on different streams overlap on the device;
+  free stream, so that batches on different streams overlap on the device; a
+  request of at least ``solo_flops`` runs as a batch of its own, so that the
+  small requests of a batch never wait for a large one;
   before launching it reserves the batch's library workspace (queried with
   ``cdcc_workspace_bytes``; the library keeps a grow-only workspace per stream);
 * retires batches by polling their completion events and records per-request
@@ -68,9 +70,15 @@ class Request:
 
 class LadderServer:
     def __init__(self, hbm_budget_bytes: int, n_streams: int = 3, precision: str = "fp64",
-                 max_batch: int = 16, batch_bytes: int = 256 << 20, clock=time.perf_counter):
+                 max_batch: int = 16, batch_bytes: int = 256 << 20, clock=time.perf_counter,
+                 solo_flops: float | None = 1e11):
         import torch
         self.torch = torch
+        # a request of at least this many flops (1e11: about 1.5-2.5 ms of
+        # device time, enough to fill the GPU alone) runs as a batch of its
+        # own, and batches of smaller requests never wait for one; None
+        # batches every request alike
+        self.solo_flops = solo_flops
         self.budget = int(hbm_budget_bytes)
         self.precision = precision
         self.max_batch = max_batch
@@ -127,10 +135,11 @@ class LadderServer:
     def _launch(self) -> None:
         while self.ready and self.free:
             head = self.ready[0]
-            if head.solo:
+            if head.solo or self._heavy(head):
                 batch = [head]
             else:
-                batch = [r for r in self.ready if r.kind == head.kind and not r.solo][:self.max_batch]
+                batch = [r for r in self.ready
+                         if r.kind == head.kind and not r.solo and not self._heavy(r)][:self.max_batch]
             probs = [r.problem() for r in batch]
             need = workspace_bytes(probs, head.kind == "lambda", self.precision, batch_bytes=self.batch_bytes)
             s = self.free[0]
@@ -180,6 +189,9 @@ class LadderServer:
             for r in batch:
                 r.t_launch, r.status = now, "running"
             self.running.append((s, ev, batch))
+
+    def _heavy(self, r: Request) -> bool:
+        return self.solo_flops is not None and r.flops >= self.solo_flops
 
     def _release_done(self) -> None:
         for r in self.finished:
@@ -239,12 +251,13 @@ def make_stream(pool, n: int, rate_hz: float, seed: int = 5, p_large: float = 0.
     return reqs
 
 
-def measure(pool, precision="fp64", n_requests=2000, warmup=200, load=0.7, n_streams=3, max_batch=16, seed=5):
+def measure(pool, precision="fp64", n_requests=2000, warmup=200, load=0.7, n_streams=3, max_batch=16, seed=5,
+            **server_kw):
     """Warm-up (``warmup`` requests at t=0, at least two per pool shape, not
     counted), saturation throughput of the mix (``n_requests`` at t=0), then a
     Poisson stream of ``n_requests`` at ``load`` times that rate.  ``pool``:
     device-resident request inputs (dicts with layout, B, X, flops, large)."""
-    out = measure_sweep(pool, precision, n_requests, (load,), n_streams, max_batch, seed, warmup)
+    out = measure_sweep(pool, precision, n_requests, (load,), n_streams, max_batch, seed, warmup, **server_kw)
     st = out.pop("streams")[0]
     out["load"], out["rate_hz"] = st.pop("load"), st.pop("rate_hz")
     out["stream"] = st
@@ -252,17 +265,18 @@ def measure(pool, precision="fp64", n_requests=2000, warmup=200, load=0.7, n_str
 
 
 def measure_sweep(pool, precision="fp64", n_requests=2000, loads=(0.3, 0.5, 0.7, 0.9), n_streams=3,
-                  max_batch=16, seed=5, warmup=200, log=None):
+                  max_batch=16, seed=5, warmup=200, log=None, **server_kw):
     """Warm-up (``warmup`` requests at t=0, at least two per pool shape, not
     counted), saturation throughput of the mix, then one Poisson stream of
     ``n_requests`` per entry of ``loads`` (a fraction of the saturation
-    rate).  ``log(str)`` is called after each measured run."""
+    rate).  ``log(str)`` is called after each measured run; ``server_kw``
+    go to every ``LadderServer``."""
     import torch
     free, total = torch.cuda.mem_get_info()
     budget = int(free * 0.6)
 
     def server():
-        return LadderServer(budget, n_streams, precision, max_batch)
+        return LadderServer(budget, n_streams, precision, max_batch, **server_kw)
 
     server().serve(make_stream(pool, max(warmup, 2 * len(pool)), 0, seed + 1))
     sat = latency_stats(server().serve(make_stream(pool, n_requests, 0.0, seed)))

@@ -56,6 +56,31 @@ def test_results_identical_alone_and_in_the_mix(gpu_lib, precision):
         assert np.array_equal(r.pair_energy.cpu().numpy(), Ea), r.rid
 
 
+def test_large_requests_run_alone(gpu_lib):
+    """Under the default policy a request of at least ``solo_flops`` is a
+    batch of its own, the small requests are still batched together, and
+    every result equals its standalone one bitwise."""
+    import torch
+    from paper_2512_21909_amd import serve
+    pool = _pool(gpu_lib, S.batch_syms(4, seed=3) + [S.sym_custom([10, 8], [90, 80], [700, 600])])
+    reqs = [serve.Request(rid=k, arrival=0.0, layout=pool[k % 5]["layout"], B=pool[k % 5]["B"],
+                          X=pool[k % 5]["X"], flops=pool[k % 5]["flops"], want_energy=True) for k in range(20)]
+    solo = sorted({r.flops for r in reqs})[-1]
+    assert solo > 4 * sorted({r.flops for r in reqs})[-2]
+    srv = serve.LadderServer(int(torch.cuda.mem_get_info()[0] * 0.5), n_streams=3, max_batch=8, solo_flops=solo)
+    done = srv.serve(reqs)
+    assert sorted(r.rid for r in done) == list(range(20)) and all(r.status == "done" for r in done)
+    batches = [[r for r in done if r.t_launch == t] for t in {r.t_launch for r in done}]
+    for b in batches:
+        if any(r.flops >= solo for r in b):
+            assert len(b) == 1
+    assert max(len(b) for b in batches) > 1
+    for r in done:
+        Ra, Ea = _alone(gpu_lib, r, "fp64")
+        assert np.array_equal(r.R.cpu().numpy(), Ra), r.rid
+        assert np.array_equal(r.pair_energy.cpu().numpy(), Ea), r.rid
+
+
 def test_admission_rejects_oversize_and_serves_the_rest(gpu_lib):
     from paper_2512_21909_amd import serve
     pool = _pool(gpu_lib, [S.sym_custom([2, 1], [6, 5], [20, 9]), S.sym_c1_small()])
@@ -116,17 +141,18 @@ _MIX_REF = {}
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_mix_with_the_large_request_matches_alone_and_oracle(gpu_lib, precision):
     """The serving mix with the large request (o=30, v=300, 2500 vectors, 8
-    irreps, drawn with probability 0.3 here so that it lands in batches with
-    small ones): every request completes, equals its standalone result
-    bitwise, and every distinct shape matches the oracle (R normwise, pair
-    energies) within the path's tolerance."""
+    irreps, drawn with probability 0.3 here and batched like the small ones,
+    so that it lands in batches with them): every request completes, equals
+    its standalone result bitwise, and every distinct shape matches the
+    oracle (R normwise, pair energies) within the path's tolerance."""
     import torch
     import oracle as O
     from paper_2512_21909_amd import serve
     pool = _pool(gpu_lib, S.batch_syms(5, seed=11) + [S.sym_serving_large()], seed=40, large=True, keep=True)
     reqs = serve.make_stream(pool, 30, 0.0, seed=3, p_large=0.3)
     assert 3 <= sum(r.layout is pool[-1]["layout"] for r in reqs) < 30
-    srv = serve.LadderServer(int(torch.cuda.mem_get_info()[0] * 0.5), n_streams=3, precision=precision, max_batch=6)
+    srv = serve.LadderServer(int(torch.cuda.mem_get_info()[0] * 0.5), n_streams=3, precision=precision, max_batch=6,
+                             solo_flops=None)
     done = srv.serve(reqs)
     assert sorted(r.rid for r in done) == list(range(30)) and all(r.status == "done" for r in done)
     tol = 1e-12 if precision == "fp64" else 1e-7
