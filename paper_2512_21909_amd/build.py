@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libcdcc.so")
 BUILD = os.path.join(PKG, "_build")
 
-HIP_SOURCES = ["kernels_f64.hip", "kernels_mixed.hip", "kernels_bf16.hip", "kernels_density.hip",
+HIP_SOURCES = ["kernels_f64.hip", "kernels_mixed.hip", "kernels_split128.hip", "kernels_density.hip",
                "kernels_partial.hip", "kernels_cd.hip", "noalloc.hip"]
 CXX_SOURCES = ["layout.cpp", "cdcc.cpp"]
 

@@ -554,10 +554,10 @@ hipError_t launch_slice(int fmt, const SliceJob *jobs, const int2 *rows, int nro
   return hipGetLastError();
 }
 
-// the 128 x 128 split-BF16 class (kernels_bf16.hip)
-hipError_t launch_assemble_bf16(int neg, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
-                                const SysPtrs *sp, double *xbuf, hipStream_t s);
-int occupancy_bf16();
+// the four-wave 128 x 128 class of both split formats (kernels_split128.hip)
+hipError_t launch_assemble_split128(int fmt, int neg, int grid, const P1Desc *descs, const Tile *tiles,
+                                    const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s);
+int occupancy_split128(int fmt);
 
 template <bool I8, bool LONGK, bool NEG>
 static void launch_assemble_fmt(int cls, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
@@ -576,6 +576,10 @@ hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int neg, int grid,
                                  const Tile *tiles, const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf,
                                  hipStream_t s) {
   if (grid <= 0) return hipSuccess;
+  // the four-wave 128 x 128 kernel, except for 8-bit launches with K
+  // segments or a T1-dressed Lambda stack
+  if (cls == 2 && (fmt == 0 || (!longk && !neg)))
+    return launch_assemble_split128(fmt, neg, grid, descs, tiles, Q, cnt, sp, xbuf, s);
   if (fmt == 1) {
     if (longk && neg)
       launch_assemble_fmt<true, true, true>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
@@ -585,8 +589,6 @@ hipError_t launch_assemble_mixed(int fmt, int cls, int longk, int neg, int grid,
       launch_assemble_fmt<true, false, true>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
     else
       launch_assemble_fmt<true, false, false>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
-  } else if (cls == 2) {
-    return launch_assemble_bf16(neg, grid, descs, tiles, Q, cnt, sp, xbuf, s);
   } else if (neg) {
     launch_assemble_fmt<false, false, true>(cls, grid, descs, tiles, Q, cnt, sp, xbuf, s);
   } else {
@@ -611,7 +613,7 @@ static int occupancy_fmt(int cls) {
 }
 
 int occupancy_mixed(int fmt, int cls) {
-  if (fmt == 0 && cls == 2) return occupancy_bf16();
+  if (cls == 2) return occupancy_split128(fmt);
   return fmt == 1 ? occupancy_fmt<true>(cls) : occupancy_fmt<false>(cls);
 }
 

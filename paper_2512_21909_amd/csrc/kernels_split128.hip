@@ -1,22 +1,25 @@
-// Split-BF16 (ac|bd) batch assembly for gfx950, 128 x 128 tiles on four waves.
+// Split-precision (ac|bd) batch assembly for gfx950, 128 x 128 tiles on four
+// waves, for both split formats: BF16 slices and 8-bit digits.
 //
-// Slices, slice products, accumulators and flush points are those of the
-// split-BF16 scheme of kernels_mixed.hip: per output element the same MFMA
-// products reach each FP32 accumulator in the same order and the FP64 total
-// is formed the same way, so the results are bitwise the same as with that
-// file's kernels.  What differs is the schedule:
+// Slices or digits, their products, accumulators and (BF16) flush points are
+// those of the schemes of kernels_mixed.hip: per output element the same
+// MFMA products reach each accumulator (BF16: in the same order) and the
+// FP64 value is formed the same way, so the results are bitwise the same as
+// with that file's kernels.  What differs is the schedule:
 //  * each wave owns a 64 x 64 block of the tile (2 x 2 MFMA blocks of 32 x 32):
-//    16 fragment reads feed 44 MFMAs per K block of 16; with one wave per SIMD
-//    a wave has 512 registers, enough for the twelve FP32 accumulators, the
-//    FP64 totals and the fragments (read straight into the AGPRs);
+//    16 fragment reads feed 44 BF16 MFMAs per K block of 16, or 52 int8 MFMAs
+//    per K block of 32; with one wave per SIMD a wave has 512 registers,
+//    enough for the twelve FP32 accumulators and the FP64 totals (BF16) or
+//    the twenty int32 accumulators (8-bit), and the fragments;
 //  * the fragments of K block k + 1 are read while the MFMAs of block k run,
 //    each as soon as the registers it replaces are no longer needed, so no
 //    MFMA waits for LDS;
 //  * operand rows come from global memory straight into LDS through a ring
 //    of four stages, three K blocks ahead, with one barrier per K block;
-//  * the subtracted half of the Lambda stack negates the accumulators and the
-//    running total once, at its first K block (exact), instead of the B
-//    fragments of every block;
+//  * the subtracted half of the (BF16) Lambda stack negates the accumulators
+//    and the running total once, at its first K block (exact), instead of the
+//    B fragments of every block; 8-bit Lambda stacks use the eight-wave
+//    kernel of kernels_mixed.hip;
 //  * the next tile's first copies are issued before this tile's epilogue, and
 //    the epilogue takes each element's X offset and scale from row and column
 //    tables that were written to LDS when the tile was set up;
@@ -26,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <type_traits>
 
 #include "kernel_common.hpp"
 
@@ -34,6 +38,8 @@ namespace cdcc {
 namespace {
 
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+typedef int i4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -68,17 +74,24 @@ __device__ __forceinline__ unsigned lds_addr(const unsigned char *p) {
 
 // MFMA f32 32x32x16 bf16 lane mapping (gfx950): A[i][k] in lane i + 32(k/8),
 // element k%8; B[k][j] in lane j + 32(k/8); result register r of lane l is
-// D[8(r/4) + 4(l/32) + r%4][l%32].
+// D[8(r/4) + 4(l/32) + r%4][l%32].  The int8 32x32x32 MFMA maps A[i][k] to
+// lane i + 32(k/16), byte k%16, and its result like the BF16 one, so a lane
+// reads the same 16 bytes of a row chunk in both formats.
 //
-// LDS row layout (as in kernels_mixed.hip): one K block of all four slices of
-// an operand row, eight 16-byte chunks; physical chunk c of row r holds
-// logical chunk c ^ ((r / 2) % 8), slice s being logical chunks 2s and 2s + 1.
-// NEG: the launch assembles a T1-dressed Lambda stack (with a subtracted half).
-template <bool NEG>
-__global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__restrict__ descs,
-                                                            const Tile *__restrict__ tiles, Queues Q,
-                                                            int *__restrict__ cnt, const SysPtrs *__restrict__ sp,
-                                                            double *__restrict__ xbuf) {
+// LDS row layout (as in kernels_mixed.hip): one K block of all four slices or
+// digits of an operand row, eight 16-byte chunks; physical chunk c of row r
+// holds logical chunk c ^ ((r / 2) % 8), slice or digit s being logical
+// chunks 2s and 2s + 1.  I8: 8-bit digits (K blocks of 32); NEG: the launch
+// assembles a T1-dressed Lambda stack (with a subtracted half), BF16 only.
+template <bool I8, bool NEG>
+__global__ __launch_bounds__(256) void assemble_split128_kernel(const P1Desc *__restrict__ descs,
+                                                                const Tile *__restrict__ tiles, Queues Q,
+                                                                int *__restrict__ cnt,
+                                                                const SysPtrs *__restrict__ sp,
+                                                                double *__restrict__ xbuf) {
+  static_assert(!(I8 && NEG), "8-bit T1-dressed Lambda stacks use the eight-wave kernel");
+  constexpr int kKB = I8 ? 32 : 16;  // K per block (one 128-byte row chunk)
+  using Frag = typename std::conditional<I8, i4v, bf8>::type;
   __shared__ __attribute__((aligned(16))) unsigned char st0[kStage];
   __shared__ __attribute__((aligned(16))) unsigned char st1[kStage];
   __shared__ __attribute__((aligned(16))) unsigned char st2[kStage];
@@ -128,9 +141,9 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
     const P1Desc D = descs[tl.desc];
     const SysPtrs S = sp[D.sys];
     const int m0 = tl.tm * kBM, n0 = tl.tn * kBN;
-    nkb = D.Kp / 16;
+    nkb = D.Kp / kKB;
     kneg = D.kneg_blk;
-    const int64_t rowstride = int64_t(D.Kp) * 8;  // bytes per sliced row
+    const int64_t rowstride = int64_t(D.Kp) * (I8 ? 4 : 8);  // bytes per sliced row
 #pragma unroll
     for (int i = 0; i < kNI; ++i) {
       const int r = (i * kWaves + wave) * 8 + (lane >> 3);
@@ -183,48 +196,77 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
   }
 
   while (t >= 0) {
-    // acc0: s0 s0; acc1: s0 s1 and s1 s0; acc2: the eight products of weights
-    // two to four (t + u = 2, 3, and s2 s2); blocks [i][j] of the wave
+    // BF16: acc0: s0 s0; acc1: s0 s1 and s1 s0; acc2: the eight products of
+    // weights two to four (t + u = 2, 3, and s2 s2); blocks [i][j] of the
+    // wave.  8-bit digits: iacc[w] holds the exact int32 sum of the products
+    // of weight t + u = w.
     f16v acc0[2][2], acc1[2][2], acc2[2][2];
     double tot[2][2][16];
+    i16v iacc[5][2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        acc0[i][j] = f16v{};
-        acc1[i][j] = f16v{};
-        acc2[i][j] = f16v{};
+        if constexpr (I8) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) tot[i][j][r] = 0.0;
+          for (int w = 0; w < 5; ++w) iacc[w][i][j] = i16v{};
+        } else {
+          acc0[i][j] = f16v{};
+          acc1[i][j] = f16v{};
+          acc2[i][j] = f16v{};
+#pragma unroll
+          for (int r = 0; r < 16; ++r) tot[i][j][r] = 0.0;
+        }
       }
-    bf8 fa[2][4], fb[2][4];
+    Frag fa[2][4], fb[2][4];
     auto read_a = [&](const unsigned char *L, int i) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        fa[i][s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + abase + i * 32 * kRowB + coff[s]));
+        fa[i][s] = __builtin_bit_cast(Frag, *reinterpret_cast<const u32x4 *>(L + abase + i * 32 * kRowB + coff[s]));
     };
     auto read_b = [&](const unsigned char *L, int j) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        fb[j][s] = __builtin_bit_cast(bf8, *reinterpret_cast<const u32x4 *>(L + bbase + j * 32 * kRowB + coff[s]));
+        fb[j][s] = __builtin_bit_cast(Frag, *reinterpret_cast<const u32x4 *>(L + bbase + j * 32 * kRowB + coff[s]));
     };
-    // the eleven products of block (i, j); per accumulator the order is
-    // acc0: a0b0; acc1: a0b1, a1b0; acc2: a0b2, a1b1, a2b0, a0b3, a1b2, a2b1,
-    // a3b0, a2b2 (consecutive MFMAs on one accumulator need no wait states)
+    // the products of block (i, j).  BF16, eleven; per accumulator the order
+    // is acc0: a0b0; acc1: a0b1, a1b0; acc2: a0b2, a1b1, a2b0, a0b3, a1b2,
+    // a2b1, a3b0, a2b2 (consecutive MFMAs on one accumulator need no wait
+    // states).  8-bit digits, the thirteen with t + u <= 4 (integer sums:
+    // their order does not matter).
     auto sub = [&](int i, int j) {
+      if constexpr (I8) {
+#define CDCC_Q(t, u) \
+  iacc[t + u][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[i][t], fb[j][u], iacc[t + u][i][j], 0, 0, 0)
+        CDCC_Q(0, 0);
+        CDCC_Q(0, 1);
+        CDCC_Q(0, 2);
+        CDCC_Q(0, 3);
+        CDCC_Q(1, 3);
+        CDCC_Q(1, 0);
+        CDCC_Q(1, 1);
+        CDCC_Q(1, 2);
+        CDCC_Q(2, 2);
+        CDCC_Q(2, 0);
+        CDCC_Q(2, 1);
+        CDCC_Q(3, 1);
+        CDCC_Q(3, 0);
+#undef CDCC_Q
+      } else {
 #define CDCC_P(acc, s, u) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][s], fb[j][u], acc[i][j], 0, 0, 0)
-      CDCC_P(acc0, 0, 0);
-      CDCC_P(acc1, 0, 1);
-      CDCC_P(acc2, 0, 2);
-      CDCC_P(acc1, 1, 0);
-      CDCC_P(acc2, 1, 1);
-      CDCC_P(acc2, 2, 0);
-      CDCC_P(acc2, 0, 3);
-      CDCC_P(acc2, 1, 2);
-      CDCC_P(acc2, 2, 1);
-      CDCC_P(acc2, 3, 0);
-      CDCC_P(acc2, 2, 2);
+        CDCC_P(acc0, 0, 0);
+        CDCC_P(acc1, 0, 1);
+        CDCC_P(acc2, 0, 2);
+        CDCC_P(acc1, 1, 0);
+        CDCC_P(acc2, 1, 1);
+        CDCC_P(acc2, 2, 0);
+        CDCC_P(acc2, 0, 3);
+        CDCC_P(acc2, 1, 2);
+        CDCC_P(acc2, 2, 1);
+        CDCC_P(acc2, 3, 0);
+        CDCC_P(acc2, 2, 2);
 #undef CDCC_P
+      }
     };
     // one block at a time, so that few converted values are live at once
     auto flush = [&]() {
@@ -318,9 +360,31 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
           read_a(nx, 1);
           read_b(nx, 1);
           __builtin_amdgcn_sched_barrier(0);
-          if ((k & 15) == 15 || k == nkb - 1) flush();  // every 256 K: keeps acc0 and acc1 exact
+          if constexpr (!I8) {
+            if ((k & 15) == 15 || k == nkb - 1) flush();  // every 256 K: keeps acc0 and acc1 exact
+          }
         }
       }
+    }
+
+    if constexpr (I8) {
+      // the digit sums in FP64, one block at a time (one rounding per
+      // element: every term but the last sum is exact); here, before the
+      // next tile is set up, so that its copy addresses are not live beside
+      // the twenty accumulators
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            tot[i][j][r] = (((double(iacc[4][i][j][r]) * 0x1p-32 + double(iacc[3][i][j][r]) * 0x1p-24) +
+                             double(iacc[2][i][j][r]) * 0x1p-16) +
+                            double(iacc[1][i][j][r]) * 0x1p-8) +
+                           double(iacc[0][i][j][r]);
+        }
+      __builtin_amdgcn_sched_barrier(0);
     }
 
     // every wave is done with the stages (the barrier of the claim), then
@@ -330,7 +394,8 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
     if (tn >= 0) prepare(tn);
     __asm__ volatile("" ::: "memory");  // the epilogue stays after the next tile's copies
 
-    const double unit = kneg_c < nkb_c ? -0.5 : 0.5;  // negated total of a Lambda stack
+    // negated total of a Lambda stack; digit products are in units of 2^-14
+    const double unit = (kneg_c < nkb_c ? -0.5 : 0.5) * (I8 ? 1.0 / 16384.0 : 1.0);
     EpiEntry ce[2];
     int ck[2];
 #pragma unroll
@@ -359,19 +424,29 @@ __global__ __launch_bounds__(256) void assemble_bf16_kernel(const P1Desc *__rest
   }
 }
 
-hipError_t launch_assemble_bf16(int neg, int grid, const P1Desc *descs, const Tile *tiles, const Queues &Q, int *cnt,
-                                const SysPtrs *sp, double *xbuf, hipStream_t s) {
+// fmt: 0 split-BF16, 1 8-bit digits (every tile of the launch has K <= 32736,
+// so its int32 sums stay exact); neg: a T1-dressed Lambda stack, split-BF16
+// only (the 8-bit form negates twenty int32 accumulators in its K loop, and
+// with them the compiler runs out of registers and spills)
+hipError_t launch_assemble_split128(int fmt, int neg, int grid, const P1Desc *descs, const Tile *tiles,
+                                    const Queues &Q, int *cnt, const SysPtrs *sp, double *xbuf, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (neg)
-    assemble_bf16_kernel<true><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf);
+  if (fmt == 1 && neg) return hipErrorInvalidValue;
+  if (fmt == 1)
+    assemble_split128_kernel<true, false><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf);
+  else if (neg)
+    assemble_split128_kernel<false, true><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf);
   else
-    assemble_bf16_kernel<false><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf);
+    assemble_split128_kernel<false, false><<<grid, 256, 0, s>>>(descs, tiles, Q, cnt, sp, xbuf);
   return hipGetLastError();
 }
 
-int occupancy_bf16() {
+int occupancy_split128(int fmt) {
   int n = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, assemble_bf16_kernel<false>, 256, 0);
+  const hipError_t e = fmt == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                      &n, assemble_split128_kernel<true, false>, 256, 0)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                      &n, assemble_split128_kernel<false, false>, 256, 0);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
