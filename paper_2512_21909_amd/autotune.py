@@ -32,7 +32,7 @@ from . import _lib
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tile_table.txt")
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tile_cache.json")
 HEADER = ("# key -> assembly tile class[:contraction K segment] (fp64: 0=64x64 1=128x64 2=128x128; mixed, "
-          "mixed_i8: 0=64x128 1=128x64 2=128x128 (mixed: 4 waves of 64x64, mixed_i8: 8 waves) 3=64x64); keys: "
+          "mixed_i8: 0=64x128 1=128x64 2=128x128 (4 waves of 64x64; 8-bit Lambda stacks: 8 waves) 3=64x64); keys: "
           "'<precision> <kind> h nocc[h] nvir[h] ncd[h]' (exact shape) or '<precision> <kind> b<h> <T> <K> <M>' "
           "(size class)")
 NCLASS = {"fp64": 3, "mixed": 4, "mixed_i8": 4}
