@@ -57,12 +57,12 @@ PAIR_GATE = 1e-8   # Eh, split paths (FP64: 1e-12 relative to max |e_ij|)
 # call is one batch).  The vvvv density
 # and partial-contraction entries are the launch of their GEMM kernel,
 # counted the same way.
-TRAFFIC = {("d2h_medium", "mixed", "assemble"): 3.197e9, ("d2h_medium", "fp64", "assemble"): 2.266e9,
-           ("d2h_medium", "mixed_i8", "assemble"): 1.392e9,
-           ("d2h_large", "fp64", "assemble"): 45.980e9, ("d2h_large", "mixed", "assemble"): 41.673e9,
-           ("d2h_large", "mixed_i8", "assemble"): 26.958e9,
-           ("d2h_large", "fp64", "contract"): 35.871e9, ("d2h_large", "mixed", "contract"): 35.871e9,
-           ("d2h_large", "mixed_i8", "contract"): 35.871e9,
+TRAFFIC = {("d2h_medium", "mixed", "assemble"): 2.641e9, ("d2h_medium", "fp64", "assemble"): 2.276e9,
+           ("d2h_medium", "mixed_i8", "assemble"): 1.396e9,
+           ("d2h_large", "fp64", "assemble"): 45.957e9, ("d2h_large", "mixed", "assemble"): 42.393e9,
+           ("d2h_large", "mixed_i8", "assemble"): 25.243e9,
+           ("d2h_large", "fp64", "contract"): 36.554e9, ("d2h_large", "mixed", "contract"): 36.554e9,
+           ("d2h_large", "mixed_i8", "contract"): 36.554e9,
            ("vvvv_d2h_medium", "fp64", "gemm"): 3.800e9,
            ("pm_d2h_medium", "fp64", "gemm"): 0.277e9, ("pm_d2h_large", "fp64", "gemm"): 7.494e9}
 # A single system is checked on every element when the plain oracle costs at
