@@ -54,15 +54,15 @@ PAIR_GATE = 1e-8   # Eh, split paths (FP64: 1e-12 relative to max |e_ij|)
 # as committed (profiles/).  A "launch" is what the library times as one: an
 # assembly launch (the T2 and the Lambda launch of a step averaged), or one
 # batch's contraction with its split-K reduction and unpack (at o=40/v=400 a
-# call is one batch).  The vvvv density
+# call is one batch and its contraction one K segment, with no reduction).  The vvvv density
 # and partial-contraction entries are the launch of their GEMM kernel,
 # counted the same way.
 TRAFFIC = {("d2h_medium", "mixed", "assemble"): 2.641e9, ("d2h_medium", "fp64", "assemble"): 2.276e9,
            ("d2h_medium", "mixed_i8", "assemble"): 1.396e9,
            ("d2h_large", "fp64", "assemble"): 45.957e9, ("d2h_large", "mixed", "assemble"): 42.393e9,
            ("d2h_large", "mixed_i8", "assemble"): 25.243e9,
-           ("d2h_large", "fp64", "contract"): 36.554e9, ("d2h_large", "mixed", "contract"): 36.554e9,
-           ("d2h_large", "mixed_i8", "contract"): 36.554e9,
+           ("d2h_large", "fp64", "contract"): 31.999e9, ("d2h_large", "mixed", "contract"): 31.999e9,
+           ("d2h_large", "mixed_i8", "contract"): 31.999e9,
            ("vvvv_d2h_medium", "fp64", "gemm"): 3.800e9,
            ("pm_d2h_medium", "fp64", "gemm"): 0.277e9, ("pm_d2h_large", "fp64", "gemm"): 7.494e9}
 # A single system is checked on every element when the plain oracle costs at
