@@ -520,7 +520,26 @@ def ladder_main(args, cdcc):
                 f"p99 {s['stream'].get('p99_ms', 0):.2f} ms")
     if "cpu_baseline" in m:
         line["cpu_baseline"] = m["cpu_baseline"]
+    line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line, default=str), flush=True)
+
+
+# The paper's own timings with their hardware (Section "Analysis of timings"),
+# context only: whole CD-CCSD geometry optimisations, not ladder evaluations,
+# so no ratio against them is formed (vs_baseline stays null).
+PAPER_CONTEXT = {
+    "hexabenzocoronene_cc-pVDZ": {
+        "size": "o=135, v=543, about 3710 Cholesky vectors, D2h",
+        "time": "about 4 d 15 h for 24 geometry-optimisation steps (about 4.6 h per gradient step)",
+        "hardware": "AMD EPYC 7282 16-core node, 32 OpenMP threads",
+    },
+    "coronene_cc-pVTZ": {
+        "size": "o=78, v=810, about 4420 Cholesky vectors, D2h",
+        "time": "about 2 d for 8 geometry-optimisation steps",
+        "hardware": "Intel Xeon Gold 6140M node, 32 OpenMP threads",
+    },
+    "note": "a gradient step holds every T2 and Lambda iteration, the densities and the derivative contractions",
+}
 
 
 def serving_sweep_main(args, cdcc):
