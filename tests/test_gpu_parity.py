@@ -202,6 +202,37 @@ def test_t2_d2h_large_one_batch_equals_four(gpu_lib, precision):
     assert np.array_equal(out[0][1], out[1][1])
 
 
+def _workspace_bytes(sym, precision, batch_bytes=0):
+    """Device bytes of a T2 call on this system.  The size query reads the
+    layout and the options only, so the data pointers are placeholders."""
+    import ctypes
+    from paper_2512_21909_amd import Layout, _lib
+    lay = Layout(sym)
+    P = _lib.Problem()
+    P.lay = ctypes.pointer(lay.c)
+    P.B = P.X = P.R = ctypes.c_void_p(1 << 12)
+    o = _lib.Opts()
+    o.precision = {"fp64": _lib.FP64, "mixed": _lib.MIXED, "mixed_i8": _lib.MIXED_I8}[precision]
+    o.batch_bytes = batch_bytes
+    out = ctypes.c_int64(0)
+    _lib.check(_lib.load().cdcc_workspace_bytes(1, ctypes.byref(P), ctypes.byref(o), 0, ctypes.byref(out)),
+               "cdcc_workspace_bytes")
+    return out.value
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
+def test_default_batch_rule(gpu_lib, precision):
+    """Default batch cap: one batch when the whole (ac|bd) intermediate fits
+    16 GiB (o=40/v=400: about 14 GB, so the workspace exceeds that of a 4 GiB
+    cap by most of it), else batches of at most 4 GiB (o=135/v=543: the
+    default plan takes exactly the workspace of an explicit 4 GiB cap)."""
+    big = _workspace_bytes(S.sym_d2h_large(), precision)
+    capped = _workspace_bytes(S.sym_d2h_large(), precision, 4 << 30)
+    assert big - capped > 8e9 and big < capped + (16 << 30)
+    hbc = S.sym_hbc_shape()
+    assert _workspace_bytes(hbc, precision) == _workspace_bytes(hbc, precision, 4 << 30)
+
+
 # ---------------------------------------------------------------- mixed path
 MIXED_TOL = 1e-7      # normwise relative
 PAIR_TOL = 1e-8       # Eh, absolute
