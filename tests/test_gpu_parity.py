@@ -186,6 +186,42 @@ def test_t2_d2h_large_full(gpu_lib, precision):
         assert err_e <= 1e-8
 
 
+_LARGE_LAMBDA = {}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_i8"])
+def test_lambda_d2h_large_full(gpu_lib, precision):
+    """The T1-dressed Lambda ladder at o=40, v=400, 3000 vectors (8 irreps;
+    a stack of 750 per irrep with its subtracted half), every element
+    against the oracle (computed once per session, about half a minute of
+    host BLAS): Z and Z/D normwise (1e-12 FP64, 1e-7 split paths), pair
+    energies (1e-12 relative FP64, 1e-8 Eh split paths), Z_ij^ab = Z_ji^ba
+    bitwise."""
+    if not _LARGE_LAMBDA:
+        prob = problem(S.sym_d2h_large(), seed=0, kind="lambda")
+        sym = prob["sym"]
+        ref = oracle_result(prob)
+        _LARGE_LAMBDA.update(prob=prob, ref=ref, e=O.pair_energies_blocks(sym, prob["X"], ref),
+                             delta=O.denominator_update_blocks(sym, ref, prob["eps_occ"], prob["eps_vir"]))
+    L = _LARGE_LAMBDA
+    prob, ref = L["prob"], L["ref"]
+    d = device_problem(gpu_lib, prob, want_delta=True, want_energy=True)
+    run(gpu_lib, d, kind="lambda", precision=precision)
+    tol = FP64_TOL if precision == "fp64" else 1e-7
+    got = blocks(d)
+    mx, fro = _check(got, ref, tol, f"Z {precision}")
+    _check(blocks(d, "delta"), L["delta"], tol, f"Z/D {precision}")
+    assert _pair_symmetric_blocks(prob["sym"], got)
+    e_got = d["pair_energy"].cpu().numpy().reshape(L["e"].shape)
+    err_e = float(np.max(np.abs(e_got - L["e"])))
+    print(f"d2h_large lambda {precision}: max {mx:.2e} fro {fro:.2e} pair-energy {err_e:.2e} Eh "
+          f"(max |e_ij| {np.max(np.abs(L['e'])):.3f})")
+    if precision == "fp64":
+        assert err_e <= 1e-12 * max(1.0, float(np.max(np.abs(L["e"]))))
+    else:
+        assert err_e <= 1e-8
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_t2_d2h_large_one_batch_equals_four(gpu_lib, precision):
     """The o=40/v=400 intermediate (about 14 GB) runs as one batch under the
