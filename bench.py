@@ -61,8 +61,8 @@ TRAFFIC = {("d2h_medium", "mixed", "assemble"): 2.641e9, ("d2h_medium", "fp64", 
            ("d2h_medium", "mixed_i8", "assemble"): 1.396e9,
            ("d2h_large", "fp64", "assemble"): 45.957e9, ("d2h_large", "mixed", "assemble"): 42.393e9,
            ("d2h_large", "mixed_i8", "assemble"): 25.243e9,
-           ("d2h_large", "fp64", "contract"): 31.999e9, ("d2h_large", "mixed", "contract"): 31.999e9,
-           ("d2h_large", "mixed_i8", "contract"): 31.999e9,
+           ("d2h_large", "fp64", "contract"): 28.984e9, ("d2h_large", "mixed", "contract"): 28.984e9,
+           ("d2h_large", "mixed_i8", "contract"): 28.984e9,
            ("vvvv_d2h_medium", "fp64", "gemm"): 3.800e9,
            ("pm_d2h_medium", "fp64", "gemm"): 0.277e9, ("pm_d2h_large", "fp64", "gemm"): 7.494e9}
 # A single system is checked on every element when the plain oracle costs at

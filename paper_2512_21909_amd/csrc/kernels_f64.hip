@@ -454,6 +454,10 @@ __device__ __forceinline__ void contract_tile(const P2Group &g, const Tile &tl, 
     // when they are used, so no instruction waits on these loads until then
     // (steps past the end load but count as absent)
     auto dload = [&](int q, int s) {
+      // widest tile: an empty asm takes this stage's table entry here, so the
+      // optimiser cannot start the next stage's address arithmetic early and
+      // wait there for the youngest load in flight (every load of the ring)
+      if constexpr (FM == 4) __asm__ volatile("" : "+v"(kc[q]), "+v"(r1[q]), "+v"(r2[q]));
       const bool in = s < ns;
       fl[q] = ((in && kc[q] >= 0) ? 1 : 0) | ((in && r1[q] >= 0) ? 2 : 0) | ((in && r2[q] >= 0) ? 4 : 0);
       const int64_t ko = int64_t(kc[q] >= 0 ? kc[q] : 0) * g.th_rs;
